@@ -1,0 +1,172 @@
+"""Seeded synthetic inputs shared by the oracle, the tests and the benchmark.
+
+This module only draws random numbers and lays out model parameters.  It
+holds none of the method's arithmetic: no Pauli algebra, no Jordan-Wigner
+mapping, no sector indexing and no operator application.  Both the oracle
+and the GPU path read their inputs from here, so a parity test compares two
+independent computations on identical bytes.
+
+Conventions (spin-orbital layout used by the molecular Hamiltonian of
+Eq. second_quantized_hamiltonian in the paper's Section 2.1):
+
+* spatial orbital p with spin alpha is spin-orbital p, with spin beta it is
+  spin-orbital n_orb + p ("blocked" order, so that the alpha string is the
+  low half of a basis index and the beta string the high half, matching the
+  spin-resolved product basis of Section 2.4);
+* spatial two-electron integrals are in chemists' notation g[p,q,r,s] =
+  (pq|rs) with the 8-fold permutational symmetry of real orbitals;
+* the spin-orbital tensor h2[P,Q,R,S] is the coefficient of
+  1/2 a+_P a+_Q a_R a_S, i.e. (p_P p_S | p_Q p_R) when spin(P) = spin(S)
+  and spin(Q) = spin(R), and 0 otherwise.
+"""
+
+import numpy as np
+
+__all__ = [
+    "molecular_integrals",
+    "spin_orbital_integrals",
+    "molecular_spin_integrals",
+    "hubbard_spatial_integrals",
+    "hubbard_spin_integrals",
+    "tfim_terms",
+    "random_state",
+    "random_pauli_strings",
+    "neel_occupations",
+]
+
+
+def molecular_integrals(n_orb, seed, h_scale=1.0, g_scale=0.1):
+    """Random real spatial integrals (h, g).
+
+    h: symmetric, h[p,q] = h[q,p] ~ N(0, h_scale^2) drawn for p <= q.
+    g: one N(0, g_scale^2) draw per 8-fold orbit, copied to all 8 index
+       permutations (pq|rs) = (qp|rs) = (pq|sr) = (rs|pq) = ...
+    """
+    rng = np.random.default_rng(seed)
+    a = rng.standard_normal((n_orb, n_orb)) * h_scale
+    h = np.triu(a) + np.triu(a, 1).T
+    raw = rng.standard_normal((n_orb,) * 4) * g_scale
+    p, q, r, s = np.indices((n_orb,) * 4)
+    # canonical representative of each orbit: ordered pairs, then ordered pair-of-pairs
+    pq_hi, pq_lo = np.maximum(p, q), np.minimum(p, q)
+    rs_hi, rs_lo = np.maximum(r, s), np.minimum(r, s)
+    pq = pq_hi * n_orb + pq_lo
+    rs = rs_hi * n_orb + rs_lo
+    first_is_big = pq >= rs
+    a_hi = np.where(first_is_big, pq_hi, rs_hi)
+    a_lo = np.where(first_is_big, pq_lo, rs_lo)
+    b_hi = np.where(first_is_big, rs_hi, pq_hi)
+    b_lo = np.where(first_is_big, rs_lo, pq_lo)
+    g = raw[a_hi, a_lo, b_hi, b_lo]
+    return h, g
+
+
+def spin_orbital_integrals(h, g):
+    """Spatial (h, g) -> spin-orbital (h1, h2) in the blocked layout."""
+    n = h.shape[0]
+    ns = 2 * n
+    sp = np.arange(ns) % n          # spatial index of each spin-orbital
+    spin = np.arange(ns) // n       # 0 = alpha, 1 = beta
+    h1 = h[sp[:, None], sp[None, :]] * (spin[:, None] == spin[None, :])
+    P, Q, R, S = np.indices((ns,) * 4)
+    allowed = (spin[P] == spin[S]) & (spin[Q] == spin[R])
+    h2 = np.where(allowed, g[sp[P], sp[S], sp[Q], sp[R]], 0.0)
+    return np.ascontiguousarray(h1, dtype=np.float64), np.ascontiguousarray(h2, dtype=np.float64)
+
+
+def molecular_spin_integrals(n_orb, seed):
+    """Spin-orbital integrals of the synthetic molecular Hamiltonian."""
+    h, g = molecular_integrals(n_orb, seed)
+    return spin_orbital_integrals(h, g)
+
+
+def _lattice_bonds(rows, cols, periodic):
+    bonds = set()
+    for r in range(rows):
+        for c in range(cols):
+            i = r * cols + c
+            for dr, dc in ((0, 1), (1, 0)):
+                rr, cc = r + dr, c + dc
+                if periodic:
+                    rr %= rows
+                    cc %= cols
+                elif rr >= rows or cc >= cols:
+                    continue
+                j = rr * cols + cc
+                if i != j:
+                    bonds.add((min(i, j), max(i, j)))
+    return sorted(bonds)
+
+
+def hubbard_spatial_integrals(rows, cols, t=1.0, u=4.0, periodic=True):
+    """Fermi-Hubbard model as spatial integrals (sites row-major).
+
+    H = -t sum_<ij>,sigma (a+_i a_j + h.c.) + U sum_i n_i,up n_i,down, so
+    h[i,j] = -t on each bond (a bond counted once even if periodic wrapping
+    reaches the same neighbour twice) and (ii|ii) = U.
+    """
+    n = rows * cols
+    h = np.zeros((n, n))
+    for i, j in _lattice_bonds(rows, cols, periodic):
+        h[i, j] = h[j, i] = -t
+    g = np.zeros((n,) * 4)
+    for i in range(n):
+        g[i, i, i, i] = u
+    return h, g
+
+
+def hubbard_spin_integrals(rows, cols, t=1.0, u=4.0, periodic=True):
+    h, g = hubbard_spatial_integrals(rows, cols, t, u, periodic)
+    h1, h2 = spin_orbital_integrals(h, g)
+    # With only on-site (ii|ii) integrals the same-spin entries h2[P,P,P,P]
+    # multiply a+_P a+_P = 0; they are harmless but kept for fidelity.
+    return h1, h2
+
+
+def tfim_terms(n_sites, j=0.25, h=1.0):
+    """Open-chain transverse-field Ising model J sum Z_i Z_i+1 + h sum X_i.
+
+    Returned as letter strings (one char per qubit, qubit 0 first) with real
+    coefficients; this is input data, not algebra.
+    """
+    terms = []
+    for i in range(n_sites - 1):
+        s = ["I"] * n_sites
+        s[i] = s[i + 1] = "Z"
+        terms.append(("".join(s), complex(j)))
+    for i in range(n_sites):
+        s = ["I"] * n_sites
+        s[i] = "X"
+        terms.append(("".join(s), complex(h)))
+    return terms
+
+
+def random_state(dim, seed):
+    """(N(0,1) + i N(0,1)) per amplitude, normalised in float64."""
+    rng = np.random.default_rng(seed)
+    v = rng.standard_normal(dim) + 1j * rng.standard_normal(dim)
+    v /= np.sqrt(np.vdot(v, v).real)
+    return v.astype(np.complex128)
+
+
+def random_pauli_strings(n_strings, n_qubits, seed, with_phase=True):
+    """Random letter strings as uint8 arrays (0=I, 1=X, 2=Y, 3=Z) and Z4 phases."""
+    rng = np.random.default_rng(seed)
+    letters = rng.integers(0, 4, size=(n_strings, n_qubits), dtype=np.uint8)
+    phase = rng.integers(0, 4, size=n_strings, dtype=np.uint8) if with_phase else np.zeros(n_strings, np.uint8)
+    return letters, phase
+
+
+def neel_occupations(rows, cols):
+    """Neel-like product state on a rows x cols lattice: site (r, c) holds an
+    alpha electron when r + c is even and a beta electron otherwise.
+    Returns (alpha_bits, beta_bits) as integers over the sites."""
+    a = b = 0
+    for r in range(rows):
+        for c in range(cols):
+            i = r * cols + c
+            if (r + c) % 2 == 0:
+                a |= 1 << i
+            else:
+                b |= 1 << i
+    return a, b
