@@ -1,0 +1,223 @@
+/*
+ * pbs.h -- C ABI of the Pauli-sum operator-state library for AMD MI355X (gfx950).
+ *
+ * Implements the data-parallel path of "A High-Performance Pauli-Algebra
+ * Framework for Large-Scale Quantum Simulations" (arXiv 2606.28952): Pauli
+ * strings in binary symplectic form (Section 2.2), their products and
+ * canonical linear combinations (Section 2.3), the Jordan-Wigner Hamiltonian
+ * built directly from integrals (Section 2.3, Algorithm 1), grouping by
+ * X-mask (Section 2.4, Eq. topological_group), the full and spin-sector
+ * configuration spaces (Section 2.4, spin-resolved product basis; Eq. fcidim)
+ * and the target-driven operator-state product (Eq. reverse_sum,
+ * Eq. sreverse_sum) with the energy of Eq. vqe_energy.  Every data-parallel
+ * step runs as a HIP kernel on the caller's stream.
+ *
+ * Conventions used throughout
+ * ---------------------------
+ *  - Qubit k is bit k of a basis index (Eqs. xp_encoding, zp_encoding).  A
+ *    mask of n qubits occupies W = ceil(n/64) uint64 words, word w holding
+ *    qubits 64w..64w+63; arrays of strings are term-major: x[i*W + w].
+ *  - A string (x, z, g) in "letter form" is i^g times the tensor product of
+ *    sigma^(x_k, z_k) with (0,0)=I, (1,0)=X, (1,1)=Y, (0,1)=Z
+ *    (Eq. single_pauli_mapping, Eq. pauli_group); g is a Z4 exponent stored
+ *    in a uint8 (values 0..3).  Pauli-sum coefficients at this boundary are in
+ *    letter form, complex float64 stored as interleaved (re, im) doubles, so a
+ *    Hermitian sum has real coefficients.  Kernels use the XZ form
+ *    C_k = c_k * i^popcount(x_k & z_k) internally (Section 2.3).
+ *  - Canonical form (Section 2.3): unique strings sorted by (X, Z) read as
+ *    unsigned big integers, X major; every coefficient is the correctly
+ *    rounded (nearest-even) exact sum of its contributions, real and
+ *    imaginary parts separately, with exact zeros written as +0.0; a term is
+ *    dropped when max(|Re c|, |Im c|) <= eps_drop (pass a negative eps_drop
+ *    to keep exact zeros).
+ *  - Sector spaces use n_orb spatial orbitals on 2*n_orb qubits: qubits
+ *    0..n_orb-1 hold the alpha string, n_orb..2n_orb-1 the beta string.  Spin
+ *    strings are enumerated in ascending integer order and a configuration's
+ *    index is rank_alpha * D_beta + rank_beta.
+ *  - State vectors are complex, interleaved (re, im), either complex128
+ *    (PBS_C128) or complex64 (PBS_C64); all accumulation is float64.
+ *
+ * Memory and streams
+ * ------------------
+ *  - Handles (pbs_sum, pbs_grouped, pbs_space) own device memory; it is
+ *    allocated when a handle is built and released by its destroy call.
+ *    Handles are immutable after creation except through
+ *    pbs_pauli_canonicalize, so concurrent const use is thread-safe.
+ *  - Pointers documented as "device" must be device (or managed) memory on
+ *    the current HIP device; pointers documented as "host or device" may be
+ *    either.  State vectors, outputs and workspaces are owned by the caller.
+ *  - `stream` is a hipStream_t (NULL = the null stream).  Calls documented as
+ *    asynchronous only enqueue work; calls that build handles synchronize the
+ *    stream before returning.
+ *
+ * Errors
+ * ------
+ *  Every call returns a pbs_status; no exception crosses the ABI.  On error
+ *  pbs_last_error() returns a message for the calling thread (valid until the
+ *  thread's next call).  HIP failures map to PBS_ERR_DEVICE.
+ */
+#ifndef PBS_H_
+#define PBS_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t pbs_status;
+#define PBS_OK 0
+#define PBS_ERR_ARG 1         /* null pointer, bad enum, inconsistent sizes, overlapping buffers */
+#define PBS_ERR_RANGE 2       /* size or qubit count beyond what the call supports */
+#define PBS_ERR_ALLOC 3       /* device or host allocation failed */
+#define PBS_ERR_DEVICE 4      /* a HIP runtime call failed */
+#define PBS_ERR_UNSUPPORTED 5 /* valid request outside the implemented cases */
+
+typedef enum { PBS_C128 = 0, PBS_C64 = 1 } pbs_dtype;
+
+typedef struct pbs_sum pbs_sum;         /* Pauli sum: strings + letter-form coefficients */
+typedef struct pbs_grouped pbs_grouped; /* sum grouped by X-mask, kernel tables */
+typedef struct pbs_space pbs_space;     /* configuration space (full or spin sector) */
+
+/* Message describing the calling thread's last failure ("" after success). */
+const char* pbs_last_error(void);
+
+/* Library ABI version (increments on any signature change). */
+int32_t pbs_abi_version(void);
+
+/* ------------------------------------------------------------------ strings */
+
+/* Elementwise product of Pauli strings, out_i = A_i * B_i (Section 2.3,
+ * Eqs. pauli_prod_x, pauli_prod_z, pauli_prod_phase): X and Z masks are
+ * XORed and the Z4 phase is computed from popcounts.
+ *  n_qubits  1..256; W = ceil(n_qubits/64) words per mask.
+ *  n         number of string pairs.
+ *  xa, za    device, n*W words each; pa device, n letter-form phases (0..3).
+ *  xb, zb, pb  same for the right factors.
+ *  xo, zo, po  device outputs; they may alias the inputs exactly.
+ * Asynchronous.  Bits at or above n_qubits must be zero (not checked). */
+pbs_status pbs_pauli_mul(uint32_t n_qubits, uint64_t n, const uint64_t* xa, const uint64_t* za, const uint8_t* pa,
+                         const uint64_t* xb, const uint64_t* zb, const uint8_t* pb, uint64_t* xo, uint64_t* zo,
+                         uint8_t* po, void* stream);
+
+/* ------------------------------------------------------------------ Pauli sums */
+
+/* Builds a sum handle from n_terms strings with letter-form coefficients
+ * (arrays X, Z, C of Section 2.3).  x, z: host or device, n_terms*W words;
+ * coeff: host or device, 2*n_terms doubles (re, im).  The data are copied;
+ * the sum is not canonical until pbs_pauli_canonicalize.  Synchronizes. */
+pbs_status pbs_sum_create(uint32_t n_qubits, uint64_t n_terms, const uint64_t* x, const uint64_t* z,
+                          const double* coeff, void* stream, pbs_sum** out);
+
+/* Qubit count, number of terms and whether the sum is canonical (1/0). */
+pbs_status pbs_sum_info(const pbs_sum* s, uint32_t* n_qubits, uint64_t* n_terms, int32_t* canonical);
+
+/* Copies the terms out (host or device destinations sized as in create).
+ * Any destination may be NULL to skip it.  Synchronizes. */
+pbs_status pbs_sum_read(const pbs_sum* s, uint64_t* x, uint64_t* z, double* coeff, void* stream);
+
+void pbs_sum_destroy(pbs_sum* s);
+
+/* Canonical reduction in place (Section 2.3): radix sort on the (X, Z) key,
+ * linear merge with correctly rounded sums, drop rule above.  Synchronizes. */
+pbs_status pbs_pauli_canonicalize(pbs_sum* s, double eps_drop, void* stream);
+
+/* Canonical product of two sums, A*B = sum_kl R(X_k^X_l, Z_k^Z_l, C_kl)
+ * (Eq. pauli_operator_multiplication).  Each coefficient is the correctly
+ * rounded exact value of its sum of pair products.  Requires equal qubit
+ * counts and n_terms(A)*n_terms(B) < 2^30.  Synchronizes. */
+pbs_status pbs_pauli_sum_mul(const pbs_sum* a, const pbs_sum* b, double eps_drop, void* stream, pbs_sum** out);
+
+/* Jordan-Wigner qubit Hamiltonian built directly from integrals (Section 2.3,
+ * Algorithm 1):
+ *   H = e0 I + sum_PQ h1[P,Q] a+_P a_Q + 1/2 sum_PQRS h2[P,Q,R,S] a+_P a+_Q a_R a_S
+ * (Eq. second_quantized_hamiltonian over spin-orbitals), with
+ * a+_p = 1/2 (X_p - i Y_p) Z_{p-1}..Z_0 and a_p = 1/2 (X_p + i Y_p) Z_{p-1}..Z_0.
+ * Each integral with |h| > eps expands into its 4 or 16 Pauli strings and
+ * phase-corrected coefficients by the product rule; the contributions are
+ * reduced to canonical form.
+ *  n_spin_orb  1..256 (qubits).
+ *  h1          device, n^2 doubles, row-major [P][Q].
+ *  h2          device, n^4 doubles, row-major [P][Q][R][S] (may be NULL = 0).
+ * Output: new canonical sum.  Synchronizes. */
+pbs_status pbs_jw_transform(uint32_t n_spin_orb, const double* h1, const double* h2, double e0, double eps,
+                            double eps_drop, void* stream, pbs_sum** out);
+
+/* ------------------------------------------------------------------ grouping */
+
+/* Groups a canonical sum by X-mask (Eq. topological_group): group g holds
+ * X_g, its Z-masks Z_k and XZ-form coefficients C_k = c_k i^popcount(X&Z).
+ * Also builds the tables of the spin-sector kernel when n_qubits is even
+ * (alpha/beta split at n_qubits/2).  Requires a canonical sum with
+ * n_qubits <= 64.  Synchronizes. */
+pbs_status pbs_group_by_xmask(const pbs_sum* h, void* stream, pbs_grouped** out);
+
+/* Qubit count, number of groups G and number of terms M. */
+pbs_status pbs_grouped_info(const pbs_grouped* g, uint32_t* n_qubits, uint64_t* n_groups, uint64_t* n_terms);
+
+/* Copies the CSR form out: xg [G] group masks, offsets [G+1] term offsets,
+ * zk [M] Z-masks, ck [2M] XZ-form coefficients.  Host or device
+ * destinations; NULL skips an array.  Synchronizes. */
+pbs_status pbs_grouped_read(const pbs_grouped* g, uint64_t* xg, uint64_t* offsets, uint64_t* zk, double* ck,
+                            void* stream);
+
+void pbs_grouped_destroy(pbs_grouped* g);
+
+/* ------------------------------------------------------------------ spaces */
+
+/* Full space of n_qubits (1..40): D = 2^n, index = bit pattern. */
+pbs_status pbs_space_full(uint32_t n_qubits, pbs_space** out);
+
+/* Spin sector with fixed (N_alpha, N_beta) (Section 2.4; Eq. fcidim gives
+ * D = C(n_orb, N_alpha) C(n_orb, N_beta)).  n_orb 1..32, D < 2^40.  Builds
+ * the spin-string lists and combinatorial rank tables on the device.
+ * Synchronizes. */
+pbs_status pbs_space_sector(uint32_t n_orb, uint32_t n_alpha, uint32_t n_beta, void* stream, pbs_space** out);
+
+/* Dimension D. */
+pbs_status pbs_space_dim(const pbs_space* sp, uint64_t* dim);
+
+/* Sector shape: n_orb, N_alpha, N_beta, D_alpha, D_beta (zeros and
+ * PBS_ERR_ARG for a full space). */
+pbs_status pbs_space_shape(const pbs_space* sp, uint32_t* n_orb, uint32_t* n_alpha, uint32_t* n_beta,
+                           uint64_t* dim_alpha, uint64_t* dim_beta);
+
+/* Index of each basis bit pattern (device arrays of n), -1 when outside the
+ * space.  Asynchronous. */
+pbs_status pbs_space_rank(const pbs_space* sp, uint64_t n, const uint64_t* bits, int64_t* idx, void* stream);
+
+/* Bit pattern of each index (device arrays of n); indices outside [0, D)
+ * give UINT64_MAX.  Asynchronous. */
+pbs_status pbs_space_unrank(const pbs_space* sp, uint64_t n, const int64_t* idx, uint64_t* bits, void* stream);
+
+void pbs_space_destroy(pbs_space* sp);
+
+/* ------------------------------------------------------------------ operator-state */
+
+/* out = P H P psi (P = projector on the space; equal to H psi for operators
+ * that conserve the sector, and for any operator on the full space), by
+ * target-driven summation over X-mask groups (Eq. reverse_sum; in a sector,
+ * Eq. sreverse_sum): every target amplitude gathers psi[t ^ X_g] times its
+ * group's phase sum, so no two threads write the same output.
+ *  psi, out  device, D complex values of type dt; out must not overlap psi.
+ *  The grouped operator must have the space's qubit count.
+ * Asynchronous; allocates nothing. */
+pbs_status pbs_apply_pauli_sum(const pbs_grouped* h, const pbs_space* sp, pbs_dtype dt, const void* psi, void* out,
+                               void* stream);
+
+/* Device workspace bytes needed by pbs_expval on this space. */
+pbs_status pbs_expval_workspace_bytes(const pbs_space* sp, uint64_t* bytes);
+
+/* Energy of Eq. vqe_energy: result[0..2] = (Re <psi|H|psi>, Im <psi|H|psi>,
+ * <psi|psi>), with the operator-state gather of pbs_apply_pauli_sum fused
+ * into a float64 reduction (the gathered H psi is never rounded to storage
+ * precision).  result: device, 3 doubles; work: device workspace of at
+ * least pbs_expval_workspace_bytes.  Asynchronous; allocates nothing. */
+pbs_status pbs_expval(const pbs_grouped* h, const pbs_space* sp, pbs_dtype dt, const void* psi, double* result,
+                      void* work, uint64_t work_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PBS_H_ */

@@ -274,3 +274,23 @@ def commutes(la, lb):
     lb = np.asarray(lb)
     anti = (la != I) & (lb != I) & (la != lb)
     return int(anti.sum()) % 2 == 0
+
+
+def group_by_x(x, z, coeff):
+    """Partition canonical terms by X-mask (Eq. topological_group).
+
+    Returns (xg [G], offsets [G+1], z [M], C [M]) where C_k = c_k * Lambda_k
+    with Lambda_k = i^popcount(X_k & Z_k) (Section 2.3), i.e. the coefficient
+    of X^x Z^z.  Groups appear in the canonical order (ascending X); exact
+    zeros are written as +0.0, as in the canonical form."""
+    x = np.asarray(x, dtype=np.uint64).reshape(len(coeff), -1)
+    z = np.asarray(z, dtype=np.uint64).reshape(len(coeff), -1)
+    assert x.shape[1] == 1, "single-word masks only"
+    xs = x[:, 0]
+    heads = np.ones(len(xs), dtype=bool)
+    heads[1:] = xs[1:] != xs[:-1]
+    starts = np.flatnonzero(heads)
+    offsets = np.append(starts, len(xs)).astype(np.uint64)
+    n_y = np.bitwise_count(xs & z[:, 0]).astype(np.int64)
+    lam = I_POW[n_y % 4]
+    return xs[starts], offsets, z[:, 0].copy(), np.asarray(coeff) * lam + 0.0

@@ -1,0 +1,245 @@
+"""Python binding of the C ABI (argument marshalling only).
+
+Bulk arrays are torch tensors on the HIP device; 64-bit masks travel as
+torch.int64 tensors holding the unsigned bit patterns.  Every computation
+runs in the HIP library on the current torch stream; handles free their
+device memory when garbage-collected.
+"""
+
+import ctypes
+from ctypes import byref, c_int32, c_uint32, c_uint64, c_void_p
+
+import numpy as np
+import torch
+
+from . import _abi
+from ._abi import PBS_C64, PBS_C128, call
+
+__all__ = [
+    "PauliSum", "Grouped", "Space", "pauli_mul", "jw_transform", "apply_pauli_sum", "expval",
+    "words_for", "PBS_C64", "PBS_C128",
+]
+
+
+def words_for(n_qubits):
+    return max(1, (n_qubits + 63) // 64)
+
+
+def _stream():
+    return c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if isinstance(t, np.ndarray):
+        assert t.flags.c_contiguous
+        return c_void_p(t.ctypes.data)
+    assert t.is_contiguous(), "tensor must be contiguous"
+    return c_void_p(t.data_ptr())
+
+
+def _dev_u64(a, device="cuda"):
+    """numpy uint64 / int64 / torch tensor -> contiguous int64 device tensor."""
+    if isinstance(a, torch.Tensor):
+        return a.to(device=device, dtype=torch.int64).contiguous()
+    arr = np.ascontiguousarray(np.asarray(a).astype(np.uint64).view(np.int64))
+    return torch.from_numpy(arr).to(device)
+
+
+def pauli_mul(n_qubits, xa, za, pa, xb, zb, pb):
+    """Elementwise products of strings (device tensors); returns (x, z, phase)."""
+    w = words_for(n_qubits)
+    n = pa.numel()
+    xo = torch.empty(n * w, dtype=torch.int64, device=xa.device)
+    zo = torch.empty_like(xo)
+    po = torch.empty(n, dtype=torch.uint8, device=xa.device)
+    call("pbs_pauli_mul", n_qubits, n, _ptr(xa), _ptr(za), _ptr(pa), _ptr(xb), _ptr(zb), _ptr(pb),
+         _ptr(xo), _ptr(zo), _ptr(po), _stream())
+    return xo, zo, po
+
+
+class PauliSum:
+    """Handle to a library-owned Pauli sum (letter-form coefficients)."""
+
+    def __init__(self, handle):
+        self._h = c_void_p(handle) if not isinstance(handle, c_void_p) else handle
+
+    @staticmethod
+    def create(n_qubits, x, z, coeff):
+        """x, z: uint64 words [m*W] (numpy host or torch device); coeff: complex [m]."""
+        if isinstance(coeff, torch.Tensor):
+            c = torch.view_as_real(coeff.to(torch.complex128).contiguous()).contiguous()
+            xd, zd = _dev_u64(x, coeff.device), _dev_u64(z, coeff.device)
+        else:
+            c = np.ascontiguousarray(np.asarray(coeff, dtype=np.complex128).view(np.float64))
+            xd = np.ascontiguousarray(np.asarray(x, dtype=np.uint64).reshape(-1))
+            zd = np.ascontiguousarray(np.asarray(z, dtype=np.uint64).reshape(-1))
+        m = (c.shape[0] // 2) if isinstance(c, np.ndarray) else c.shape[0]
+        out = c_void_p()
+        call("pbs_sum_create", n_qubits, m, _ptr(xd), _ptr(zd), _ptr(c), _stream(), byref(out))
+        return PauliSum(out)
+
+    def info(self):
+        nq, nt, can = c_uint32(), c_uint64(), c_int32()
+        call("pbs_sum_info", self._h, byref(nq), byref(nt), byref(can))
+        return nq.value, nt.value, bool(can.value)
+
+    @property
+    def n_qubits(self):
+        return self.info()[0]
+
+    @property
+    def n_terms(self):
+        return self.info()[1]
+
+    def read(self):
+        """Host copies (x [m, W] uint64, z [m, W] uint64, coeff [m] complex128)."""
+        nq, m, _ = self.info()
+        w = words_for(nq)
+        x = np.empty((m, w), np.uint64)
+        z = np.empty((m, w), np.uint64)
+        c = np.empty(m, np.complex128)
+        call("pbs_sum_read", self._h, _ptr(x), _ptr(z), _ptr(c.view(np.float64)), _stream())
+        return x, z, c
+
+    def canonicalize(self, eps_drop=0.0):
+        call("pbs_pauli_canonicalize", self._h, float(eps_drop), _stream())
+        return self
+
+    def mul(self, other, eps_drop=0.0):
+        out = c_void_p()
+        call("pbs_pauli_sum_mul", self._h, other._h, float(eps_drop), _stream(), byref(out))
+        return PauliSum(out)
+
+    def group(self):
+        out = c_void_p()
+        call("pbs_group_by_xmask", self._h, _stream(), byref(out))
+        return Grouped(out)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _abi._LIB is not None:
+            _abi._LIB.pbs_sum_destroy(h)
+            self._h = None
+
+
+def jw_transform(h1, h2, e0=0.0, eps=0.0, eps_drop=0.0):
+    """Canonical JW Hamiltonian from spin-orbital integrals (float64 device tensors)."""
+    n = h1.shape[0]
+    h1d = h1.to(dtype=torch.float64).contiguous()
+    h2d = None if h2 is None else h2.to(dtype=torch.float64).contiguous()
+    out = c_void_p()
+    call("pbs_jw_transform", n, _ptr(h1d), _ptr(h2d), float(e0), float(eps), float(eps_drop), _stream(), byref(out))
+    return PauliSum(out)
+
+
+class Grouped:
+    """Handle to an operator grouped by X-mask with its kernel tables."""
+
+    def __init__(self, handle):
+        self._h = handle
+
+    def info(self):
+        nq, g, m = c_uint32(), c_uint64(), c_uint64()
+        call("pbs_grouped_info", self._h, byref(nq), byref(g), byref(m))
+        return nq.value, g.value, m.value
+
+    @property
+    def n_groups(self):
+        return self.info()[1]
+
+    def read(self):
+        """Host copies (xg [G], offsets [G+1], zk [M], ck [M] complex128)."""
+        _, g, m = self.info()
+        xg = np.empty(g, np.uint64)
+        off = np.empty(g + 1, np.uint64)
+        zk = np.empty(m, np.uint64)
+        ck = np.empty(m, np.complex128)
+        call("pbs_grouped_read", self._h, _ptr(xg), _ptr(off), _ptr(zk), _ptr(ck.view(np.float64)), _stream())
+        return xg, off, zk, ck
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _abi._LIB is not None:
+            _abi._LIB.pbs_grouped_destroy(h)
+            self._h = None
+
+
+class Space:
+    """Full 2^n space or a fixed-(N_alpha, N_beta) spin sector."""
+
+    def __init__(self, handle):
+        self._h = handle
+
+    @staticmethod
+    def full(n_qubits):
+        out = c_void_p()
+        call("pbs_space_full", n_qubits, byref(out))
+        return Space(out)
+
+    @staticmethod
+    def sector(n_orb, n_alpha, n_beta):
+        out = c_void_p()
+        call("pbs_space_sector", n_orb, n_alpha, n_beta, _stream(), byref(out))
+        return Space(out)
+
+    @property
+    def dim(self):
+        d = c_uint64()
+        call("pbs_space_dim", self._h, byref(d))
+        return d.value
+
+    def shape(self):
+        vals = [c_uint32(), c_uint32(), c_uint32(), c_uint64(), c_uint64()]
+        call("pbs_space_shape", self._h, *[byref(v) for v in vals])
+        return tuple(v.value for v in vals)
+
+    def rank(self, bits):
+        """bits: int64 device tensor of basis patterns -> int64 indices (-1 outside)."""
+        idx = torch.empty_like(bits, dtype=torch.int64)
+        call("pbs_space_rank", self._h, bits.numel(), _ptr(bits), _ptr(idx), _stream())
+        return idx
+
+    def unrank(self, idx):
+        bits = torch.empty_like(idx, dtype=torch.int64)
+        call("pbs_space_unrank", self._h, idx.numel(), _ptr(idx), _ptr(bits), _stream())
+        return bits
+
+    def workspace_bytes(self):
+        b = c_uint64()
+        call("pbs_expval_workspace_bytes", self._h, byref(b))
+        return b.value
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _abi._LIB is not None:
+            _abi._LIB.pbs_space_destroy(h)
+            self._h = None
+
+
+def _dtype_code(t):
+    if t.dtype == torch.complex128:
+        return PBS_C128
+    if t.dtype == torch.complex64:
+        return PBS_C64
+    raise TypeError(f"state must be complex64 or complex128, got {t.dtype}")
+
+
+def apply_pauli_sum(grouped, space, psi, out=None):
+    """out = P H P psi on the device (asynchronous on the current stream)."""
+    if out is None:
+        out = torch.empty_like(psi)
+    call("pbs_apply_pauli_sum", grouped._h, space._h, _dtype_code(psi), _ptr(psi), _ptr(out), _stream())
+    return out
+
+
+def expval(grouped, space, psi, work=None, result=None):
+    """(Re <psi|H|psi>, Im <psi|H|psi>, <psi|psi>) as a float64 device tensor of 3."""
+    if work is None:
+        work = torch.empty(max(1, space.workspace_bytes() // 8), dtype=torch.float64, device=psi.device)
+    if result is None:
+        result = torch.empty(3, dtype=torch.float64, device=psi.device)
+    call("pbs_expval", grouped._h, space._h, _dtype_code(psi), _ptr(psi), _ptr(result), _ptr(work),
+         work.numel() * 8, _stream())
+    return result

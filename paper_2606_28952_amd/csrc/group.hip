@@ -1,0 +1,267 @@
+// Grouping of a canonical Pauli sum by X-mask (Section 2.4,
+// Eq. topological_group) and the tables of the spin-sector kernel.
+#include "handles.h"
+
+namespace pbs {
+namespace {
+
+__global__ void k_x_heads(const uint64_t* x, uint64_t m, uint32_t* heads) {
+  for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < m;
+       i += static_cast<uint64_t>(gridDim.x) * blockDim.x)
+    heads[i] = (i == 0 || x[i] != x[i - 1]) ? 1u : 0u;
+}
+
+// CSR fill: group masks and offsets from heads; XZ-form coefficients
+// C_k = c_k * i^popcount(x_k & z_k) (Section 2.3).
+__global__ void k_csr_fill(const uint64_t* x, const uint64_t* z, const double* c, uint64_t m, const uint32_t* heads,
+                           const uint32_t* gid, uint64_t* xg, uint32_t* off, uint64_t* zk, double* ck) {
+  for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < m;
+       i += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+    if (heads[i]) {
+      xg[gid[i]] = x[i];
+      off[gid[i]] = static_cast<uint32_t>(i);
+    }
+    zk[i] = z[i];
+    const uint32_t y = static_cast<uint32_t>(__popcll(x[i] & z[i])) & 3u;
+    const double r = c[2 * i], im = c[2 * i + 1];
+    double a = r, b = im;
+    if (y == 1) { a = -im; b = r; }
+    else if (y == 2) { a = -r; b = -im; }
+    else if (y == 3) { a = im; b = -r; }
+    ck[2 * i] = a + 0.0;  // exact zeros written as +0.0
+    ck[2 * i + 1] = b + 0.0;
+  }
+}
+
+__global__ void k_set_u32(uint32_t* p, uint32_t v) { *p = v; }
+
+// Sector rewrite of every term: alive flag, sort keys and signed coefficient.
+__global__ void k_sector_terms(const uint64_t* x, const uint64_t* zk, const double* ck, uint64_t m, uint32_t h,
+                               uint32_t* alive, uint64_t* key_hi, uint64_t* key_lo, double* cre, double* cim) {
+  const uint64_t mask = (h == 32) ? 0xffffffffull : ((1ull << h) - 1ull);
+  for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < m;
+       i += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+    const uint64_t xa = x[i] & mask, xb = (x[i] >> h) & mask;
+    const uint64_t za = zk[i] & mask;
+    uint64_t zb = (zk[i] >> h) & mask;
+    const int pa = __popcll(xa), pb = __popcll(xb);
+    alive[i] = ((pa & 1) == 0 && (pb & 1) == 0) ? 1u : 0u;
+    double sgn = 1.0;
+    if (xb != 0 && (zb & (xb & (~xb + 1ull)))) {
+      zb ^= xb;
+      if ((pb >> 1) & 1) sgn = -1.0;
+    }
+    key_hi[i] = (xa << 32) | xb;
+    key_lo[i] = (zb << 32) | za;
+    cre[i] = sgn * ck[2 * i];
+    cim[i] = sgn * ck[2 * i + 1];
+  }
+}
+
+__global__ void k_compact_alive(const uint32_t* alive, const uint32_t* pos, uint64_t m, const uint64_t* key_hi,
+                                const uint64_t* key_lo, uint64_t* keys_soa, uint64_t ma) {
+  for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < m;
+       i += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+    if (!alive[i]) continue;
+    const uint64_t o = pos[i];
+    keys_soa[o] = key_lo[i];        // word 0 (less significant)
+    keys_soa[ma + o] = key_hi[i];   // word 1
+  }
+}
+
+__global__ void k_alive_index(const uint32_t* alive, const uint32_t* pos, uint64_t m, uint32_t* src) {
+  for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < m;
+       i += static_cast<uint64_t>(gridDim.x) * blockDim.x)
+    if (alive[i]) src[pos[i]] = static_cast<uint32_t>(i);
+}
+
+// Heads of classes (X_alpha), plan groups (X_alpha, X_beta) and uniques
+// (X_alpha, X_beta, z_beta') over the sorted alive terms.
+__global__ void k_plan_heads(const uint64_t* keys_soa, uint64_t ma, uint32_t* hc, uint32_t* hg, uint32_t* hu) {
+  for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < ma;
+       i += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+    const uint64_t hi = keys_soa[ma + i], lo = keys_soa[i];
+    if (i == 0) {
+      hc[i] = hg[i] = hu[i] = 1u;
+      continue;
+    }
+    const uint64_t phi = keys_soa[ma + i - 1], plo = keys_soa[i - 1];
+    hc[i] = ((hi >> 32) != (phi >> 32)) ? 1u : 0u;
+    hg[i] = (hi != phi) ? 1u : 0u;
+    hu[i] = (hi != phi || (lo >> 32) != (plo >> 32)) ? 1u : 0u;
+  }
+}
+
+__global__ void k_plan_fill(const uint64_t* keys_soa, uint64_t ma, const uint32_t* order, const uint32_t* src,
+                            const double* cre, const double* cim, const uint32_t* hc, const uint32_t* hg,
+                            const uint32_t* hu, const uint32_t* cid, const uint32_t* gid, const uint32_t* uid,
+                            uint32_t* cls_xa, uint32_t* cls_g0, uint32_t* pg_xb, uint32_t* pg_u0, uint32_t* u_zb,
+                            uint32_t* u_t0, uint32_t* pt_za, double* pt_c) {
+  for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < ma;
+       i += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+    const uint64_t hi = keys_soa[ma + i], lo = keys_soa[i];
+    if (hc[i]) {
+      cls_xa[cid[i]] = static_cast<uint32_t>(hi >> 32);
+      cls_g0[cid[i]] = gid[i];
+    }
+    if (hg[i]) {
+      pg_xb[gid[i]] = static_cast<uint32_t>(hi & 0xffffffffull);
+      pg_u0[gid[i]] = uid[i];
+    }
+    if (hu[i]) {
+      u_zb[uid[i]] = static_cast<uint32_t>(lo >> 32);
+      u_t0[uid[i]] = static_cast<uint32_t>(i);
+    }
+    pt_za[i] = static_cast<uint32_t>(lo & 0xffffffffull);
+    const uint32_t s = src[order[i]];
+    pt_c[2 * i] = cre[s];
+    pt_c[2 * i + 1] = cim[s];
+  }
+}
+
+}  // namespace
+
+static void build_sector_tables(pbs_grouped& g, const uint64_t* x, hipStream_t s) {
+  const uint64_t m = g.n_terms;
+  const uint32_t h = g.n_qubits / 2;
+  g.half = h;
+  DevBuf<uint32_t> alive(m), apos(m), cnt(4);
+  DevBuf<uint64_t> key_hi(m), key_lo(m);
+  DevBuf<double> cre(m), cim(m);
+  hipLaunchKernelGGL(k_sector_terms, dim3(grid_for(m, 256, 65536)), dim3(256), 0, s, x, g.zk.get(), g.ck.get(), m, h,
+                     alive.get(), key_hi.get(), key_lo.get(), cre.get(), cim.get());
+  PBS_HIP(hipGetLastError());
+  exclusive_scan_u32(alive.get(), apos.get(), m, cnt.get(), s);
+  const uint64_t ma = read_scalar(cnt.get(), s);
+  g.n_pterm = static_cast<uint32_t>(ma);
+  if (ma == 0) {
+    g.n_class = g.n_pgroup = g.n_unique = 0;
+    g.cls_g0.alloc(1);
+    g.pg_u0.alloc(1);
+    g.u_t0.alloc(1);
+    hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, s, g.cls_g0.get(), 0u);
+    hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, s, g.pg_u0.get(), 0u);
+    hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, s, g.u_t0.get(), 0u);
+    PBS_HIP(hipStreamSynchronize(s));
+    g.has_sector = true;
+    return;
+  }
+  DevBuf<uint64_t> keys(2 * ma);
+  DevBuf<uint32_t> src(ma), order(ma);
+  hipLaunchKernelGGL(k_compact_alive, dim3(grid_for(m, 256, 65536)), dim3(256), 0, s, alive.get(), apos.get(), m,
+                     key_hi.get(), key_lo.get(), keys.get(), ma);
+  hipLaunchKernelGGL(k_alive_index, dim3(grid_for(m, 256, 65536)), dim3(256), 0, s, alive.get(), apos.get(), m,
+                     src.get());
+  PBS_HIP(hipGetLastError());
+  iota_u32(order.get(), ma, s);
+  radix_sort_keys(keys.get(), order.get(), ma, 2, s);
+  DevBuf<uint32_t> hc(ma), hg(ma), hu(ma), cid(ma), gid(ma), uid(ma);
+  hipLaunchKernelGGL(k_plan_heads, dim3(grid_for(ma, 256, 65536)), dim3(256), 0, s, keys.get(), ma, hc.get(),
+                     hg.get(), hu.get());
+  exclusive_scan_u32(hc.get(), cid.get(), ma, cnt.get() + 1, s);
+  exclusive_scan_u32(hg.get(), gid.get(), ma, cnt.get() + 2, s);
+  exclusive_scan_u32(hu.get(), uid.get(), ma, cnt.get() + 3, s);
+  uint32_t counts[4];
+  PBS_HIP(hipMemcpyAsync(counts, cnt.get(), sizeof(counts), hipMemcpyDeviceToHost, s));
+  PBS_HIP(hipStreamSynchronize(s));
+  g.n_class = counts[1];
+  g.n_pgroup = counts[2];
+  g.n_unique = counts[3];
+  g.cls_xa.alloc(g.n_class);
+  g.cls_g0.alloc(g.n_class + 1);
+  g.pg_xb.alloc(g.n_pgroup);
+  g.pg_u0.alloc(g.n_pgroup + 1);
+  g.u_zb.alloc(g.n_unique);
+  g.u_t0.alloc(g.n_unique + 1);
+  g.pt_za.alloc(ma);
+  g.pt_c.alloc(2 * ma);
+  hipLaunchKernelGGL(k_plan_fill, dim3(grid_for(ma, 256, 65536)), dim3(256), 0, s, keys.get(), ma, order.get(),
+                     src.get(), cre.get(), cim.get(), hc.get(), hg.get(), hu.get(), cid.get(), gid.get(), uid.get(),
+                     g.cls_xa.get(), g.cls_g0.get(), g.pg_xb.get(), g.pg_u0.get(), g.u_zb.get(), g.u_t0.get(),
+                     g.pt_za.get(), g.pt_c.get());
+  hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, s, g.cls_g0.get() + g.n_class, g.n_pgroup);
+  hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, s, g.pg_u0.get() + g.n_pgroup, g.n_unique);
+  hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, s, g.u_t0.get() + g.n_unique, static_cast<uint32_t>(ma));
+  PBS_HIP(hipGetLastError());
+  PBS_HIP(hipStreamSynchronize(s));
+  g.has_sector = true;
+}
+
+}  // namespace pbs
+
+using namespace pbs;
+
+extern "C" {
+
+pbs_status pbs_group_by_xmask(const pbs_sum* hs, void* stream, pbs_grouped** out) {
+  return guarded([&] {
+    PBS_REQUIRE(out != nullptr, PBS_ERR_ARG, "null output handle");
+    *out = nullptr;
+    PBS_REQUIRE(hs != nullptr, PBS_ERR_ARG, "null pbs_sum");
+    PBS_REQUIRE(hs->canonical, PBS_ERR_ARG, "group_by_xmask needs a canonical sum");
+    PBS_REQUIRE(hs->n_qubits <= 64, PBS_ERR_RANGE, "grouping supports at most 64 qubits");
+    hipStream_t s = as_stream(stream);
+    auto* g = new pbs_grouped();
+    try {
+      const uint64_t m = hs->n_terms;
+      g->n_qubits = hs->n_qubits;
+      g->n_terms = m;
+      DevBuf<uint32_t> heads(m), gid(m), cnt(1);
+      uint64_t G = 0;
+      if (m) {
+        hipLaunchKernelGGL(k_x_heads, dim3(grid_for(m, 256, 65536)), dim3(256), 0, s, hs->x.get(), m, heads.get());
+        exclusive_scan_u32(heads.get(), gid.get(), m, cnt.get(), s);
+        G = read_scalar(cnt.get(), s);
+      }
+      g->n_groups = G;
+      g->xg.alloc(G);
+      g->off.alloc(G + 1);
+      g->zk.alloc(m);
+      g->ck.alloc(2 * m);
+      hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, s, g->off.get() + G, static_cast<uint32_t>(m));
+      if (m)
+        hipLaunchKernelGGL(k_csr_fill, dim3(grid_for(m, 256, 65536)), dim3(256), 0, s, hs->x.get(), hs->z.get(),
+                           hs->coeff.get(), m, heads.get(), gid.get(), g->xg.get(), g->off.get(), g->zk.get(),
+                           g->ck.get());
+      PBS_HIP(hipGetLastError());
+      PBS_HIP(hipStreamSynchronize(s));
+      if ((g->n_qubits % 2) == 0) build_sector_tables(*g, hs->x.get(), s);
+    } catch (...) {
+      delete g;
+      throw;
+    }
+    *out = g;
+  });
+}
+
+pbs_status pbs_grouped_info(const pbs_grouped* g, uint32_t* n_qubits, uint64_t* n_groups, uint64_t* n_terms) {
+  return guarded([&] {
+    PBS_REQUIRE(g != nullptr, PBS_ERR_ARG, "null pbs_grouped");
+    if (n_qubits) *n_qubits = g->n_qubits;
+    if (n_groups) *n_groups = g->n_groups;
+    if (n_terms) *n_terms = g->n_terms;
+  });
+}
+
+pbs_status pbs_grouped_read(const pbs_grouped* g, uint64_t* xg, uint64_t* offsets, uint64_t* zk, double* ck,
+                            void* stream) {
+  return guarded([&] {
+    PBS_REQUIRE(g != nullptr, PBS_ERR_ARG, "null pbs_grouped");
+    hipStream_t s = as_stream(stream);
+    if (xg && g->n_groups) PBS_HIP(hipMemcpyAsync(xg, g->xg.get(), g->n_groups * 8, hipMemcpyDefault, s));
+    if (zk && g->n_terms) PBS_HIP(hipMemcpyAsync(zk, g->zk.get(), g->n_terms * 8, hipMemcpyDefault, s));
+    if (ck && g->n_terms) PBS_HIP(hipMemcpyAsync(ck, g->ck.get(), g->n_terms * 16, hipMemcpyDefault, s));
+    if (offsets) {
+      std::vector<uint32_t> o(g->n_groups + 1);
+      PBS_HIP(hipMemcpyAsync(o.data(), g->off.get(), o.size() * 4, hipMemcpyDeviceToHost, s));
+      PBS_HIP(hipStreamSynchronize(s));
+      std::vector<uint64_t> o64(o.begin(), o.end());
+      PBS_HIP(hipMemcpyAsync(offsets, o64.data(), o64.size() * 8, hipMemcpyDefault, s));
+    }
+    PBS_HIP(hipStreamSynchronize(s));
+  });
+}
+
+void pbs_grouped_destroy(pbs_grouped* g) { delete g; }
+
+}  // extern "C"

@@ -1,0 +1,66 @@
+// Device-side layout of the grouped operator and the configuration spaces.
+#pragma once
+
+#include "pbs_internal.h"
+
+// Operator grouped by X-mask (Eq. topological_group) plus the tables of the
+// spin-sector kernel.
+//
+// CSR form (full-space kernel): group g has mask xg[g] and terms
+// off[g]..off[g+1]-1 with Z-masks zk[] and XZ-form coefficients ck[] (re, im).
+//
+// Sector form (n_qubits even, split at h = n_qubits/2 into alpha = low half,
+// beta = high half).  Terms are ordered by (X_alpha, X_beta, z_beta', z_alpha):
+//   class c      : distinct X_alpha, groups cls_g0[c]..cls_g0[c+1]-1
+//   group g      : X_beta = pg_xb[g], uniques pg_u0[g]..pg_u0[g+1]-1
+//   unique u     : beta Z-mask u_zb[u], terms u_t0[u]..u_t0[u+1]-1
+//   term t       : alpha Z-mask pt_za[t], coefficient pt_c[t] (re, im)
+// Two exact rewrites valid inside any fixed-(N_alpha, N_beta) sector are
+// applied: a term whose X_alpha or X_beta has odd popcount never maps a
+// sector configuration into the sector and is removed; and because a
+// sector-preserving move with X_beta flips exactly |X_beta|/2 set bits,
+// (-1)^popcount(z & s) = (-1)^(|X_beta|/2) (-1)^popcount((z ^ X_beta) & s),
+// so z_beta is replaced by the smaller of z_beta and z_beta ^ X_beta (the
+// one without X_beta's lowest bit) with the sign moved into the coefficient.
+// Terms that become equal in (z_beta', z_alpha) are kept separate; those with
+// equal z_beta' share one unique entry, whose alpha parities are folded per
+// target row at run time.
+struct pbs_grouped {
+  uint32_t n_qubits = 0;
+  uint64_t n_groups = 0;
+  uint64_t n_terms = 0;
+  pbs::DevBuf<uint64_t> xg;
+  pbs::DevBuf<uint32_t> off;
+  pbs::DevBuf<uint64_t> zk;
+  pbs::DevBuf<double> ck;
+
+  bool has_sector = false;
+  uint32_t half = 0;
+  uint32_t n_class = 0, n_pgroup = 0, n_unique = 0, n_pterm = 0;
+  pbs::DevBuf<uint32_t> cls_xa, cls_g0;
+  pbs::DevBuf<uint32_t> pg_xb, pg_u0;
+  pbs::DevBuf<uint32_t> u_zb, u_t0;
+  pbs::DevBuf<uint32_t> pt_za;
+  pbs::DevBuf<double> pt_c;
+};
+
+// Full space (D = 2^n) or spin sector.
+struct pbs_space {
+  bool sector = false;
+  uint32_t n_qubits = 0;
+  uint64_t dim = 0;
+  uint32_t n_orb = 0, n_alpha = 0, n_beta = 0;
+  uint64_t dim_alpha = 0, dim_beta = 0;
+  uint32_t n_chunks = 0;              // 8-bit chunks of an n_orb-bit spin string
+  pbs::DevBuf<uint32_t> str_alpha;    // [dim_alpha] ascending
+  pbs::DevBuf<uint32_t> str_beta;     // [dim_beta] ascending
+  // rank_tab[(c * (n_orb + 1) + k) * 256 + b]: contribution of byte b of chunk c
+  // to the combinatorial rank when k ones lie below the chunk.
+  pbs::DevBuf<uint32_t> rank_tab;
+};
+
+namespace pbs {
+inline size_t rank_tab_entries(uint32_t n_orb) {
+  return static_cast<size_t>((n_orb + 7) / 8) * (n_orb + 1) * 256;
+}
+}  // namespace pbs

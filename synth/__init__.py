@@ -170,3 +170,28 @@ def neel_occupations(rows, cols):
             else:
                 b |= 1 << i
     return a, b
+
+
+def random_symplectic(n_strings, n_qubits, seed, pool=None):
+    """Random binary symplectic masks: x, z uint64 [n_strings, W] with bits at or
+    above n_qubits clear, and uniform Z4 phases.  With ``pool``, rows are drawn
+    from ``pool`` distinct random keys (so that duplicates occur)."""
+    rng = np.random.default_rng(seed)
+    w = max(1, (n_qubits + 63) // 64)
+    rows = n_strings if pool is None else pool
+
+    def draw():
+        words = rng.integers(0, 2 ** 63, size=(rows, w), dtype=np.uint64) * np.uint64(2) + \
+            rng.integers(0, 2, size=(rows, w), dtype=np.uint64)
+        for k in range(w):
+            top = n_qubits - 64 * k
+            if top < 64:
+                words[:, k] &= np.uint64((1 << max(top, 0)) - 1)
+        return words
+
+    x, z = draw(), draw()
+    if pool is not None:
+        pick = rng.integers(0, pool, size=n_strings)
+        x, z = x[pick], z[pick]
+    phase = rng.integers(0, 4, size=n_strings, dtype=np.uint8)
+    return np.ascontiguousarray(x), np.ascontiguousarray(z), phase

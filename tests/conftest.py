@@ -25,3 +25,25 @@ def golden_rows(name):
             if line:
                 rows.append(line.split())
     return rows
+
+
+@pytest.fixture(scope="session")
+def dev():
+    """HIP device for GPU tests; the library must be built (no fallback)."""
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2606_28952_amd import _abi
+
+    _abi.lib()  # raises if libpbs.so is missing
+    return torch.device("cuda:0")
+
+
+def rel_err(a, b):
+    import numpy as np
+
+    a = np.asarray(a)
+    b = np.asarray(b)
+    den = np.linalg.norm(b)
+    return float(np.linalg.norm(a - b) / (den if den > 0 else 1.0))

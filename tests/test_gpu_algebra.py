@@ -1,0 +1,171 @@
+"""GPU parity of the Pauli algebra through the C ABI, bit-exact against the
+oracle: string products, canonical reduction, sum products and the
+Jordan-Wigner Hamiltonian."""
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import jw as ojw
+from oracle import pauli as opauli
+from oracle.pauli import PauliSum as OSum
+
+pytestmark = pytest.mark.gpu
+
+
+def _api():
+    from paper_2606_28952_amd import api
+
+    return api
+
+
+def _oracle_mul(n, xa, za, pa, xb, zb, pb):
+    la = opauli.xz_to_letters(xa, za, n)
+    lb = opauli.xz_to_letters(xb, zb, n)
+    lo, po = opauli.string_product(la, pa, lb, pb)
+    xo, zo = opauli.letters_to_xz(lo)
+    return xo, zo, po
+
+
+@pytest.mark.parametrize("n", [1, 7, 63, 64, 65, 130, 256])
+def test_pauli_mul_bit_exact(dev, n):
+    api = _api()
+    m = 3001
+    xa, za, pa = synth.random_symplectic(m, n, seed=10 + n)
+    xb, zb, pb = synth.random_symplectic(m, n, seed=20 + n)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a).view(np.int64).reshape(-1)).to(dev)
+    xo, zo, po = api.pauli_mul(n, t(xa), t(za), torch.from_numpy(pa).to(dev), t(xb), t(zb),
+                               torch.from_numpy(pb).to(dev))
+    rx, rz, rp = _oracle_mul(n, xa, za, pa, xb, zb, pb)
+    np.testing.assert_array_equal(xo.cpu().numpy().view(np.uint64).reshape(m, -1), rx)
+    np.testing.assert_array_equal(zo.cpu().numpy().view(np.uint64).reshape(m, -1), rz)
+    np.testing.assert_array_equal(po.cpu().numpy(), rp)
+
+
+def test_pauli_mul_in_place(dev):
+    api = _api()
+    n, m = 40, 500
+    xa, za, pa = synth.random_symplectic(m, n, seed=1)
+    xb, zb, pb = synth.random_symplectic(m, n, seed=2)
+    ta = torch.from_numpy(xa.view(np.int64).reshape(-1)).to(dev)
+    tz = torch.from_numpy(za.view(np.int64).reshape(-1)).to(dev)
+    tp = torch.from_numpy(pa).to(dev)
+    from paper_2606_28952_amd._abi import call
+    from paper_2606_28952_amd.api import _ptr, _stream
+    tb = [torch.from_numpy(v).to(dev) for v in (xb.view(np.int64).reshape(-1), zb.view(np.int64).reshape(-1), pb)]
+    call("pbs_pauli_mul", n, m, _ptr(ta), _ptr(tz), _ptr(tp), _ptr(tb[0]), _ptr(tb[1]), _ptr(tb[2]),
+         _ptr(ta), _ptr(tz), _ptr(tp), _stream())
+    rx, rz, rp = _oracle_mul(n, xa, za, pa, xb, zb, pb)
+    np.testing.assert_array_equal(ta.cpu().numpy().view(np.uint64).reshape(m, -1), rx)
+    np.testing.assert_array_equal(tp.cpu().numpy(), rp)
+
+
+def _canon_case(n, m, pool, seed, scale_spread):
+    x, z, _ = synth.random_symplectic(m, n, seed=seed, pool=pool)
+    rng = np.random.default_rng(seed + 1)
+    mag = 10.0 ** rng.integers(-scale_spread, scale_spread + 1, size=m)
+    c = (rng.standard_normal(m) * mag + 1j * rng.standard_normal(m) * mag).astype(np.complex128)
+    # exact cancellations: duplicate some rows with negated coefficients
+    k = m // 10
+    x = np.concatenate([x, x[:k]])
+    z = np.concatenate([z, z[:k]])
+    c = np.concatenate([c, -c[:k]])
+    return x, z, c
+
+
+@pytest.mark.parametrize("n,m,pool,spread", [(5, 2000, 300, 0), (28, 50_000, 4000, 12), (64, 20_000, 20_000, 3),
+                                             (130, 5000, 600, 20), (12, 1, 1, 0)])
+@pytest.mark.parametrize("eps", [0.0, 1e-3, -1.0])
+def test_canonicalize_bit_exact(dev, n, m, pool, spread, eps):
+    api = _api()
+    x, z, c = _canon_case(n, m, pool, seed=n + m, scale_spread=spread)
+    s = api.PauliSum.create(n, x.reshape(-1), z.reshape(-1), c)
+    s.canonicalize(eps)
+    gx, gz, gc = s.read()
+    rx, rz, rc = opauli.canonicalize_xz(x, z, c.real, c.imag, eps)
+    np.testing.assert_array_equal(gx, rx)
+    np.testing.assert_array_equal(gz, rz)
+    assert gc.tobytes() == rc.tobytes()
+    assert s.info()[2]
+
+
+def test_canonicalize_empty(dev):
+    api = _api()
+    s = api.PauliSum.create(10, np.zeros(0, np.uint64), np.zeros(0, np.uint64), np.zeros(0, np.complex128))
+    s.canonicalize()
+    assert s.n_terms == 0
+
+
+@pytest.mark.parametrize("n,ma,mb", [(4, 12, 9), (9, 40, 30), (70, 25, 20)])
+def test_sum_mul_bit_exact(dev, n, ma, mb):
+    api = _api()
+    rng = np.random.default_rng(n)
+    la, _ = synth.random_pauli_strings(ma, n, seed=100 + n)
+    lb, _ = synth.random_pauli_strings(mb, n, seed=200 + n)
+    ca = rng.standard_normal(ma) + 1j * rng.standard_normal(ma)
+    cb = rng.standard_normal(mb) + 1j * rng.standard_normal(mb)
+    A, B = OSum(n, la, ca), OSum(n, lb, cb)
+    xa, za = opauli.letters_to_xz(la)
+    xb, zb = opauli.letters_to_xz(lb)
+    ga = api.PauliSum.create(n, xa.reshape(-1), za.reshape(-1), ca)
+    gb = api.PauliSum.create(n, xb.reshape(-1), zb.reshape(-1), cb)
+    gx, gz, gc = ga.mul(gb).read()
+    rx, rz, rc = opauli.sum_product_canonical(A, B)
+    np.testing.assert_array_equal(gx, rx)
+    np.testing.assert_array_equal(gz, rz)
+    assert gc.tobytes() == rc.tobytes()
+
+
+def _jw_gpu(dev, h1, h2, e0=0.0, eps=0.0, eps_drop=0.0):
+    api = _api()
+    return api.jw_transform(torch.from_numpy(h1).to(dev), None if h2 is None else torch.from_numpy(h2).to(dev),
+                            e0, eps, eps_drop).read()
+
+
+def _assert_same(got, want):
+    np.testing.assert_array_equal(got[0], want[0])
+    np.testing.assert_array_equal(got[1], want[1])
+    assert got[2].tobytes() == want[2].tobytes()
+
+
+@pytest.mark.parametrize("n_o", [1, 2, 3, 6, 10, 14])
+def test_jw_molecular_bit_exact(dev, n_o):
+    h1, h2 = synth.molecular_spin_integrals(n_o, seed=1000 + n_o)
+    got = _jw_gpu(dev, h1, h2)
+    want = ojw.jw_hamiltonian(h1, h2)
+    _assert_same(got, want)
+    if n_o == 14:
+        assert len(got[2]) == 55_371
+
+
+def test_jw_hubbard_bit_exact(dev):
+    h1, h2 = synth.hubbard_spin_integrals(4, 4)
+    got = _jw_gpu(dev, h1, h2)
+    _assert_same(got, ojw.jw_hamiltonian(h1, h2))
+    assert len(got[2]) == 177
+
+
+def test_jw_general_tensors_thresholds_e0(dev):
+    rng = np.random.default_rng(7)
+    n = 6
+    h1 = rng.standard_normal((n, n)) * (rng.random((n, n)) < 0.7)
+    h2 = rng.standard_normal((n,) * 4) * (rng.random((n,) * 4) < 0.3)
+    for eps, drop in [(0.0, 0.0), (0.5, 0.0), (0.0, 1e-2), (0.0, -1.0)]:
+        _assert_same(_jw_gpu(dev, h1, h2, 1.25, eps, drop), ojw.jw_hamiltonian(h1, h2, 1.25, eps, drop))
+    _assert_same(_jw_gpu(dev, h1, None, -0.5), ojw.jw_hamiltonian(h1, np.zeros((n,) * 4), -0.5))
+
+
+def test_jw_multiword(dev):
+    # 70 spin-orbitals: masks span two words
+    n = 70
+    rng = np.random.default_rng(8)
+    h1 = np.zeros((n, n))
+    for _ in range(60):
+        p, q = rng.integers(0, n, 2)
+        h1[p, q] += rng.standard_normal()
+    h2 = np.zeros((n,) * 4)
+    for _ in range(40):
+        p, q, r, s = rng.integers(0, n, 4)
+        h2[p, q, r, s] += rng.standard_normal()
+    _assert_same(_jw_gpu(dev, h1, h2), ojw.jw_hamiltonian(h1, h2))

@@ -1,0 +1,252 @@
+"""GPU parity of the operator-state product and the fused energy.
+
+Tolerances: the FP64 path (complex128 storage, float64 accumulation) must
+match the oracle to 1e-12 in the relative 2-norm.  The complex64 path stores
+amplitudes in FP32 but accumulates in float64; it is compared with the oracle
+run on the same FP32-rounded input upcast to float64, so the only error left
+is the final rounding of each output amplitude to FP32 (relative 2^-24 ~
+6e-8 per component), bounded here by 1e-6.  Energies from the fused
+reduction never round the gathered H psi, so on identical inputs they agree
+with the oracle to float64 accumulation error (1e-10 relative bound)."""
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import apply as oapply
+from oracle import jw as ojw
+from oracle import pauli as opauli
+from oracle import space as ospace
+from tests.conftest import rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+def _api():
+    from paper_2606_28952_amd import api
+
+    return api
+
+
+def _gpu_op(dev, op):
+    """Letter-form oracle PauliSum -> canonical, grouped GPU operator."""
+    api = _api()
+    x, z = op.xz()
+    s = api.PauliSum.create(op.n_qubits, x.reshape(-1), z.reshape(-1), op.coeff)
+    s.canonicalize()
+    return s.group()
+
+
+def _random_op(n, m, seed, hermitian=False):
+    letters, _ = synth.random_pauli_strings(m, n, seed)
+    rng = np.random.default_rng(seed + 1)
+    c = rng.standard_normal(m) + (0 if hermitian else 1j * rng.standard_normal(m))
+    return opauli.PauliSum(n, letters, c.astype(np.complex128))
+
+
+def _run(dev, grouped, space, psi, dtype):
+    api = _api()
+    t = torch.from_numpy(psi.astype(dtype)).to(dev)
+    return api.apply_pauli_sum(grouped, space, t).cpu().numpy()
+
+
+@pytest.mark.parametrize("n,m", [(1, 2), (2, 5), (5, 40), (8, 120), (10, 300), (11, 50)])
+def test_full_space_random_operator(dev, n, m):
+    api = _api()
+    op = _random_op(n, m, seed=10 + n)
+    psi = synth.random_state(1 << n, seed=20 + n)
+    G = _gpu_op(dev, op)
+    sp = api.Space.full(n)
+    ref = oapply.apply_scatter(op, ospace.FullSpace(n), psi)
+    assert rel_err(_run(dev, G, sp, psi, np.complex128), ref) < 1e-12
+    psi32 = psi.astype(np.complex64)
+    ref32 = oapply.apply_scatter(op, ospace.FullSpace(n), psi32.astype(np.complex128))
+    assert rel_err(_run(dev, G, sp, psi32, np.complex64), ref32) < 1e-6
+
+
+def test_twelve_qubit_molecular_full_and_sector(dev):
+    api = _api()
+    h1, h2 = synth.molecular_spin_integrals(6, seed=1001)
+    H = api.jw_transform(torch.from_numpy(h1).to(dev), torch.from_numpy(h2).to(dev))
+    G = H.group()
+    op = ojw.jw_sum(h1, h2)
+    for space, ospace_, seed in [(api.Space.full(12), ospace.FullSpace(12), 1101),
+                                 (api.Space.sector(6, 3, 3), ospace.SectorSpace(6, 3, 3), 1102)]:
+        psi = synth.random_state(ospace_.dim, seed)
+        ref = oapply.apply_scatter(op, ospace_, psi)
+        out = _run(dev, G, space, psi, np.complex128)
+        assert rel_err(out, ref) < 1e-12
+        psi32 = psi.astype(np.complex64)
+        ref32 = oapply.apply_scatter(op, ospace_, psi32.astype(np.complex128))
+        assert rel_err(_run(dev, G, space, psi32, np.complex64), ref32) < 1e-6
+        e = api.expval(G, space, torch.from_numpy(psi).to(dev)).cpu().numpy()
+        e_ref = np.vdot(psi, ref)
+        assert abs(e[0] - e_ref.real) < 1e-12 * abs(e_ref) and abs(e[1]) < 1e-12 * abs(e_ref)
+        assert abs(e[2] - 1.0) < 1e-13
+        e32 = api.expval(G, space, torch.from_numpy(psi32).to(dev)).cpu().numpy()
+        e32_ref = np.vdot(psi32.astype(np.complex128), ref32)
+        assert abs(e32[0] - e32_ref.real) < 1e-10 * abs(e32_ref)
+
+
+@pytest.mark.parametrize("n_o,na,nb", [(1, 0, 1), (1, 1, 1), (3, 1, 2), (4, 0, 4), (5, 2, 3), (9, 4, 5),
+                                       (11, 5, 5), (12, 6, 6), (13, 6, 6)])
+def test_sector_projection_random_operator(dev, n_o, na, nb):
+    """Non-conserving random operators: the sector result is P H P psi.  The
+    operators carry many strings with even X popcounts per spin so that the
+    sector sees nonzero coupling; beta dimensions span 1 to 1716 columns
+    (several lanes per thread, ragged tails)."""
+    api = _api()
+    n = 2 * n_o
+    rng = np.random.default_rng(n_o * 31 + na)
+    m = 400
+    letters, _ = synth.random_pauli_strings(m, n, seed=n_o + 7)
+    # make ~70% of the strings sector-compatible: pair up X/Y flips within each spin
+    for k in range(m):
+        if rng.random() < 0.7:
+            for half in (0, 1):
+                cols = np.arange(half * n_o, (half + 1) * n_o)
+                flips = cols[(letters[k, cols] == 1) | (letters[k, cols] == 2)]
+                if len(flips) % 2 == 1:
+                    letters[k, flips[0]] = 3
+    coeff = rng.standard_normal(m) + 1j * rng.standard_normal(m)
+    op = opauli.PauliSum(n, letters, coeff)
+    osp = ospace.SectorSpace(n_o, na, nb)
+    G = _gpu_op(dev, op)
+    sp = api.Space.sector(n_o, na, nb)
+    psi = synth.random_state(osp.dim, seed=n_o + 100)
+    if osp.dim <= 200_000:
+        ref = oapply.apply_scatter(op, osp, psi)
+        assert rel_err(_run(dev, G, sp, psi, np.complex128), ref) < 1e-12
+    else:
+        sel = np.random.default_rng(1).integers(0, osp.dim, 300)
+        got = _run(dev, G, sp, psi, np.complex128)[sel]
+        ref = oapply.apply_targets(op, osp, psi, sel)
+        assert rel_err(got, ref) < 1e-12
+
+
+def test_twenty_qubit_molecular_sector(dev):
+    api = _api()
+    h1, h2 = synth.molecular_spin_integrals(10, seed=4)
+    H = api.jw_transform(torch.from_numpy(h1).to(dev), torch.from_numpy(h2).to(dev))
+    G = H.group()
+    op = ojw.jw_sum(h1, h2)
+    osp = ospace.SectorSpace(10, 5, 5)
+    psi = synth.random_state(osp.dim, seed=5)
+    ref = oapply.apply_scatter(op, osp, psi)
+    sp = api.Space.sector(10, 5, 5)
+    out = _run(dev, G, sp, psi, np.complex128)
+    assert rel_err(out, ref) < 1e-12
+    # a second spin sector of the same operator
+    osp2 = ospace.SectorSpace(10, 4, 6)
+    psi2 = synth.random_state(osp2.dim, seed=6)
+    assert rel_err(_run(dev, G, api.Space.sector(10, 4, 6), psi2, np.complex128),
+                   oapply.apply_scatter(op, osp2, psi2)) < 1e-12
+
+
+def test_deterministic_and_edge_operators(dev):
+    api = _api()
+    h1, h2 = synth.molecular_spin_integrals(5, seed=9)
+    G = api.jw_transform(torch.from_numpy(h1).to(dev), torch.from_numpy(h2).to(dev)).group()
+    sp = api.Space.sector(5, 2, 3)
+    psi = torch.from_numpy(synth.random_state(sp.dim, 3)).to(dev)
+    a = api.apply_pauli_sum(G, sp, psi)
+    b = api.apply_pauli_sum(G, sp, psi)
+    assert torch.equal(a.view(torch.float64), b.view(torch.float64))
+    # empty operator: zero output
+    empty = api.PauliSum.create(10, np.zeros(0, np.uint64), np.zeros(0, np.uint64), np.zeros(0, np.complex128))
+    empty.canonicalize()
+    Ge = empty.group()
+    out = api.apply_pauli_sum(Ge, sp, psi)
+    assert torch.count_nonzero(out) == 0
+    out_full = api.apply_pauli_sum(Ge, api.Space.full(10), torch.ones(1024, dtype=torch.complex64, device=dev))
+    assert torch.count_nonzero(out_full) == 0
+    # identity times a complex constant
+    ident = api.PauliSum.create(10, np.zeros(1, np.uint64), np.zeros(1, np.uint64), np.array([0.5 - 2j]))
+    ident.canonicalize()
+    out = api.apply_pauli_sum(ident.group(), sp, psi)
+    assert torch.allclose(out, (0.5 - 2j) * psi, rtol=0, atol=1e-15)
+
+
+def test_argument_errors(dev):
+    api = _api()
+    from paper_2606_28952_amd._abi import PbsError
+
+    h1, h2 = synth.molecular_spin_integrals(3, seed=1)
+    G = api.jw_transform(torch.from_numpy(h1).to(dev), torch.from_numpy(h2).to(dev)).group()
+    sp = api.Space.sector(3, 1, 1)
+    psi = torch.zeros(sp.dim, dtype=torch.complex128, device=dev)
+    with pytest.raises(PbsError, match="overlaps"):
+        api.apply_pauli_sum(G, sp, psi, out=psi)
+    with pytest.raises(PbsError, match="qubits"):
+        api.apply_pauli_sum(G, api.Space.full(8), torch.zeros(256, dtype=torch.complex128, device=dev))
+    with pytest.raises(PbsError, match="workspace"):
+        work = torch.zeros(1, dtype=torch.float64, device=dev)
+        api.expval(G, sp, psi, work=work)
+
+
+def _sampled_targets(rng, dim, k, extra=()):
+    sel = set(int(v) for v in rng.integers(0, dim, k))
+    sel.update(int(v) for v in extra)
+    return np.array(sorted(sel), dtype=np.int64)
+
+
+def test_28_qubit_sector_sampled(dev):
+    """Full-size molecular workload: n_orb = 14, (7, 7) sector, D = 11,778,624,
+    in the launch configuration the benchmark uses; sampled outputs against
+    the oracle's one-by-one targets, plus Hermiticity and the energy."""
+    api = _api()
+    h1, h2 = synth.molecular_spin_integrals(14, seed=2001)
+    H = api.jw_transform(torch.from_numpy(h1).to(dev), torch.from_numpy(h2).to(dev))
+    G = H.group()
+    sp = api.Space.sector(14, 7, 7)
+    osp = ospace.SectorSpace(14, 7, 7)
+    assert sp.dim == 11_778_624
+    op = ojw.jw_sum(h1, h2)
+    psi = synth.random_state(sp.dim, seed=2101)
+    rng = np.random.default_rng(3)
+    sel = _sampled_targets(rng, sp.dim, 48, extra=[0, sp.dim - 1, 3431, 3432])
+    ref = oapply.apply_targets(op, osp, psi, sel)
+    tpsi = torch.from_numpy(psi).to(dev)
+    out = api.apply_pauli_sum(G, sp, tpsi)
+    assert rel_err(out[torch.from_numpy(sel).to(dev)].cpu().numpy(), ref) < 1e-12
+    psi32 = psi.astype(np.complex64)
+    ref32 = oapply.apply_targets(op, osp, psi32, sel)
+    t32 = torch.from_numpy(psi32).to(dev)
+    out32 = api.apply_pauli_sum(G, sp, t32)
+    assert rel_err(out32[torch.from_numpy(sel).to(dev)].cpu().numpy(), ref32) < 1e-6
+    # whole-vector properties: Hermiticity and the fused energy
+    phi = torch.from_numpy(synth.random_state(sp.dim, seed=2102)).to(dev)
+    hphi = api.apply_pauli_sum(G, sp, phi)
+    lhs = torch.vdot(phi, out).item()
+    rhs = torch.vdot(tpsi, hphi).item().conjugate()
+    assert abs(lhs - rhs) < 1e-11 * max(1.0, abs(lhs))
+    e = api.expval(G, sp, tpsi).cpu().numpy()
+    e_dot = torch.vdot(tpsi, out).item()
+    assert abs(e[0] - e_dot.real) < 1e-11 * abs(e_dot) and abs(e[1]) < 1e-11 * abs(e_dot)
+    e32 = api.expval(G, sp, t32).cpu().numpy()
+    h32 = api.apply_pauli_sum(G, sp, t32.to(torch.complex128))
+    e32_dot = torch.vdot(t32.to(torch.complex128), h32).item()
+    assert abs(e32[0] - e32_dot.real) < 1e-11 * abs(e32_dot)
+
+
+def test_32_qubit_hubbard_sampled(dev):
+    """4x4 periodic Hubbard model, (8, 8) sector, D = 165,636,900 (complex64
+    1.33 GB); sampled outputs against the oracle."""
+    api = _api()
+    h1, h2 = synth.hubbard_spin_integrals(4, 4)
+    G = api.jw_transform(torch.from_numpy(h1).to(dev), torch.from_numpy(h2).to(dev)).group()
+    sp = api.Space.sector(16, 8, 8)
+    osp = ospace.SectorSpace(16, 8, 8)
+    assert sp.dim == 165_636_900
+    op = ojw.jw_sum(h1, h2)
+    psi32 = synth.random_state(sp.dim, seed=4101).astype(np.complex64)
+    sel = _sampled_targets(np.random.default_rng(4), sp.dim, 64, extra=[0, sp.dim - 1, 12869, 12870])
+    ref = oapply.apply_targets(op, osp, psi32, sel)
+    t32 = torch.from_numpy(psi32).to(dev)
+    out = api.apply_pauli_sum(G, sp, t32)
+    assert rel_err(out[torch.from_numpy(sel).to(dev)].cpu().numpy(), ref) < 1e-6
+    del out
+    t64 = t32.to(torch.complex128)
+    out64 = api.apply_pauli_sum(G, sp, t64)
+    assert rel_err(out64[torch.from_numpy(sel).to(dev)].cpu().numpy(), ref) < 1e-12
