@@ -1,0 +1,270 @@
+"""Benchmark of the Pauli-sum operator-state path on one MI355X.
+
+One step is one pass of the whole path on the 28-qubit molecular workload
+(14 spatial orbitals, (7, 7) spin sector, D = 11,778,624): Jordan-Wigner
+construction from device-resident integrals (string products + canonical
+reduction), grouping by X-mask with the sector tables, the sector's rank
+tables, H|psi> with complex64 storage and float64 accumulation, and the fused
+float64 energy <psi|H|psi>.  The metric is amplitude*terms per second,
+D * M / t_step with M the number of canonical Pauli strings.
+
+The dominant kernel (the sector apply) is timed with HIP events on the
+stream it runs on; its roofline fraction uses the algorithmic gather bytes
+per launch, D * b * (1 + G_conn) with b = 8 bytes per complex64 amplitude and
+G_conn the connected groups per target.  The complex128 (FP64 plain) apply
+is timed beside it, and the oracle is timed on a bounded sample of the same
+workload on the host cores.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+"""
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+WORKLOADS = {
+    # name: (kind, params)
+    "molecular-28q-sector": ("molecular", dict(n_orb=14, n_alpha=7, n_beta=7, h_seed=2001, psi_seed=2101)),
+    "molecular-12q-sector": ("molecular", dict(n_orb=6, n_alpha=3, n_beta=3, h_seed=1001, psi_seed=1102)),
+    "hubbard-32q-sector": ("hubbard", dict(rows=4, cols=4, n_alpha=8, n_beta=8, psi_seed=4101)),
+}
+
+
+def _source_hash():
+    h = hashlib.sha256()
+    for f in ("apply.hip", "handles.h"):
+        with open(os.path.join(ROOT, "paper_2606_28952_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _connected_groups(x_groups, n_orb, n_alpha, n_beta):
+    """Average number of groups whose source lies in the sector, per target:
+    a group with masks (X_alpha, X_beta) connects a target iff each half flips
+    as many occupied as empty orbitals; counted exactly by combinatorics."""
+    from math import comb
+
+    mask = (1 << n_orb) - 1
+    total = 0
+    da, db = comb(n_orb, n_alpha), comb(n_orb, n_beta)
+    for x in x_groups.tolist():
+        xa, xb = x & mask, x >> n_orb
+        pa, pb = bin(xa).count("1"), bin(xb).count("1")
+        if pa % 2 or pb % 2:
+            continue
+        # targets whose alpha string has exactly pa/2 ones inside xa
+        ca = comb(pa, pa // 2) * comb(n_orb - pa, n_alpha - pa // 2)
+        cb = comb(pb, pb // 2) * comb(n_orb - pb, n_beta - pb // 2)
+        total += ca * cb
+    return total / (da * db)
+
+
+def _traffic(kernel_tag):
+    """HBM bytes per launch from committed rocprofv3 counter summaries, or
+    None when absent or taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", f"{kernel_tag}_counters.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("source_hash") != _source_hash():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(h1, h2, n_orb, n_alpha, n_beta, psi, budget_s=20.0):
+    """Oracle (plain NumPy, float64, scatter order) on the first K canonical
+    terms over every source configuration; K grows until ~budget_s of work."""
+    from oracle import apply as oapply
+    from oracle import jw as ojw
+    from oracle import space as ospace
+    from oracle.pauli import PauliSum
+
+    op = ojw.jw_sum(h1, h2)
+    osp = ospace.SectorSpace(n_orb, n_alpha, n_beta)
+    psi = np.asarray(psi, dtype=np.complex128)
+    done_terms = 0
+    elapsed = 0.0
+    k = 1
+    while elapsed < budget_s and done_terms < op.n_terms:
+        sub = PauliSum(op.n_qubits, op.letters[done_terms:done_terms + k], op.coeff[done_terms:done_terms + k])
+        t0 = time.perf_counter()
+        oapply.apply_scatter(sub, osp, psi)
+        elapsed += time.perf_counter() - t0
+        done_terms += sub.n_terms
+        k = min(2 * k, 64)
+    rate = osp.dim * done_terms / elapsed
+    return {"value": rate, "unit": "amplitude*terms/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {done_terms} of {op.n_terms} canonical strings applied to all {osp.dim} "
+                      f"sector configurations (NumPy float64 scatter), {elapsed:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="molecular-28q-sector", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--apply-only", type=int, default=0,
+                    help="profiling mode: run only N sector applies (complex64) after setup, print nothing else")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); this path has no multi-GPU mode.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import synth
+    from paper_2606_28952_amd import api
+
+    kind, prm = WORKLOADS[args.workload]
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    if kind == "molecular":
+        n_orb = prm["n_orb"]
+        h1, h2 = synth.molecular_spin_integrals(n_orb, prm["h_seed"])
+    else:
+        n_orb = prm["rows"] * prm["cols"]
+        h1, h2 = synth.hubbard_spin_integrals(prm["rows"], prm["cols"])
+    na, nb = prm["n_alpha"], prm["n_beta"]
+    h1_d = torch.from_numpy(h1).to(dev)
+    h2_d = torch.from_numpy(h2).to(dev)
+    psi64_np = synth.random_state(_dim(n_orb, na, nb), prm["psi_seed"])
+    psi32 = torch.from_numpy(psi64_np.astype(np.complex64)).to(dev)
+    out32 = torch.empty_like(psi32)
+    res = torch.empty(3, dtype=torch.float64, device=dev)
+
+    def build():
+        H = api.jw_transform(h1_d, h2_d)
+        G = H.group()
+        sp = api.Space.sector(n_orb, na, nb)
+        return H, G, sp
+
+    if args.apply_only:
+        _, G, sp = build()
+        for _ in range(args.apply_only):
+            api.apply_pauli_sum(G, sp, psi32, out=out32)
+        torch.cuda.synchronize()
+        print(f"apply-only done: {args.apply_only} launches")
+        return
+
+    H, G, sp = build()
+    work = torch.empty(max(1, sp.workspace_bytes() // 8), dtype=torch.float64, device=dev)
+    D = sp.dim
+    M = H.n_terms
+    xg = G.read()[0]
+    g_conn = _connected_groups(xg, n_orb, na, nb)
+    del H, G, sp
+
+    def step(ev0=None, ev1=None):
+        H, G, sp = build()
+        if ev0 is not None:
+            ev0.record()
+        api.apply_pauli_sum(G, sp, psi32, out=out32)
+        if ev1 is not None:
+            ev1.record()
+        api.expval(G, sp, psi32, work=work, result=res)
+        return H, G, sp
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(*evs[k])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    apply_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    energy = res.cpu().numpy()
+
+    # FP64 plain (complex128 storage) vs complex64 storage, apply kernel only
+    _, G, sp = build()
+    psi64 = torch.from_numpy(psi64_np).to(dev)
+    out64 = torch.empty_like(psi64)
+
+    def time_apply(psi, out, reps=10):
+        api.apply_pauli_sum(G, sp, psi, out=out)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record()
+        for _ in range(reps):
+            api.apply_pauli_sum(G, sp, psi, out=out)
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    c64_ms = time_apply(psi32, out32)
+    c128_ms = time_apply(psi64, out64)
+    # storage error of the complex64 path: against complex128 on the same
+    # FP32-rounded input (kernel error) and against the FP64 state
+    ref_same = api.apply_pauli_sum(G, sp, psi32.to(torch.complex128))
+    err_kernel = (torch.linalg.vector_norm(out32.to(torch.complex128) - ref_same) /
+                  torch.linalg.vector_norm(ref_same)).item()
+    err_state = (torch.linalg.vector_norm(out32.to(torch.complex128) - out64) /
+                 torch.linalg.vector_norm(out64)).item()
+    e64 = api.expval(G, sp, psi64).cpu().numpy()
+    e32 = api.expval(G, sp, psi32).cpu().numpy()
+
+    bytes_per_launch = D * 8 * (1.0 + g_conn)
+    achieved = bytes_per_launch / (apply_ms * 1e-3) / 1e9
+    kernel_tag = f"apply_sector_c64_{args.workload}"
+    traffic = _traffic(kernel_tag)
+    line = {
+        "metric": "H|psi> amplitude*terms/s (complex64 storage, float64 accumulation)",
+        "value": D * M / (ms_step * 1e-3),
+        "unit": "amplitude*terms/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded Gaussian integrals and states)",
+        "config": {"workload": args.workload, "n_orb": n_orb, "n_alpha": na, "n_beta": nb, "dim": D,
+                   "n_strings": M, "groups_connected_per_target": round(g_conn, 3), "storage": "complex64",
+                   "step": "jw_transform+group_by_xmask+space_sector+apply_pauli_sum+expval"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
+        "apply_ms_c64": c64_ms,
+        "apply_ms_c128": c128_ms,
+        "apply_rate_c64": D * M / (c64_ms * 1e-3),
+        "apply_rate_c128": D * M / (c128_ms * 1e-3),
+        "speedup_c64_vs_c128": c128_ms / c64_ms,
+        "rel_err_c64_vs_c128_same_input": err_kernel,
+        "rel_err_c64_vs_fp64_state": err_state,
+        "energy_c64": float(e32[0]),
+        "energy_c128": float(e64[0]),
+        "energy_diff_c64_c128": float(e32[0] - e64[0]),
+        "energy_step": float(energy[0]),
+        "kernel_source": _source_hash(),
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(h1, h2, n_orb, na, nb, psi64_np)
+    print(json.dumps(line))
+
+
+def _dim(n_orb, na, nb):
+    from math import comb
+
+    return comb(n_orb, na) * comb(n_orb, nb)
+
+
+if __name__ == "__main__":
+    main()
