@@ -216,6 +216,29 @@ pbs_status pbs_expval_workspace_bytes(const pbs_space* sp, uint64_t* bytes);
 pbs_status pbs_expval(const pbs_grouped* h, const pbs_space* sp, pbs_dtype dt, const void* psi, double* result,
                       void* work, uint64_t work_bytes, void* stream);
 
+/* ------------------------------------------------------------------ propagation */
+
+/* Device workspace bytes for pbs_krylov_step with m Krylov vectors (1..16):
+ * m + 1 state vectors of type dt plus reduction scratch. */
+pbs_status pbs_krylov_workspace_bytes(const pbs_space* sp, pbs_dtype dt, uint32_t m, uint64_t* bytes);
+
+/* One real-time step psi <- exp(-i H dt_step) psi (Section 2.1,
+ * Eq. real_time_evolution) by short-iterative Lanczos: up to m Krylov vectors
+ * built with pbs_apply_pauli_sum's kernels, two classical Gram-Schmidt passes
+ * per vector with float64 inner products, exp(-i T dt) e_1 of the tridiagonal
+ * T from its eigen-decomposition, psi rebuilt as |psi| V exp(-i T dt) e_1.
+ * The basis stops early when the new vector's norm falls below 1e-14 times
+ * the largest entry of T (the Krylov space is then invariant and the step is
+ * exact).  H must be Hermitian.
+ *  psi    device, D complex values of type dt, updated in place.
+ *  work   device workspace of at least pbs_krylov_workspace_bytes; must not
+ *         overlap psi.
+ *  info   host, 4 doubles: |psi| before the step, <H> of the normalised input
+ *         state, number of Krylov vectors used, norm of the last residual.
+ * Synchronizes the stream (the tridiagonal matrix is read back). */
+pbs_status pbs_krylov_step(const pbs_grouped* h, const pbs_space* sp, pbs_dtype dt, void* psi, double dt_step,
+                           uint32_t m, void* work, uint64_t work_bytes, double* info, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -17,7 +17,7 @@ from ._abi import PBS_C64, PBS_C128, call
 
 __all__ = [
     "PauliSum", "Grouped", "Space", "pauli_mul", "jw_transform", "apply_pauli_sum", "expval",
-    "words_for", "PBS_C64", "PBS_C128",
+    "words_for", "PBS_C64", "PBS_C128", "KrylovPropagator",
 ]
 
 
@@ -243,3 +243,24 @@ def expval(grouped, space, psi, work=None, result=None):
     call("pbs_expval", grouped._h, space._h, _dtype_code(psi), _ptr(psi), _ptr(result), _ptr(work),
          work.numel() * 8, _stream())
     return result
+
+
+class KrylovPropagator:
+    """psi <- exp(-i H dt) psi by short-iterative Lanczos with m vectors; owns
+    its device workspace (allocated once, reused by every step)."""
+
+    def __init__(self, grouped, space, dtype=torch.complex64, m=12, device="cuda"):
+        self.grouped, self.space, self.m = grouped, space, m
+        self.code = PBS_C128 if dtype == torch.complex128 else PBS_C64
+        nb = c_uint64()
+        call("pbs_krylov_workspace_bytes", space._h, self.code, m, byref(nb))
+        self.work = torch.empty(nb.value, dtype=torch.uint8, device=device)
+        self.info = np.zeros(4, np.float64)
+
+    def step(self, psi, dt):
+        """Advances psi in place; returns (norm before, <H>, vectors used, last residual)."""
+        if _dtype_code(psi) != self.code:
+            raise TypeError("state dtype differs from the propagator's")
+        call("pbs_krylov_step", self.grouped._h, self.space._h, self.code, _ptr(psi), float(dt), self.m,
+             _ptr(self.work), self.work.numel(), _ptr(self.info), _stream())
+        return tuple(float(v) for v in self.info)

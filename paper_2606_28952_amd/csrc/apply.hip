@@ -11,12 +11,23 @@
 // coefficients, phase sums, accumulators, reductions -- is float64.
 //
 // Sector kernel layout: a workgroup owns one target alpha string t_a (one
-// row of the alpha-major state) and a range of beta columns; each lane holds
-// NT targets of that row.  Groups are visited class by class (classes share
-// X_alpha), so the source row s_a = t_a ^ X_alpha, its validity and its rank
-// are uniform across the workgroup, and so are the alpha parities of all
-// terms: each unique beta Z-mask's coefficient is folded over its terms'
-// alpha parities once per group visit and applied to NT targets.
+// row of the alpha-major state) and kSB consecutive beta columns, one target
+// per lane.  Groups are visited class by class (a class shares X_alpha), so
+// the source row s_a = t_a ^ X_alpha, its validity and its rank are uniform
+// across the workgroup, and so are the alpha parities of every term: the
+// coefficients of each unique beta Z-mask are folded over their terms' alpha
+// parities cooperatively into LDS once per class.  Per class:
+//  * the group with X_beta = 0 gathers from the lane's own column;
+//  * groups whose X_beta flips two orbitals are visited by enumerating the
+//    lane's valid pair moves (occupied -> empty, the same count for every
+//    target of a sector), cached in registers with their source ranks, and a
+//    per-class pair map; invalid moves are never visited;
+//  * other groups are scanned with a per-lane validity test;
+//  * consecutive classes holding only an X_beta = 0 group share one fold;
+//  * the source row is staged in LDS as float64 when it fits.
+// Parities are evaluated against the target strings each lane holds; the
+// constant (-1)^popcount(z & X) factors were moved into the coefficients
+// when the tables were built.
 #include "handles.h"
 
 namespace pbs {
@@ -52,8 +63,9 @@ __device__ inline double signed_by(double v, uint32_t p) {
   return __hiloint2double(__double2hiint(v) ^ static_cast<int>((p & 1u) << 31), __double2loint(v));
 }
 
+template <int B>
 __device__ inline void block_reduce3_store(double a, double b, double c, double* dst) {
-  __shared__ double red[3][kBlock / 64];
+  __shared__ double red[3][B / 64];
   for (int d = 32; d > 0; d >>= 1) {
     a += __shfl_xor(a, d, 64);
     b += __shfl_xor(b, d, 64);
@@ -68,7 +80,7 @@ __device__ inline void block_reduce3_store(double a, double b, double c, double*
   __syncthreads();
   if (threadIdx.x == 0) {
     double s0 = 0, s1 = 0, s2 = 0;
-    for (int w = 0; w < kBlock / 64; ++w) {
+    for (int w = 0; w < B / 64; ++w) {
       s0 += red[0][w];
       s1 += red[1][w];
       s2 += red[2][w];
@@ -115,20 +127,32 @@ __global__ __launch_bounds__(kBlock) void k_apply_full(uint64_t dim, uint32_t n_
       Amp<T>::store(out, t, acc_r, acc_i);
     }
   }
-  if (EXPVAL) block_reduce3_store(e_re, e_im, nrm, partial + 3ull * blockIdx.x);
+  if (EXPVAL) block_reduce3_store<kBlock>(e_re, e_im, nrm, partial + 3ull * blockIdx.x);
 }
 
 // ---------------------------------------------------------------- spin sector
+constexpr int kSB = 512;              // lanes per sector workgroup = beta columns per workgroup
+constexpr int kMaxMoves = 64;         // pair moves cached per lane
+constexpr uint32_t kFCap = 1536;      // folded uniques held in LDS at once
+constexpr uint32_t kRowCapBytes = 64u * 1024u;
+constexpr uint32_t kSimpleCap = 64;   // uniques of a batchable single-group class
+
 struct SectorArgs {
   uint32_t n_orb, n_alpha, n_beta, n_chunks;
-  uint64_t dim_beta;
-  uint32_t cols;  // beta columns per workgroup
-  uint32_t n_class;
+  uint32_t dim_beta;
+  uint32_t n_class, n_pairs, n_moves;
+  uint32_t rank_lds, row_lds, enum_ok;
+  uint32_t off_rank, off_row, off_f, off_fz, off_pu;  // LDS byte offsets
   const uint32_t* str_a;
   const uint32_t* str_b;
   const uint32_t* rank_tab;
   const uint32_t* cls_xa;
   const uint32_t* cls_g0;
+  const int32_t* cls_zg;
+  const int32_t* cls_p0;
+  const int32_t* cls_p1;
+  const int32_t* cls_pm;
+  const int32_t* pmap;
   const uint32_t* pg_xb;
   const uint32_t* pg_u0;
   const uint32_t* u_zb;
@@ -147,99 +171,289 @@ __device__ inline uint32_t rank_of(uint32_t s, uint32_t n_orb, uint32_t n_chunks
   return r;
 }
 
-constexpr uint32_t kRankLdsEntries = 2 * 17 * 256;  // n_orb <= 16
+// Folds the alpha parities of uniques [ua, ub) for target alpha string ta:
+// F[u - ua] = sum over the unique's terms of C_t (-1)^popcount(za_t & ta).
+__device__ inline void fold_uniques(const SectorArgs& P, uint32_t ua, uint32_t ub, uint32_t ta, double2* F,
+                                    uint32_t* Fz) {
+  for (uint32_t u = ua + threadIdx.x; u < ub; u += kSB) {
+    double fr = 0.0, fi = 0.0;
+    const uint32_t t1 = P.u_t0[u + 1];
+    for (uint32_t t = P.u_t0[u]; t < t1; ++t) {
+      const uint32_t par = __popc(P.pt_za[t] & ta);
+      const double2 c = P.pt_c[t];
+      fr += signed_by(c.x, par);
+      fi += signed_by(c.y, par);
+    }
+    F[u - ua] = make_double2(fr, fi);
+    Fz[u - ua] = P.u_zb[u];
+  }
+}
 
-template <class T, int NT, bool EXPVAL, bool RANK_LDS>
-__global__ __launch_bounds__(kBlock) void k_apply_sector(SectorArgs P, const T* __restrict__ psi, T* __restrict__ out,
-                                                         double* __restrict__ partial) {
-  __shared__ uint32_t s_rank[RANK_LDS ? kRankLdsEntries : 1];
+// Phase sum of cnt folded uniques starting at LDS slot b, against beta target tb.
+__device__ inline void phase_sum_lds(const double2* F, const uint32_t* Fz, uint32_t b, uint32_t cnt, uint32_t tb,
+                                     double& fr, double& fi) {
+  for (uint32_t i = 0; i < cnt; ++i) {
+    const uint32_t par = __popc(Fz[b + i] & tb);
+    const double2 f = F[b + i];
+    fr += signed_by(f.x, par);
+    fi += signed_by(f.y, par);
+  }
+}
+
+// Phase sum of group g straight from the term tables (groups too large for LDS).
+__device__ inline void phase_sum_direct(const SectorArgs& P, uint32_t g, uint32_t ta, uint32_t tb, double& fr,
+                                        double& fi) {
+  const uint32_t u1 = P.pg_u0[g + 1];
+  for (uint32_t u = P.pg_u0[g]; u < u1; ++u) {
+    double gr = 0.0, gi = 0.0;
+    const uint32_t t1 = P.u_t0[u + 1];
+    for (uint32_t t = P.u_t0[u]; t < t1; ++t) {
+      const uint32_t par = __popc(P.pt_za[t] & ta);
+      const double2 c = P.pt_c[t];
+      gr += signed_by(c.x, par);
+      gi += signed_by(c.y, par);
+    }
+    const uint32_t par = __popc(P.u_zb[u] & tb);
+    fr += signed_by(gr, par);
+    fi += signed_by(gi, par);
+  }
+}
+
+__device__ inline void cmul_acc(double fr, double fi, double ar, double ai, double& acc_r, double& acc_i) {
+  acc_r = fma(ar, fr, fma(-ai, fi, acc_r));
+  acc_i = fma(ar, fi, fma(ai, fr, acc_i));
+}
+
+template <class T>
+__device__ inline void load_amp(const double2* srow, bool staged, const T* psi, uint64_t rowoff, uint32_t j,
+                                double& ar, double& ai) {
+  if (staged) {
+    const double2 v = srow[j];
+    ar = v.x;
+    ai = v.y;
+  } else {
+    Amp<T>::load(psi, rowoff + j, ar, ai);
+  }
+}
+
+__device__ inline bool class_is_simple(const SectorArgs& P, uint32_t c) {
+  const uint32_t g0 = P.cls_g0[c];
+  return P.cls_zg[c] >= 0 && P.cls_g0[c + 1] == g0 + 1 && P.pg_u0[g0 + 1] - P.pg_u0[g0] <= kSimpleCap;
+}
+
+// One workgroup: target alpha string ia (one row of the state), kSB beta
+// columns.  See the file header for the scheme.
+template <class T, bool EXPVAL>
+__global__ __launch_bounds__(kSB) void k_apply_sector(SectorArgs P, const T* __restrict__ psi, T* __restrict__ out,
+                                                      double* __restrict__ partial) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  uint32_t* s_rank = reinterpret_cast<uint32_t*>(smem + P.off_rank);
+  double2* s_row = reinterpret_cast<double2*>(smem + P.off_row);
+  double2* s_F = reinterpret_cast<double2*>(smem + P.off_f);
+  uint32_t* s_Fz = reinterpret_cast<uint32_t*>(smem + P.off_fz);
+  uint32_t* s_pu = reinterpret_cast<uint32_t*>(smem + P.off_pu);
+
   const uint32_t* rtab = P.rank_tab;
-  if (RANK_LDS) {
+  if (P.rank_lds) {
     const uint32_t n = P.n_chunks * (P.n_orb + 1) * 256;
-    for (uint32_t i = threadIdx.x; i < n; i += kBlock) s_rank[i] = P.rank_tab[i];
-    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < n; i += kSB) s_rank[i] = P.rank_tab[i];
     rtab = s_rank;
   }
-  const uint64_t db = P.dim_beta;
+  __syncthreads();
+
+  const uint32_t db = P.dim_beta;
   const uint64_t ia = blockIdx.x;
-  const uint32_t col0 = blockIdx.y * P.cols;
-  const uint32_t col1 = (col0 + P.cols < db) ? col0 + P.cols : static_cast<uint32_t>(db);
+  const uint32_t col = blockIdx.y * kSB + threadIdx.x;
+  const bool live = col < db;
   const uint32_t ta = P.str_a[ia];
+  const uint32_t tb = P.str_b[live ? col : 0];
+  const uint32_t n_orb = P.n_orb;
 
-  uint32_t tb[NT];
-  bool live[NT];
-  double acc_r[NT], acc_i[NT];
+  // Pair moves of this lane's target: occupied p -> empty q, source rank and
+  // pair index packed as jb | pair << 16 (enumerated occupied-major).
+  uint32_t mv[kMaxMoves];
+  if (P.enum_ok) {
+    const uint32_t full = (n_orb == 32) ? 0xffffffffu : ((1u << n_orb) - 1u);
+    const uint32_t emp = ~tb & full;
+    const uint32_t ne = n_orb - P.n_beta;
+    uint32_t pm_occ = tb, pm_emp = emp, j = 0;
+    uint32_t p = __ffs(pm_occ) - 1;
 #pragma unroll
-  for (int j = 0; j < NT; ++j) {
-    const uint32_t c = col0 + threadIdx.x + j * kBlock;
-    live[j] = c < col1;
-    tb[j] = live[j] ? P.str_b[c] : 0u;
-    acc_r[j] = 0.0;
-    acc_i[j] = 0.0;
-  }
-
-  for (uint32_t cl = 0; cl < P.n_class; ++cl) {
-    const uint32_t sa = ta ^ P.cls_xa[cl];
-    if (static_cast<uint32_t>(__popc(sa)) != P.n_alpha) continue;  // uniform
-    const uint64_t row = static_cast<uint64_t>(rank_of(sa, P.n_orb, P.n_chunks, rtab)) * db;
-    const uint32_t g1 = P.cls_g0[cl + 1];
-    for (uint32_t g = P.cls_g0[cl]; g < g1; ++g) {
-      const uint32_t xb = P.pg_xb[g];
-      uint32_t sb[NT];
-      double fr[NT], fi[NT];
-#pragma unroll
-      for (int j = 0; j < NT; ++j) {
-        sb[j] = tb[j] ^ xb;
-        fr[j] = 0.0;
-        fi[j] = 0.0;
-      }
-      const uint32_t u1 = P.pg_u0[g + 1];
-      for (uint32_t u = P.pg_u0[g]; u < u1; ++u) {
-        double Fr = 0.0, Fi = 0.0;
-        const uint32_t t1 = P.u_t0[u + 1];
-        for (uint32_t t = P.u_t0[u]; t < t1; ++t) {
-          const uint32_t par = __popc(P.pt_za[t] & sa);
-          const double2 c = P.pt_c[t];
-          Fr += signed_by(c.x, par);
-          Fi += signed_by(c.y, par);
-        }
-        const uint32_t zb = P.u_zb[u];
-#pragma unroll
-        for (int j = 0; j < NT; ++j) {
-          const uint32_t par = __popc(zb & sb[j]);
-          fr[j] += signed_by(Fr, par);
-          fi[j] += signed_by(Fi, par);
-        }
-      }
-#pragma unroll
-      for (int j = 0; j < NT; ++j) {
-        if (live[j] && static_cast<uint32_t>(__popc(sb[j])) == P.n_beta) {
-          const uint64_t src = row + rank_of(sb[j], P.n_orb, P.n_chunks, rtab);
-          double ar, ai;
-          Amp<T>::load(psi, src, ar, ai);
-          acc_r[j] = fma(ar, fr[j], fma(-ai, fi[j], acc_r[j]));
-          acc_i[j] = fma(ar, fi[j], fma(ai, fr[j], acc_i[j]));
+    for (int k = 0; k < kMaxMoves; ++k) {
+      mv[k] = 0;
+      if (static_cast<uint32_t>(k) < P.n_moves) {
+        const uint32_t q = __ffs(pm_emp) - 1;
+        pm_emp &= pm_emp - 1;
+        const uint32_t lo = p < q ? p : q, hi = p < q ? q : p;
+        const uint32_t pair = hi * (hi - 1) / 2 + lo;
+        const uint32_t s = tb ^ (1u << p) ^ (1u << q);
+        mv[k] = rank_of(s, n_orb, P.n_chunks, rtab) | (pair << 16);
+        if (++j == ne) {
+          j = 0;
+          pm_emp = emp;
+          pm_occ &= pm_occ - 1;
+          p = __ffs(pm_occ) - 1;
         }
       }
     }
+  }
+
+  double acc_r = 0.0, acc_i = 0.0;
+  uint32_t c = 0;
+  while (c < P.n_class) {
+    if (class_is_simple(P, c)) {
+      // batch of consecutive single-group classes: one cooperative fold
+      const uint32_t cb = c;
+      const uint32_t ua = P.pg_u0[P.cls_g0[c]];
+      uint32_t ce = c;
+      while (ce < P.n_class && class_is_simple(P, ce) && P.pg_u0[P.cls_g0[ce] + 1] - ua <= kFCap) ++ce;
+      const uint32_t ub = P.pg_u0[P.cls_g0[ce - 1] + 1];
+      __syncthreads();
+      fold_uniques(P, ua, ub, ta, s_F, s_Fz);
+      __syncthreads();
+      if (live) {
+        for (uint32_t cc = cb; cc < ce; ++cc) {
+          const uint32_t sa = ta ^ P.cls_xa[cc];
+          if (static_cast<uint32_t>(__popc(sa)) != P.n_alpha) continue;
+          const uint64_t rowoff = static_cast<uint64_t>(rank_of(sa, n_orb, P.n_chunks, rtab)) * db;
+          const uint32_t g = P.cls_g0[cc];
+          double fr = 0.0, fi = 0.0;
+          phase_sum_lds(s_F, s_Fz, P.pg_u0[g] - ua, P.pg_u0[g + 1] - P.pg_u0[g], tb, fr, fi);
+          double ar, ai;
+          Amp<T>::load(psi, rowoff + col, ar, ai);
+          cmul_acc(fr, fi, ar, ai, acc_r, acc_i);
+        }
+      }
+      c = ce;
+      continue;
+    }
+
+    const uint32_t sa = ta ^ P.cls_xa[c];
+    if (static_cast<uint32_t>(__popc(sa)) != P.n_alpha) {
+      ++c;
+      continue;
+    }
+    const uint64_t rowoff = static_cast<uint64_t>(rank_of(sa, n_orb, P.n_chunks, rtab)) * db;
+    const uint32_t g0 = P.cls_g0[c], g1 = P.cls_g0[c + 1];
+    const int32_t zg = P.cls_zg[c];
+    const uint32_t gz_end = zg >= 0 ? g0 + 1 : g0;
+    const int32_t pm = P.cls_pm[c];
+    const uint32_t p1 = static_cast<uint32_t>(P.cls_p1[c]);
+    const uint32_t ua = P.pg_u0[g0];
+    const bool penum = P.enum_ok && pm >= 0 && (P.pg_u0[p1] - ua) <= kFCap;
+    const uint32_t ub_a = penum ? P.pg_u0[p1] : P.pg_u0[gz_end];
+    const bool fold_a = ub_a > ua && ub_a - ua <= kFCap;
+    const bool stage = P.row_lds && gz_end < g1;
+
+    // phase A: X_beta = 0 group and, when enumerated, the pair groups
+    if (stage || fold_a) {
+      __syncthreads();
+      if (stage) {
+        for (uint32_t j = threadIdx.x; j < db; j += kSB) {
+          double ar, ai;
+          Amp<T>::load(psi, rowoff + j, ar, ai);
+          s_row[j] = make_double2(ar, ai);
+        }
+      }
+      if (fold_a) fold_uniques(P, ua, ub_a, ta, s_F, s_Fz);
+      if (penum) {
+        for (uint32_t q = threadIdx.x; q < P.n_pairs; q += kSB) {
+          const int32_t g = P.pmap[static_cast<uint64_t>(pm) * P.n_pairs + q];
+          s_pu[q] = g >= 0 ? ((P.pg_u0[g] - ua) | ((P.pg_u0[g + 1] - P.pg_u0[g]) << 16)) : 0u;
+        }
+      }
+      __syncthreads();
+    }
+    if (live) {
+      if (zg >= 0) {
+        double fr = 0.0, fi = 0.0;
+        if (fold_a)
+          phase_sum_lds(s_F, s_Fz, 0, P.pg_u0[zg + 1] - ua, tb, fr, fi);
+        else
+          phase_sum_direct(P, static_cast<uint32_t>(zg), ta, tb, fr, fi);
+        double ar, ai;
+        load_amp<T>(s_row, stage, psi, rowoff, col, ar, ai);
+        cmul_acc(fr, fi, ar, ai, acc_r, acc_i);
+      }
+      if (penum) {
+        uint32_t n_moves = P.n_moves;
+        asm volatile("" : "+s"(n_moves));  // per-class, so the move predicates are not hoisted either
+#pragma unroll
+        for (int k = 0; k < kMaxMoves; ++k) {
+          if (static_cast<uint32_t>(k) < n_moves) {
+            uint32_t e = mv[k];
+            // keep per-move address arithmetic inside the class loop (hoisting
+            // it would cost several registers per cached move)
+            asm volatile("" : "+v"(e));
+            const uint32_t w = s_pu[e >> 16];
+            const uint32_t cnt = w >> 16;
+            if (cnt) {
+              double fr = 0.0, fi = 0.0;
+              phase_sum_lds(s_F, s_Fz, w & 0xffffu, cnt, tb, fr, fi);
+              double ar, ai;
+              load_amp<T>(s_row, stage, psi, rowoff, e & 0xffffu, ar, ai);
+              cmul_acc(fr, fi, ar, ai, acc_r, acc_i);
+            }
+          }
+        }
+      }
+    }
+
+    // phase B: remaining groups, scanned in chunks whose uniques fit in LDS
+    uint32_t gs = penum ? p1 : gz_end;
+    while (gs < g1) {
+      const uint32_t us = P.pg_u0[gs];
+      uint32_t ge = gs;
+      while (ge < g1 && P.pg_u0[ge + 1] - us <= kFCap) ++ge;
+      if (ge == gs) {
+        if (live) {
+          const uint32_t xb = P.pg_xb[gs];
+          if (2u * __popc(tb & xb) == static_cast<uint32_t>(__popc(xb))) {
+            double fr = 0.0, fi = 0.0;
+            phase_sum_direct(P, gs, ta, tb, fr, fi);
+            double ar, ai;
+            load_amp<T>(s_row, stage, psi, rowoff, rank_of(tb ^ xb, n_orb, P.n_chunks, rtab), ar, ai);
+            cmul_acc(fr, fi, ar, ai, acc_r, acc_i);
+          }
+        }
+        ++gs;
+        continue;
+      }
+      __syncthreads();
+      fold_uniques(P, us, P.pg_u0[ge], ta, s_F, s_Fz);
+      __syncthreads();
+      if (live) {
+        for (uint32_t g = gs; g < ge; ++g) {
+          const uint32_t xb = P.pg_xb[g];
+          if (2u * __popc(tb & xb) == static_cast<uint32_t>(__popc(xb))) {
+            double fr = 0.0, fi = 0.0;
+            phase_sum_lds(s_F, s_Fz, P.pg_u0[g] - us, P.pg_u0[g + 1] - P.pg_u0[g], tb, fr, fi);
+            double ar, ai;
+            load_amp<T>(s_row, stage, psi, rowoff, rank_of(tb ^ xb, n_orb, P.n_chunks, rtab), ar, ai);
+            cmul_acc(fr, fi, ar, ai, acc_r, acc_i);
+          }
+        }
+      }
+      gs = ge;
+    }
+    ++c;
   }
 
   double e_re = 0.0, e_im = 0.0, nrm = 0.0;
-#pragma unroll
-  for (int j = 0; j < NT; ++j) {
-    if (!live[j]) continue;
-    const uint64_t t = ia * db + col0 + threadIdx.x + j * kBlock;
+  if (live) {
+    const uint64_t t = ia * db + col;
     if (EXPVAL) {
       double pr, pi;
       Amp<T>::load(psi, t, pr, pi);
-      e_re = fma(pr, acc_r[j], fma(pi, acc_i[j], e_re));
-      e_im = fma(pr, acc_i[j], fma(-pi, acc_r[j], e_im));
-      nrm = fma(pr, pr, fma(pi, pi, nrm));
+      e_re = fma(pr, acc_r, pi * acc_i);
+      e_im = fma(pr, acc_i, -pi * acc_r);
+      nrm = fma(pr, pr, pi * pi);
+      if (out) Amp<T>::store(out, t, acc_r, acc_i);
     } else {
-      Amp<T>::store(out, t, acc_r[j], acc_i[j]);
+      Amp<T>::store(out, t, acc_r, acc_i);
     }
   }
-  if (EXPVAL) block_reduce3_store(e_re, e_im, nrm, partial + 3ull * (blockIdx.y * gridDim.x + blockIdx.x));
+  if (EXPVAL) block_reduce3_store<kSB>(e_re, e_im, nrm, partial + 3ull * (blockIdx.y * gridDim.x + blockIdx.x));
 }
 
 // Sums per-workgroup partials in a fixed order (deterministic).
@@ -250,37 +464,96 @@ __global__ __launch_bounds__(kBlock) void k_expval_finish(const double* partial,
     b += partial[3 * i + 1];
     c += partial[3 * i + 2];
   }
-  block_reduce3_store(a, b, c, result);
+  block_reduce3_store<kBlock>(a, b, c, result);
 }
 
 // ---------------------------------------------------------------- launch planning
 struct Launch {
   dim3 grid;
-  int nt = 0;
-  uint32_t cols = 0;
+  dim3 block;
   uint64_t parts = 0;
+  size_t lds = 0;
 };
+
+inline uint32_t align16(uint32_t v) { return (v + 15u) & ~15u; }
+
+int device_lds_limit() {
+  int dev = 0, v = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 64 * 1024;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0) {
+    (void)hipGetLastError();
+    return 64 * 1024;
+  }
+  return v;
+}
+
+// Fills the sector kernel's arguments and LDS layout for this operator/space.
+Launch plan_sector(const pbs_grouped& h, const pbs_space& sp, SectorArgs* a_out) {
+  SectorArgs a{};
+  a.n_orb = sp.n_orb;
+  a.n_alpha = sp.n_alpha;
+  a.n_beta = sp.n_beta;
+  a.n_chunks = sp.n_chunks;
+  a.dim_beta = static_cast<uint32_t>(sp.dim_beta);
+  a.n_class = h.n_class;
+  a.n_pairs = h.n_pairs;
+  a.n_moves = sp.n_beta * (sp.n_orb - sp.n_beta);
+  a.str_a = sp.str_alpha.get();
+  a.str_b = sp.str_beta.get();
+  a.rank_tab = sp.rank_tab.get();
+  a.cls_xa = h.cls_xa.get();
+  a.cls_g0 = h.cls_g0.get();
+  a.cls_zg = h.cls_zg.get();
+  a.cls_p0 = h.cls_p0.get();
+  a.cls_p1 = h.cls_p1.get();
+  a.cls_pm = h.cls_pm.get();
+  a.pmap = h.pmap.get();
+  a.pg_xb = h.pg_xb.get();
+  a.pg_u0 = h.pg_u0.get();
+  a.u_zb = h.u_zb.get();
+  a.u_t0 = h.u_t0.get();
+  a.pt_za = h.pt_za.get();
+  a.pt_c = reinterpret_cast<const double2*>(h.pt_c.get());
+
+  const int limit = device_lds_limit() - 512;  // static shared of the reduction
+  const uint32_t rank_bytes = sp.n_chunks * (sp.n_orb + 1) * 256 * 4;
+  const uint32_t f_bytes = kFCap * 16 + kFCap * 4;
+  a.enum_ok = (h.n_pmap > 0 && a.n_moves <= static_cast<uint32_t>(kMaxMoves) && sp.dim_beta < 65536 &&
+               h.n_pairs < 65536)
+                  ? 1u
+                  : 0u;
+  const uint32_t pu_bytes = a.enum_ok ? align16(h.n_pairs * 4) : 0u;
+  a.rank_lds = (sp.n_orb <= 16 && rank_bytes + f_bytes + pu_bytes <= static_cast<uint32_t>(limit)) ? 1u : 0u;
+  const uint32_t base = (a.rank_lds ? align16(rank_bytes) : 0u) + f_bytes + pu_bytes;
+  const uint64_t row_bytes = sp.dim_beta * 16ull;
+  a.row_lds = (row_bytes <= kRowCapBytes && base + row_bytes <= static_cast<uint64_t>(limit)) ? 1u : 0u;
+  uint32_t off = 0;
+  a.off_rank = off;
+  off += a.rank_lds ? align16(rank_bytes) : 0u;
+  a.off_row = off;
+  off += a.row_lds ? align16(static_cast<uint32_t>(row_bytes)) : 0u;
+  a.off_f = off;
+  off += kFCap * 16;
+  a.off_fz = off;
+  off += kFCap * 4;
+  a.off_pu = off;
+  off += pu_bytes;
+  *a_out = a;
+
+  Launch L;
+  const uint64_t chunks = (sp.dim_beta + kSB - 1) / kSB;
+  L.grid = dim3(static_cast<unsigned>(sp.dim_alpha), static_cast<unsigned>(chunks));
+  L.block = dim3(kSB);
+  L.parts = sp.dim_alpha * chunks;
+  L.lds = off;
+  return L;
+}
 
 constexpr unsigned kFullGridCap = 1u << 16;
 
-Launch plan_launch(const pbs_space& sp) {
-  Launch L;
-  if (!sp.sector) {
-    L.grid = dim3(grid_for(sp.dim, kBlock, kFullGridCap));
-    L.parts = L.grid.x;
-    return L;
-  }
-  const uint64_t db = sp.dim_beta;
-  int nt = 8;
-  if (db <= 2 * kBlock) nt = 2;
-  else if (db <= 4 * kBlock) nt = 4;
-  const uint64_t per = static_cast<uint64_t>(nt) * kBlock;
-  const uint64_t chunks = (db + per - 1) / per;
-  L.nt = nt;
-  L.cols = static_cast<uint32_t>((db + chunks - 1) / chunks);
-  L.grid = dim3(static_cast<unsigned>(sp.dim_alpha), static_cast<unsigned>(chunks));
-  L.parts = sp.dim_alpha * chunks;
-  return L;
+uint64_t partial_count(const pbs_space& sp) {
+  if (!sp.sector) return grid_for(sp.dim, kBlock, kFullGridCap);
+  return sp.dim_alpha * ((sp.dim_beta + kSB - 1) / kSB);
 }
 
 void validate(const pbs_grouped* h, const pbs_space* sp, pbs_dtype dt) {
@@ -290,57 +563,43 @@ void validate(const pbs_grouped* h, const pbs_space* sp, pbs_dtype dt) {
               "operator has " + std::to_string(h->n_qubits) + " qubits, space has " + std::to_string(sp->n_qubits));
   if (sp->sector) {
     PBS_REQUIRE(h->has_sector && h->half == sp->n_orb, PBS_ERR_ARG, "operator lacks sector tables for this split");
+    PBS_REQUIRE(sp->dim_beta < (1ull << 31) && sp->dim_alpha < (1ull << 31), PBS_ERR_RANGE,
+                "spin-string count exceeds the launch grid");
   }
 }
 
 template <class T, bool EXPVAL>
 void launch(const pbs_grouped& h, const pbs_space& sp, const void* psi, void* out, double* partial, hipStream_t s) {
-  const Launch L = plan_launch(sp);
   const T* p = static_cast<const T*>(psi);
   T* o = static_cast<T*>(out);
   if (!sp.sector) {
-    hipLaunchKernelGGL((k_apply_full<T, EXPVAL>), L.grid, dim3(kBlock), 0, s, sp.dim,
+    const dim3 grid(grid_for(sp.dim, kBlock, kFullGridCap));
+    hipLaunchKernelGGL((k_apply_full<T, EXPVAL>), grid, dim3(kBlock), 0, s, sp.dim,
                        static_cast<uint32_t>(h.n_groups), h.xg.get(), h.off.get(), h.zk.get(),
                        reinterpret_cast<const double2*>(h.ck.get()), p, o, partial);
   } else {
     SectorArgs a;
-    a.n_orb = sp.n_orb;
-    a.n_alpha = sp.n_alpha;
-    a.n_beta = sp.n_beta;
-    a.n_chunks = sp.n_chunks;
-    a.dim_beta = sp.dim_beta;
-    a.cols = L.cols;
-    a.n_class = h.n_class;
-    a.str_a = sp.str_alpha.get();
-    a.str_b = sp.str_beta.get();
-    a.rank_tab = sp.rank_tab.get();
-    a.cls_xa = h.cls_xa.get();
-    a.cls_g0 = h.cls_g0.get();
-    a.pg_xb = h.pg_xb.get();
-    a.pg_u0 = h.pg_u0.get();
-    a.u_zb = h.u_zb.get();
-    a.u_t0 = h.u_t0.get();
-    a.pt_za = h.pt_za.get();
-    a.pt_c = reinterpret_cast<const double2*>(h.pt_c.get());
-    const bool lds = sp.n_orb <= 16;
-#define PBS_SECTOR(NTV)                                                                                     \
-  if (lds)                                                                                                  \
-    hipLaunchKernelGGL((k_apply_sector<T, NTV, EXPVAL, true>), L.grid, dim3(kBlock), 0, s, a, p, o, partial);  \
-  else                                                                                                      \
-    hipLaunchKernelGGL((k_apply_sector<T, NTV, EXPVAL, false>), L.grid, dim3(kBlock), 0, s, a, p, o, partial);
-    if (L.nt == 2) {
-      PBS_SECTOR(2)
-    } else if (L.nt == 4) {
-      PBS_SECTOR(4)
-    } else {
-      PBS_SECTOR(8)
-    }
-#undef PBS_SECTOR
+    const Launch L = plan_sector(h, sp, &a);
+    auto kern = k_apply_sector<T, EXPVAL>;
+    if (L.lds > 64 * 1024)
+      PBS_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  static_cast<int>(L.lds)));
+    hipLaunchKernelGGL(kern, L.grid, L.block, L.lds, s, a, p, o, partial);
   }
   PBS_HIP(hipGetLastError());
 }
 
 }  // namespace
+
+void apply_launch(const pbs_grouped& h, const pbs_space& sp, pbs_dtype dt, const void* psi, void* out,
+                  hipStream_t s) {
+  validate(&h, &sp, dt);
+  if (dt == PBS_C128)
+    launch<double2, false>(h, sp, psi, out, nullptr, s);
+  else
+    launch<float2, false>(h, sp, psi, out, nullptr, s);
+}
+
 }  // namespace pbs
 
 using namespace pbs;
@@ -366,7 +625,7 @@ pbs_status pbs_apply_pauli_sum(const pbs_grouped* h, const pbs_space* sp, pbs_dt
 pbs_status pbs_expval_workspace_bytes(const pbs_space* sp, uint64_t* bytes) {
   return guarded([&] {
     PBS_REQUIRE(sp != nullptr && bytes != nullptr, PBS_ERR_ARG, "null argument");
-    *bytes = plan_launch(*sp).parts * 3 * sizeof(double);
+    *bytes = partial_count(*sp) * 3 * sizeof(double);
   });
 }
 
@@ -375,7 +634,7 @@ pbs_status pbs_expval(const pbs_grouped* h, const pbs_space* sp, pbs_dtype dt, c
   return guarded([&] {
     validate(h, sp, dt);
     PBS_REQUIRE(psi != nullptr && result != nullptr && work != nullptr, PBS_ERR_ARG, "null pointer");
-    const uint64_t need = plan_launch(*sp).parts * 3 * sizeof(double);
+    const uint64_t need = partial_count(*sp) * 3 * sizeof(double);
     PBS_REQUIRE(work_bytes >= need, PBS_ERR_ARG,
                 "workspace of " + std::to_string(work_bytes) + " bytes, need " + std::to_string(need));
     hipStream_t s = as_stream(stream);
@@ -384,7 +643,7 @@ pbs_status pbs_expval(const pbs_grouped* h, const pbs_space* sp, pbs_dtype dt, c
       launch<double2, true>(*h, *sp, psi, nullptr, partial, s);
     else
       launch<float2, true>(*h, *sp, psi, nullptr, partial, s);
-    hipLaunchKernelGGL(k_expval_finish, dim3(1), dim3(kBlock), 0, s, partial, plan_launch(*sp).parts, result);
+    hipLaunchKernelGGL(k_expval_finish, dim3(1), dim3(kBlock), 0, s, partial, partial_count(*sp), result);
     PBS_HIP(hipGetLastError());
   });
 }

@@ -35,37 +35,44 @@ __global__ void k_csr_fill(const uint64_t* x, const uint64_t* z, const double* c
 
 __global__ void k_set_u32(uint32_t* p, uint32_t v) { *p = v; }
 
-// Sector rewrite of every term: alive flag, sort keys and signed coefficient.
+// Sector rewrite of every term: alive flag, sort keys and signed coefficient
+// (the exact rewrites listed with pbs_grouped).  Keys, most significant word
+// first: (X_alpha << 6 | popcount(X_beta)), (X_beta << 32 | z_beta'), z_alpha.
 __global__ void k_sector_terms(const uint64_t* x, const uint64_t* zk, const double* ck, uint64_t m, uint32_t h,
-                               uint32_t* alive, uint64_t* key_hi, uint64_t* key_lo, double* cre, double* cim) {
+                               uint32_t* alive, uint64_t* k2, uint64_t* k1, uint64_t* k0, double* cre,
+                               double* cim) {
   const uint64_t mask = (h == 32) ? 0xffffffffull : ((1ull << h) - 1ull);
   for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < m;
        i += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
     const uint64_t xa = x[i] & mask, xb = (x[i] >> h) & mask;
     const uint64_t za = zk[i] & mask;
     uint64_t zb = (zk[i] >> h) & mask;
-    const int pa = __popcll(xa), pb = __popcll(xb);
-    alive[i] = ((pa & 1) == 0 && (pb & 1) == 0) ? 1u : 0u;
-    double sgn = 1.0;
+    const uint32_t pa = __popcll(xa), pb = __popcll(xb);
+    alive[i] = ((pa & 1u) == 0 && (pb & 1u) == 0) ? 1u : 0u;
+    uint32_t flips = 0;
     if (xb != 0 && (zb & (xb & (~xb + 1ull)))) {
       zb ^= xb;
-      if ((pb >> 1) & 1) sgn = -1.0;
+      flips += pb >> 1;
     }
-    key_hi[i] = (xa << 32) | xb;
-    key_lo[i] = (zb << 32) | za;
+    flips += __popcll(zb & xb) + __popcll(za & xa);
+    const double sgn = (flips & 1u) ? -1.0 : 1.0;
+    k2[i] = (xa << 6) | pb;
+    k1[i] = (xb << 32) | zb;
+    k0[i] = za;
     cre[i] = sgn * ck[2 * i];
     cim[i] = sgn * ck[2 * i + 1];
   }
 }
 
-__global__ void k_compact_alive(const uint32_t* alive, const uint32_t* pos, uint64_t m, const uint64_t* key_hi,
-                                const uint64_t* key_lo, uint64_t* keys_soa, uint64_t ma) {
+__global__ void k_compact_alive(const uint32_t* alive, const uint32_t* pos, uint64_t m, const uint64_t* k2,
+                                const uint64_t* k1, const uint64_t* k0, uint64_t* keys_soa, uint64_t ma) {
   for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < m;
        i += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
     if (!alive[i]) continue;
     const uint64_t o = pos[i];
-    keys_soa[o] = key_lo[i];        // word 0 (less significant)
-    keys_soa[ma + o] = key_hi[i];   // word 1
+    keys_soa[o] = k0[i];
+    keys_soa[ma + o] = k1[i];
+    keys_soa[2 * ma + o] = k2[i];
   }
 }
 
@@ -80,42 +87,88 @@ __global__ void k_alive_index(const uint32_t* alive, const uint32_t* pos, uint64
 __global__ void k_plan_heads(const uint64_t* keys_soa, uint64_t ma, uint32_t* hc, uint32_t* hg, uint32_t* hu) {
   for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < ma;
        i += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
-    const uint64_t hi = keys_soa[ma + i], lo = keys_soa[i];
+    const uint64_t w2 = keys_soa[2 * ma + i], w1 = keys_soa[ma + i];
     if (i == 0) {
       hc[i] = hg[i] = hu[i] = 1u;
       continue;
     }
-    const uint64_t phi = keys_soa[ma + i - 1], plo = keys_soa[i - 1];
-    hc[i] = ((hi >> 32) != (phi >> 32)) ? 1u : 0u;
-    hg[i] = (hi != phi) ? 1u : 0u;
-    hu[i] = (hi != phi || (lo >> 32) != (plo >> 32)) ? 1u : 0u;
+    const uint64_t p2 = keys_soa[2 * ma + i - 1], p1 = keys_soa[ma + i - 1];
+    const bool c = (w2 >> 6) != (p2 >> 6);
+    const bool g = c || (w1 >> 32) != (p1 >> 32);
+    hc[i] = c ? 1u : 0u;
+    hg[i] = g ? 1u : 0u;
+    hu[i] = (g || w1 != p1) ? 1u : 0u;
   }
 }
 
 __global__ void k_plan_fill(const uint64_t* keys_soa, uint64_t ma, const uint32_t* order, const uint32_t* src,
                             const double* cre, const double* cim, const uint32_t* hc, const uint32_t* hg,
                             const uint32_t* hu, const uint32_t* cid, const uint32_t* gid, const uint32_t* uid,
-                            uint32_t* cls_xa, uint32_t* cls_g0, uint32_t* pg_xb, uint32_t* pg_u0, uint32_t* u_zb,
-                            uint32_t* u_t0, uint32_t* pt_za, double* pt_c) {
+                            uint32_t* cls_xa, uint32_t* cls_g0, uint32_t* pg_xb, uint32_t* pg_pc, uint32_t* pg_u0,
+                            uint32_t* u_zb, uint32_t* u_t0, uint32_t* pt_za, double* pt_c) {
   for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < ma;
        i += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
-    const uint64_t hi = keys_soa[ma + i], lo = keys_soa[i];
+    const uint64_t w2 = keys_soa[2 * ma + i], w1 = keys_soa[ma + i], w0 = keys_soa[i];
     if (hc[i]) {
-      cls_xa[cid[i]] = static_cast<uint32_t>(hi >> 32);
+      cls_xa[cid[i]] = static_cast<uint32_t>(w2 >> 6);
       cls_g0[cid[i]] = gid[i];
     }
     if (hg[i]) {
-      pg_xb[gid[i]] = static_cast<uint32_t>(hi & 0xffffffffull);
+      pg_xb[gid[i]] = static_cast<uint32_t>(w1 >> 32);
+      pg_pc[gid[i]] = static_cast<uint32_t>(w2 & 63u);
       pg_u0[gid[i]] = uid[i];
     }
     if (hu[i]) {
-      u_zb[uid[i]] = static_cast<uint32_t>(lo >> 32);
+      u_zb[uid[i]] = static_cast<uint32_t>(w1 & 0xffffffffull);
       u_t0[uid[i]] = static_cast<uint32_t>(i);
     }
-    pt_za[i] = static_cast<uint32_t>(lo & 0xffffffffull);
+    pt_za[i] = static_cast<uint32_t>(w0);
     const uint32_t s = src[order[i]];
     pt_c[2 * i] = cre[s];
     pt_c[2 * i + 1] = cim[s];
+  }
+}
+
+// Per class: the X_beta = 0 group, the popcount-2 range, and whether the
+// class needs a pair-map row (flag written for a scan).
+__global__ void k_class_meta(uint32_t n_class, const uint32_t* cls_g0, const uint32_t* pg_pc, int32_t* zg,
+                             int32_t* p0, int32_t* p1, uint32_t* has_pairs) {
+  for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < n_class; c += gridDim.x * blockDim.x) {
+    const uint32_t g0 = cls_g0[c], g1 = cls_g0[c + 1];
+    uint32_t g = g0;
+    int32_t z = -1;
+    if (g < g1 && pg_pc[g] == 0) z = static_cast<int32_t>(g++);
+    const uint32_t a = g;
+    while (g < g1 && pg_pc[g] == 2) ++g;
+    zg[c] = z;
+    p0[c] = static_cast<int32_t>(a);
+    p1[c] = static_cast<int32_t>(g);
+    has_pairs[c] = g > a ? 1u : 0u;
+  }
+}
+
+__global__ void k_pair_rows(uint32_t n_class, const uint32_t* has_pairs, const uint32_t* slot, int32_t* pm) {
+  for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < n_class; c += gridDim.x * blockDim.x)
+    pm[c] = has_pairs[c] ? static_cast<int32_t>(slot[c]) : -1;
+}
+
+__global__ void k_fill_i32(int32_t* p, uint64_t n, int32_t v) {
+  for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<uint64_t>(gridDim.x) * blockDim.x)
+    p[i] = v;
+}
+
+// Pair map: the group of each popcount-2 X_beta in its class.
+__global__ void k_pair_map(uint32_t n_class, const int32_t* p0, const int32_t* p1, const int32_t* pm,
+                           const uint32_t* pg_xb, uint32_t n_pairs, int32_t* pmap) {
+  for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < n_class; c += gridDim.x * blockDim.x) {
+    if (pm[c] < 0) continue;
+    for (int32_t g = p0[c]; g < p1[c]; ++g) {
+      const uint32_t xb = pg_xb[g];
+      const uint32_t p = __ffs(xb) - 1;
+      const uint32_t q = 31 - __clz(xb);
+      pmap[static_cast<uint64_t>(pm[c]) * n_pairs + q * (q - 1) / 2 + p] = g;
+    }
   }
 }
 
@@ -125,17 +178,22 @@ static void build_sector_tables(pbs_grouped& g, const uint64_t* x, hipStream_t s
   const uint64_t m = g.n_terms;
   const uint32_t h = g.n_qubits / 2;
   g.half = h;
+  g.n_pairs = h * (h - 1) / 2;
   DevBuf<uint32_t> alive(m), apos(m), cnt(4);
-  DevBuf<uint64_t> key_hi(m), key_lo(m);
+  DevBuf<uint64_t> k2(m), k1(m), k0(m);
   DevBuf<double> cre(m), cim(m);
-  hipLaunchKernelGGL(k_sector_terms, dim3(grid_for(m, 256, 65536)), dim3(256), 0, s, x, g.zk.get(), g.ck.get(), m, h,
-                     alive.get(), key_hi.get(), key_lo.get(), cre.get(), cim.get());
-  PBS_HIP(hipGetLastError());
+  if (m) {
+    hipLaunchKernelGGL(k_sector_terms, dim3(grid_for(m, 256, 65536)), dim3(256), 0, s, x, g.zk.get(), g.ck.get(), m,
+                       h, alive.get(), k2.get(), k1.get(), k0.get(), cre.get(), cim.get());
+    PBS_HIP(hipGetLastError());
+  }
   exclusive_scan_u32(alive.get(), apos.get(), m, cnt.get(), s);
   const uint64_t ma = read_scalar(cnt.get(), s);
   g.n_pterm = static_cast<uint32_t>(ma);
+  g.has_sector = true;
   if (ma == 0) {
     g.n_class = g.n_pgroup = g.n_unique = 0;
+    g.n_pmap = 0;
     g.cls_g0.alloc(1);
     g.pg_u0.alloc(1);
     g.u_t0.alloc(1);
@@ -143,18 +201,17 @@ static void build_sector_tables(pbs_grouped& g, const uint64_t* x, hipStream_t s
     hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, s, g.pg_u0.get(), 0u);
     hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, s, g.u_t0.get(), 0u);
     PBS_HIP(hipStreamSynchronize(s));
-    g.has_sector = true;
     return;
   }
-  DevBuf<uint64_t> keys(2 * ma);
+  DevBuf<uint64_t> keys(3 * ma);
   DevBuf<uint32_t> src(ma), order(ma);
   hipLaunchKernelGGL(k_compact_alive, dim3(grid_for(m, 256, 65536)), dim3(256), 0, s, alive.get(), apos.get(), m,
-                     key_hi.get(), key_lo.get(), keys.get(), ma);
+                     k2.get(), k1.get(), k0.get(), keys.get(), ma);
   hipLaunchKernelGGL(k_alive_index, dim3(grid_for(m, 256, 65536)), dim3(256), 0, s, alive.get(), apos.get(), m,
                      src.get());
   PBS_HIP(hipGetLastError());
   iota_u32(order.get(), ma, s);
-  radix_sort_keys(keys.get(), order.get(), ma, 2, s);
+  radix_sort_keys(keys.get(), order.get(), ma, 3, s);
   DevBuf<uint32_t> hc(ma), hg(ma), hu(ma), cid(ma), gid(ma), uid(ma);
   hipLaunchKernelGGL(k_plan_heads, dim3(grid_for(ma, 256, 65536)), dim3(256), 0, s, keys.get(), ma, hc.get(),
                      hg.get(), hu.get());
@@ -170,6 +227,7 @@ static void build_sector_tables(pbs_grouped& g, const uint64_t* x, hipStream_t s
   g.cls_xa.alloc(g.n_class);
   g.cls_g0.alloc(g.n_class + 1);
   g.pg_xb.alloc(g.n_pgroup);
+  g.pg_pc.alloc(g.n_pgroup);
   g.pg_u0.alloc(g.n_pgroup + 1);
   g.u_zb.alloc(g.n_unique);
   g.u_t0.alloc(g.n_unique + 1);
@@ -177,14 +235,35 @@ static void build_sector_tables(pbs_grouped& g, const uint64_t* x, hipStream_t s
   g.pt_c.alloc(2 * ma);
   hipLaunchKernelGGL(k_plan_fill, dim3(grid_for(ma, 256, 65536)), dim3(256), 0, s, keys.get(), ma, order.get(),
                      src.get(), cre.get(), cim.get(), hc.get(), hg.get(), hu.get(), cid.get(), gid.get(), uid.get(),
-                     g.cls_xa.get(), g.cls_g0.get(), g.pg_xb.get(), g.pg_u0.get(), g.u_zb.get(), g.u_t0.get(),
-                     g.pt_za.get(), g.pt_c.get());
+                     g.cls_xa.get(), g.cls_g0.get(), g.pg_xb.get(), g.pg_pc.get(), g.pg_u0.get(), g.u_zb.get(),
+                     g.u_t0.get(), g.pt_za.get(), g.pt_c.get());
   hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, s, g.cls_g0.get() + g.n_class, g.n_pgroup);
   hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, s, g.pg_u0.get() + g.n_pgroup, g.n_unique);
   hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, s, g.u_t0.get() + g.n_unique, static_cast<uint32_t>(ma));
   PBS_HIP(hipGetLastError());
+
+  // bucket metadata and the pair map
+  g.cls_zg.alloc(g.n_class);
+  g.cls_p0.alloc(g.n_class);
+  g.cls_p1.alloc(g.n_class);
+  g.cls_pm.alloc(g.n_class);
+  DevBuf<uint32_t> has_pairs(g.n_class), slot(g.n_class);
+  hipLaunchKernelGGL(k_class_meta, dim3(grid_for(g.n_class, 256, 65536)), dim3(256), 0, s, g.n_class,
+                     g.cls_g0.get(), g.pg_pc.get(), g.cls_zg.get(), g.cls_p0.get(), g.cls_p1.get(), has_pairs.get());
+  exclusive_scan_u32(has_pairs.get(), slot.get(), g.n_class, cnt.get(), s);
+  g.n_pmap = read_scalar(cnt.get(), s);
+  hipLaunchKernelGGL(k_pair_rows, dim3(grid_for(g.n_class, 256, 65536)), dim3(256), 0, s, g.n_class, has_pairs.get(),
+                     slot.get(), g.cls_pm.get());
+  const uint64_t pm_entries = static_cast<uint64_t>(g.n_pmap) * g.n_pairs;
+  g.pmap.alloc(pm_entries);
+  if (pm_entries) {
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(pm_entries, 256, 65536)), dim3(256), 0, s, g.pmap.get(), pm_entries,
+                       -1);
+    hipLaunchKernelGGL(k_pair_map, dim3(grid_for(g.n_class, 256, 65536)), dim3(256), 0, s, g.n_class,
+                       g.cls_p0.get(), g.cls_p1.get(), g.cls_pm.get(), g.pg_xb.get(), g.n_pairs, g.pmap.get());
+  }
+  PBS_HIP(hipGetLastError());
   PBS_HIP(hipStreamSynchronize(s));
-  g.has_sector = true;
 }
 
 }  // namespace pbs

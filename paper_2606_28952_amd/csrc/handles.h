@@ -10,21 +10,32 @@
 // off[g]..off[g+1]-1 with Z-masks zk[] and XZ-form coefficients ck[] (re, im).
 //
 // Sector form (n_qubits even, split at h = n_qubits/2 into alpha = low half,
-// beta = high half).  Terms are ordered by (X_alpha, X_beta, z_beta', z_alpha):
-//   class c      : distinct X_alpha, groups cls_g0[c]..cls_g0[c+1]-1
+// beta = high half).  Terms are ordered by (X_alpha, popcount(X_beta),
+// X_beta, z_beta', z_alpha):
+//   class c      : distinct X_alpha, groups cls_g0[c]..cls_g0[c+1]-1; the
+//                  group with X_beta = 0 (if any) is cls_zg[c], the groups
+//                  with popcount(X_beta) = 2 are cls_p0[c]..cls_p1[c]-1 and
+//                  cls_pm[c] is their row in the pair map (or -1)
 //   group g      : X_beta = pg_xb[g], uniques pg_u0[g]..pg_u0[g+1]-1
 //   unique u     : beta Z-mask u_zb[u], terms u_t0[u]..u_t0[u+1]-1
 //   term t       : alpha Z-mask pt_za[t], coefficient pt_c[t] (re, im)
-// Two exact rewrites valid inside any fixed-(N_alpha, N_beta) sector are
-// applied: a term whose X_alpha or X_beta has odd popcount never maps a
-// sector configuration into the sector and is removed; and because a
-// sector-preserving move with X_beta flips exactly |X_beta|/2 set bits,
-// (-1)^popcount(z & s) = (-1)^(|X_beta|/2) (-1)^popcount((z ^ X_beta) & s),
-// so z_beta is replaced by the smaller of z_beta and z_beta ^ X_beta (the
-// one without X_beta's lowest bit) with the sign moved into the coefficient.
-// Terms that become equal in (z_beta', z_alpha) are kept separate; those with
-// equal z_beta' share one unique entry, whose alpha parities are folded per
-// target row at run time.
+//   pair map     : pmap[cls_pm[c] * n_pairs + pair(p, q)] = group with
+//                  X_beta = {p, q} in class c, or -1; pair(p, q) = q(q-1)/2 + p
+//                  for p < q
+// Exact rewrites valid inside any fixed-(N_alpha, N_beta) sector:
+//  * a term whose X_alpha or X_beta has odd popcount never maps a sector
+//    configuration into the sector and is removed;
+//  * a sector-preserving move with mask X flips exactly |X|/2 set bits of
+//    both the source s and the target t = s ^ X, so
+//    (-1)^popcount(z & s) = (-1)^(|X|/2) (-1)^popcount((z ^ X) & s): z_beta
+//    is replaced by whichever of z_beta, z_beta ^ X_beta lacks X_beta's
+//    lowest bit, with the sign moved into the coefficient;
+//  * (-1)^popcount(z & s) = (-1)^popcount(z & X) (-1)^popcount(z & t), so
+//    the constant factor (-1)^popcount(z & X) of both halves is moved into the
+//    coefficient and the kernel evaluates parities against the target
+//    strings, which each thread already holds.
+// Terms with equal z_beta' share one unique entry, whose alpha parities are
+// folded per target row at run time.
 struct pbs_grouped {
   uint32_t n_qubits = 0;
   uint64_t n_groups = 0;
@@ -37,7 +48,10 @@ struct pbs_grouped {
   bool has_sector = false;
   uint32_t half = 0;
   uint32_t n_class = 0, n_pgroup = 0, n_unique = 0, n_pterm = 0;
+  uint32_t n_pairs = 0, n_pmap = 0;
   pbs::DevBuf<uint32_t> cls_xa, cls_g0;
+  pbs::DevBuf<int32_t> cls_zg, cls_p0, cls_p1, cls_pm, pmap;
+  pbs::DevBuf<uint32_t> pg_pc;  // popcount(X_beta) of each group
   pbs::DevBuf<uint32_t> pg_xb, pg_u0;
   pbs::DevBuf<uint32_t> u_zb, u_t0;
   pbs::DevBuf<uint32_t> pt_za;
