@@ -63,6 +63,21 @@ __device__ inline double signed_by(double v, uint32_t p) {
   return __hiloint2double(__double2hiint(v) ^ static_cast<int>((p & 1u) << 31), __double2loint(v));
 }
 
+// Read-only load through the constant address space: uniform addresses
+// become scalar loads (the tables are never written by the kernels).
+__device__ inline uint32_t ldc(const uint32_t* p) { return *((const __attribute__((address_space(4))) uint32_t*)(p)); }
+
+__device__ inline ClassMeta ld_meta(const ClassMeta* p) {
+  static_assert(sizeof(ClassMeta) == 12 * sizeof(uint32_t), "ClassMeta layout");
+  const uint32_t* q = reinterpret_cast<const uint32_t*>(p);
+  uint32_t w[12];
+#pragma unroll
+  for (int i = 0; i < 12; ++i) w[i] = ldc(q + i);
+  ClassMeta m;
+  memcpy(&m, w, sizeof(m));
+  return m;
+}
+
 template <int B>
 __device__ inline void block_reduce3_store(double a, double b, double c, double* dst) {
   __shared__ double red[3][B / 64];
@@ -132,26 +147,21 @@ __global__ __launch_bounds__(kBlock) void k_apply_full(uint64_t dim, uint32_t n_
 
 // ---------------------------------------------------------------- spin sector
 constexpr int kSB = 512;              // lanes per sector workgroup = beta columns per workgroup
-constexpr int kMaxMoves = 64;         // pair moves cached per lane
-constexpr uint32_t kFCap = 1536;      // folded uniques held in LDS at once
+constexpr int kMaxMoves = 56;         // pair moves cached per lane (N_beta (n_orb - N_beta) <= 56)
+constexpr uint32_t kFCap = 1536;      // folded uniques held in LDS at once (+1 zero slot)
 constexpr uint32_t kRowCapBytes = 64u * 1024u;
-constexpr uint32_t kSimpleCap = 64;   // uniques of a batchable single-group class
 
 struct SectorArgs {
   uint32_t n_orb, n_alpha, n_beta, n_chunks;
   uint32_t dim_beta;
   uint32_t n_class, n_pairs, n_moves;
-  uint32_t rank_lds, row_lds, enum_ok;
+  uint32_t row_lds, enum_ok;
   uint32_t off_rank, off_row, off_f, off_fz, off_pu;  // LDS byte offsets
   const uint32_t* str_a;
   const uint32_t* str_b;
-  const uint32_t* rank_tab;
-  const uint32_t* cls_xa;
-  const uint32_t* cls_g0;
-  const int32_t* cls_zg;
-  const int32_t* cls_p0;
-  const int32_t* cls_p1;
-  const int32_t* cls_pm;
+  const uint16_t* rank16;  // n_orb <= 16
+  const uint32_t* rank32;
+  const ClassMeta* meta;
   const int32_t* pmap;
   const uint32_t* pg_xb;
   const uint32_t* pg_u0;
@@ -161,17 +171,25 @@ struct SectorArgs {
   const double2* pt_c;
 };
 
-__device__ inline uint32_t rank_of(uint32_t s, uint32_t n_orb, uint32_t n_chunks, const uint32_t* tab) {
+// Combinatorial rank of a spin string: uint16 tables in LDS (n_orb <= 16,
+// at most two byte chunks) or uint32 tables in global memory.
+template <bool R16>
+__device__ inline uint32_t rank_of(uint32_t s, const SectorArgs& P, const uint16_t* t16) {
+  if (R16) {
+    const uint32_t lo = s & 255u;
+    uint32_t r = t16[lo];
+    if (P.n_chunks > 1) r += t16[((P.n_orb + 1) + __popc(lo)) * 256 + ((s >> 8) & 255u)];
+    return r;
+  }
   uint32_t r = 0, below = 0;
-  for (uint32_t c = 0; c < n_chunks; ++c) {
+  for (uint32_t c = 0; c < P.n_chunks; ++c) {
     const uint32_t byte = (s >> (8 * c)) & 255u;
-    r += tab[(c * (n_orb + 1) + below) * 256 + byte];
+    r += P.rank32[(c * (P.n_orb + 1) + below) * 256 + byte];
     below += __popc(byte);
   }
   return r;
 }
 
-// Folds the alpha parities of uniques [ua, ub) for target alpha string ta:
 // F[u - ua] = sum over the unique's terms of C_t (-1)^popcount(za_t & ta).
 __device__ inline void fold_uniques(const SectorArgs& P, uint32_t ua, uint32_t ub, uint32_t ta, double2* F,
                                     uint32_t* Fz) {
@@ -189,7 +207,6 @@ __device__ inline void fold_uniques(const SectorArgs& P, uint32_t ua, uint32_t u
   }
 }
 
-// Phase sum of cnt folded uniques starting at LDS slot b, against beta target tb.
 __device__ inline void phase_sum_lds(const double2* F, const uint32_t* Fz, uint32_t b, uint32_t cnt, uint32_t tb,
                                      double& fr, double& fi) {
   for (uint32_t i = 0; i < cnt; ++i) {
@@ -225,39 +242,29 @@ __device__ inline void cmul_acc(double fr, double fi, double ar, double ai, doub
 }
 
 template <class T>
-__device__ inline void load_amp(const double2* srow, bool staged, const T* psi, uint64_t rowoff, uint32_t j,
-                                double& ar, double& ai) {
-  if (staged) {
-    const double2 v = srow[j];
-    ar = v.x;
-    ai = v.y;
-  } else {
-    Amp<T>::load(psi, rowoff + j, ar, ai);
-  }
-}
-
-__device__ inline bool class_is_simple(const SectorArgs& P, uint32_t c) {
-  const uint32_t g0 = P.cls_g0[c];
-  return P.cls_zg[c] >= 0 && P.cls_g0[c + 1] == g0 + 1 && P.pg_u0[g0 + 1] - P.pg_u0[g0] <= kSimpleCap;
+__device__ inline void ld_amp(const T* p, uint64_t i, double& r, double& m) {
+  Amp<T>::load(p, i, r, m);
 }
 
 // One workgroup: target alpha string ia (one row of the state), kSB beta
-// columns.  See the file header for the scheme.
-template <class T, bool EXPVAL>
-__global__ __launch_bounds__(kSB) void k_apply_sector(SectorArgs P, const T* __restrict__ psi, T* __restrict__ out,
+// columns, one target per lane.  See the file header for the scheme.
+template <class T, bool EXPVAL, bool R16, bool ROWLDS>
+__global__ __launch_bounds__(kSB) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_apply_sector(SectorArgs P, const T* __restrict__ psi, T* __restrict__ out,
                                                       double* __restrict__ partial) {
   extern __shared__ __align__(16) unsigned char smem[];
-  uint32_t* s_rank = reinterpret_cast<uint32_t*>(smem + P.off_rank);
-  double2* s_row = reinterpret_cast<double2*>(smem + P.off_row);
+  uint16_t* s_rank = reinterpret_cast<uint16_t*>(smem + P.off_rank);
+  T* s_row = reinterpret_cast<T*>(smem + P.off_row);
   double2* s_F = reinterpret_cast<double2*>(smem + P.off_f);
   uint32_t* s_Fz = reinterpret_cast<uint32_t*>(smem + P.off_fz);
   uint32_t* s_pu = reinterpret_cast<uint32_t*>(smem + P.off_pu);
 
-  const uint32_t* rtab = P.rank_tab;
-  if (P.rank_lds) {
+  if (R16) {
     const uint32_t n = P.n_chunks * (P.n_orb + 1) * 256;
-    for (uint32_t i = threadIdx.x; i < n; i += kSB) s_rank[i] = P.rank_tab[i];
-    rtab = s_rank;
+    for (uint32_t i = threadIdx.x; i < n; i += kSB) s_rank[i] = P.rank16[i];
+  }
+  if (threadIdx.x == 0) {  // zero slot for absent pair groups
+    s_F[kFCap] = make_double2(0.0, 0.0);
+    s_Fz[kFCap] = 0u;
   }
   __syncthreads();
 
@@ -265,13 +272,16 @@ __global__ __launch_bounds__(kSB) void k_apply_sector(SectorArgs P, const T* __r
   const uint64_t ia = blockIdx.x;
   const uint32_t col = blockIdx.y * kSB + threadIdx.x;
   const bool live = col < db;
+  const uint32_t colc = live ? col : 0u;  // in-bounds column for idle lanes
   const uint32_t ta = P.str_a[ia];
-  const uint32_t tb = P.str_b[live ? col : 0];
+  const uint32_t tb = P.str_b[colc];
   const uint32_t n_orb = P.n_orb;
 
-  // Pair moves of this lane's target: occupied p -> empty q, source rank and
-  // pair index packed as jb | pair << 16 (enumerated occupied-major).
+  // Pair moves of this lane's target (occupied p -> empty q), packed as
+  // source rank | pair index << 16, occupied-major.
   uint32_t mv[kMaxMoves];
+  // padding moves point at pair index n_pairs (the zero slot) and column 0
+  const uint32_t pad_move = P.n_pairs << 16;
   if (P.enum_ok) {
     const uint32_t full = (n_orb == 32) ? 0xffffffffu : ((1u << n_orb) - 1u);
     const uint32_t emp = ~tb & full;
@@ -280,14 +290,13 @@ __global__ __launch_bounds__(kSB) void k_apply_sector(SectorArgs P, const T* __r
     uint32_t p = __ffs(pm_occ) - 1;
 #pragma unroll
     for (int k = 0; k < kMaxMoves; ++k) {
-      mv[k] = 0;
+      mv[k] = pad_move;
       if (static_cast<uint32_t>(k) < P.n_moves) {
         const uint32_t q = __ffs(pm_emp) - 1;
         pm_emp &= pm_emp - 1;
         const uint32_t lo = p < q ? p : q, hi = p < q ? q : p;
         const uint32_t pair = hi * (hi - 1) / 2 + lo;
-        const uint32_t s = tb ^ (1u << p) ^ (1u << q);
-        mv[k] = rank_of(s, n_orb, P.n_chunks, rtab) | (pair << 16);
+        mv[k] = rank_of<R16>(tb ^ (1u << p) ^ (1u << q), P, s_rank) | (pair << 16);
         if (++j == ne) {
           j = 0;
           pm_emp = emp;
@@ -298,123 +307,153 @@ __global__ __launch_bounds__(kSB) void k_apply_sector(SectorArgs P, const T* __r
     }
   }
 
-  double acc_r = 0.0, acc_i = 0.0;
+  double ar4[4] = {0.0, 0.0, 0.0, 0.0}, ai4[4] = {0.0, 0.0, 0.0, 0.0};
   uint32_t c = 0;
   while (c < P.n_class) {
-    if (class_is_simple(P, c)) {
-      // batch of consecutive single-group classes: one cooperative fold
-      const uint32_t cb = c;
-      const uint32_t ua = P.pg_u0[P.cls_g0[c]];
-      uint32_t ce = c;
-      while (ce < P.n_class && class_is_simple(P, ce) && P.pg_u0[P.cls_g0[ce] + 1] - ua <= kFCap) ++ce;
-      const uint32_t ub = P.pg_u0[P.cls_g0[ce - 1] + 1];
+    const ClassMeta M = ld_meta(P.meta + c);
+    if (M.flags & kClassSimple) {
+      // consecutive single-group classes share one cooperative fold
+      const uint32_t ua = M.ua;
+      uint32_t ce = c + 1;
+      uint32_t ub = M.u_end;
+      while (ce < P.n_class) {
+        const ClassMeta N = ld_meta(P.meta + ce);
+        if (!(N.flags & kClassSimple) || N.u_end - ua > kFCap) break;
+        ub = N.u_end;
+        ++ce;
+      }
       __syncthreads();
       fold_uniques(P, ua, ub, ta, s_F, s_Fz);
       __syncthreads();
-      if (live) {
-        for (uint32_t cc = cb; cc < ce; ++cc) {
-          const uint32_t sa = ta ^ P.cls_xa[cc];
-          if (static_cast<uint32_t>(__popc(sa)) != P.n_alpha) continue;
-          const uint64_t rowoff = static_cast<uint64_t>(rank_of(sa, n_orb, P.n_chunks, rtab)) * db;
-          const uint32_t g = P.cls_g0[cc];
-          double fr = 0.0, fi = 0.0;
-          phase_sum_lds(s_F, s_Fz, P.pg_u0[g] - ua, P.pg_u0[g + 1] - P.pg_u0[g], tb, fr, fi);
-          double ar, ai;
-          Amp<T>::load(psi, rowoff + col, ar, ai);
-          cmul_acc(fr, fi, ar, ai, acc_r, acc_i);
-        }
+      for (uint32_t cc = c; cc < ce; ++cc) {
+        const ClassMeta N = ld_meta(P.meta + cc);
+        const uint32_t sa = ta ^ N.xa;
+        if (static_cast<uint32_t>(__popc(sa)) != P.n_alpha) continue;
+        const uint64_t rowoff = static_cast<uint64_t>(rank_of<R16>(sa, P, s_rank)) * db;
+        double fr = 0.0, fi = 0.0;
+        phase_sum_lds(s_F, s_Fz, N.ua - ua, N.u_end - N.ua, tb, fr, fi);
+        double a_r, a_i;
+        ld_amp<T>(psi, rowoff + colc, a_r, a_i);
+        cmul_acc(fr, fi, a_r, a_i, ar4[cc & 3], ai4[cc & 3]);
       }
       c = ce;
       continue;
     }
 
-    const uint32_t sa = ta ^ P.cls_xa[c];
+    const uint32_t sa = ta ^ M.xa;
     if (static_cast<uint32_t>(__popc(sa)) != P.n_alpha) {
       ++c;
       continue;
     }
-    const uint64_t rowoff = static_cast<uint64_t>(rank_of(sa, n_orb, P.n_chunks, rtab)) * db;
-    const uint32_t g0 = P.cls_g0[c], g1 = P.cls_g0[c + 1];
-    const int32_t zg = P.cls_zg[c];
-    const uint32_t gz_end = zg >= 0 ? g0 + 1 : g0;
-    const int32_t pm = P.cls_pm[c];
-    const uint32_t p1 = static_cast<uint32_t>(P.cls_p1[c]);
-    const uint32_t ua = P.pg_u0[g0];
-    const bool penum = P.enum_ok && pm >= 0 && (P.pg_u0[p1] - ua) <= kFCap;
-    const uint32_t ub_a = penum ? P.pg_u0[p1] : P.pg_u0[gz_end];
-    const bool fold_a = ub_a > ua && ub_a - ua <= kFCap;
-    const bool stage = P.row_lds && gz_end < g1;
+    const uint64_t rowoff = static_cast<uint64_t>(rank_of<R16>(sa, P, s_rank)) * db;
+    const uint32_t gz_end = M.zg >= 0 ? M.g0 + 1 : M.g0;
+    // enumerate pair moves when the class's pair groups are dense enough
+    const bool penum = P.enum_ok && M.pm >= 0 && (M.u_p - M.ua) <= kFCap && 2 * (M.p1 - gz_end) >= P.n_moves;
+    const bool single = penum && (M.flags & kClassPairsSingle);
+    const uint32_t ub_a = penum ? M.u_p : M.u_z;
+    const bool fold_a = ub_a > M.ua && ub_a - M.ua <= kFCap;
+    const bool stage = P.row_lds && gz_end < M.g1;
+    const T* rowg = psi + rowoff;
 
     // phase A: X_beta = 0 group and, when enumerated, the pair groups
     if (stage || fold_a) {
       __syncthreads();
-      if (stage) {
-        for (uint32_t j = threadIdx.x; j < db; j += kSB) {
-          double ar, ai;
-          Amp<T>::load(psi, rowoff + j, ar, ai);
-          s_row[j] = make_double2(ar, ai);
-        }
-      }
-      if (fold_a) fold_uniques(P, ua, ub_a, ta, s_F, s_Fz);
+      if (stage)
+        for (uint32_t j = threadIdx.x; j < db; j += kSB) s_row[j] = rowg[j];
+      if (fold_a) fold_uniques(P, M.ua, ub_a, ta, s_F, s_Fz);
       if (penum) {
-        for (uint32_t q = threadIdx.x; q < P.n_pairs; q += kSB) {
-          const int32_t g = P.pmap[static_cast<uint64_t>(pm) * P.n_pairs + q];
-          s_pu[q] = g >= 0 ? ((P.pg_u0[g] - ua) | ((P.pg_u0[g + 1] - P.pg_u0[g]) << 16)) : 0u;
+        const int32_t* pm = P.pmap + static_cast<uint64_t>(M.pm) * P.n_pairs;
+        for (uint32_t q = threadIdx.x; q <= P.n_pairs; q += kSB) {
+          const int32_t g = q < P.n_pairs ? pm[q] : -1;  // entry n_pairs serves the padding moves
+          uint32_t v;
+          if (single)
+            v = g >= 0 ? P.pg_u0[g] - M.ua : kFCap;
+          else
+            v = g >= 0 ? ((P.pg_u0[g] - M.ua) | ((P.pg_u0[g + 1] - P.pg_u0[g]) << 16)) : 0u;
+          s_pu[q] = v;
         }
       }
       __syncthreads();
     }
-    if (live) {
-      if (zg >= 0) {
-        double fr = 0.0, fi = 0.0;
-        if (fold_a)
-          phase_sum_lds(s_F, s_Fz, 0, P.pg_u0[zg + 1] - ua, tb, fr, fi);
-        else
-          phase_sum_direct(P, static_cast<uint32_t>(zg), ta, tb, fr, fi);
-        double ar, ai;
-        load_amp<T>(s_row, stage, psi, rowoff, col, ar, ai);
-        cmul_acc(fr, fi, ar, ai, acc_r, acc_i);
-      }
-      if (penum) {
-        uint32_t n_moves = P.n_moves;
-        asm volatile("" : "+s"(n_moves));  // per-class, so the move predicates are not hoisted either
+    if (M.zg >= 0) {
+      double fr = 0.0, fi = 0.0;
+      if (fold_a)
+        phase_sum_lds(s_F, s_Fz, 0, M.u_z - M.ua, tb, fr, fi);
+      else
+        phase_sum_direct(P, static_cast<uint32_t>(M.zg), ta, tb, fr, fi);
+      double a_r, a_i;
+      if (ROWLDS && stage)
+        ld_amp<T>(s_row, colc, a_r, a_i);
+      else
+        ld_amp<T>(rowg, colc, a_r, a_i);
+      cmul_acc(fr, fi, a_r, a_i, ar4[0], ai4[0]);
+    }
+    const T* rowp = ROWLDS ? s_row : rowg;  // pair and scanned groups need the staged row
+    if (penum) {
+      uint32_t n_moves = P.n_moves;
+      asm volatile("" : "+s"(n_moves));  // keep the move predicates inside the class loop
+      if (single) {
+        // straight-line groups of four moves: one unique per pair group; absent
+        // groups and padding moves hit the zero slot, so loads issue together
+#pragma unroll
+        for (int k0 = 0; k0 < kMaxMoves; k0 += 4) {
+          if (static_cast<uint32_t>(k0) < n_moves) {
+            uint32_t e[4], slot[4], z[4];
+            double2 f[4];
+            double a_r[4], a_i[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              e[i] = mv[k0 + i];
+              asm volatile("" : "+v"(e[i]));  // keep per-move address arithmetic inside the class loop
+              slot[i] = s_pu[e[i] >> 16];
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              f[i] = s_F[slot[i]];
+              z[i] = s_Fz[slot[i]];
+              ld_amp<T>(rowp, e[i] & 0xffffu, a_r[i], a_i[i]);
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const uint32_t par = __popc(z[i] & tb);
+              cmul_acc(signed_by(f[i].x, par), signed_by(f[i].y, par), a_r[i], a_i[i], ar4[i], ai4[i]);
+            }
+          }
+        }
+      } else {
 #pragma unroll
         for (int k = 0; k < kMaxMoves; ++k) {
           if (static_cast<uint32_t>(k) < n_moves) {
             uint32_t e = mv[k];
-            // keep per-move address arithmetic inside the class loop (hoisting
-            // it would cost several registers per cached move)
             asm volatile("" : "+v"(e));
             const uint32_t w = s_pu[e >> 16];
             const uint32_t cnt = w >> 16;
-            if (cnt) {
-              double fr = 0.0, fi = 0.0;
-              phase_sum_lds(s_F, s_Fz, w & 0xffffu, cnt, tb, fr, fi);
-              double ar, ai;
-              load_amp<T>(s_row, stage, psi, rowoff, e & 0xffffu, ar, ai);
-              cmul_acc(fr, fi, ar, ai, acc_r, acc_i);
-            }
+            double fr = 0.0, fi = 0.0;
+            phase_sum_lds(s_F, s_Fz, w & 0xffffu, cnt, tb, fr, fi);
+            double a_r, a_i;
+            ld_amp<T>(rowp, e & 0xffffu, a_r, a_i);
+            cmul_acc(fr, fi, a_r, a_i, ar4[k & 3], ai4[k & 3]);
           }
         }
       }
     }
 
-    // phase B: remaining groups, scanned in chunks whose uniques fit in LDS
-    uint32_t gs = penum ? p1 : gz_end;
-    while (gs < g1) {
-      const uint32_t us = P.pg_u0[gs];
+    // phase B: remaining groups, scanned in chunks whose uniques fit in LDS;
+    // invalid targets are predicated off (source index clamped, coefficient 0)
+    uint32_t gs = penum ? M.p1 : gz_end;
+    while (gs < M.g1) {
+      const uint32_t us = ldc(P.pg_u0 + gs);
       uint32_t ge = gs;
-      while (ge < g1 && P.pg_u0[ge + 1] - us <= kFCap) ++ge;
+      while (ge < M.g1 && ldc(P.pg_u0 + ge + 1) - us <= kFCap) ++ge;
       if (ge == gs) {
-        if (live) {
-          const uint32_t xb = P.pg_xb[gs];
-          if (2u * __popc(tb & xb) == static_cast<uint32_t>(__popc(xb))) {
-            double fr = 0.0, fi = 0.0;
-            phase_sum_direct(P, gs, ta, tb, fr, fi);
-            double ar, ai;
-            load_amp<T>(s_row, stage, psi, rowoff, rank_of(tb ^ xb, n_orb, P.n_chunks, rtab), ar, ai);
-            cmul_acc(fr, fi, ar, ai, acc_r, acc_i);
-          }
+        const uint32_t xb = P.pg_xb[gs];
+        const bool valid = live && 2u * __popc(tb & xb) == static_cast<uint32_t>(__popc(xb));
+        if (valid) {
+          double fr = 0.0, fi = 0.0;
+          phase_sum_direct(P, gs, ta, tb, fr, fi);
+          double a_r, a_i;
+          ld_amp<T>(rowp, rank_of<R16>(tb ^ xb, P, s_rank), a_r, a_i);
+          cmul_acc(fr, fi, a_r, a_i, ar4[1], ai4[1]);
         }
         ++gs;
         continue;
@@ -422,23 +461,26 @@ __global__ __launch_bounds__(kSB) void k_apply_sector(SectorArgs P, const T* __r
       __syncthreads();
       fold_uniques(P, us, P.pg_u0[ge], ta, s_F, s_Fz);
       __syncthreads();
-      if (live) {
-        for (uint32_t g = gs; g < ge; ++g) {
-          const uint32_t xb = P.pg_xb[g];
-          if (2u * __popc(tb & xb) == static_cast<uint32_t>(__popc(xb))) {
-            double fr = 0.0, fi = 0.0;
-            phase_sum_lds(s_F, s_Fz, P.pg_u0[g] - us, P.pg_u0[g + 1] - P.pg_u0[g], tb, fr, fi);
-            double ar, ai;
-            load_amp<T>(s_row, stage, psi, rowoff, rank_of(tb ^ xb, n_orb, P.n_chunks, rtab), ar, ai);
-            cmul_acc(fr, fi, ar, ai, acc_r, acc_i);
-          }
-        }
+#pragma unroll 2
+      for (uint32_t g = gs; g < ge; ++g) {
+        const uint32_t xb = ldc(P.pg_xb + g);
+        const uint32_t u0 = ldc(P.pg_u0 + g), u1 = ldc(P.pg_u0 + g + 1);
+        const bool valid = 2u * __popc(tb & xb) == static_cast<uint32_t>(__popc(xb));
+        const uint32_t jb = valid ? rank_of<R16>(tb ^ xb, P, s_rank) : 0u;
+        double fr = 0.0, fi = 0.0;
+        phase_sum_lds(s_F, s_Fz, u0 - us, u1 - u0, tb, fr, fi);
+        double a_r, a_i;
+        ld_amp<T>(rowp, jb, a_r, a_i);
+        if (!valid) fr = fi = 0.0;
+        cmul_acc(fr, fi, a_r, a_i, ar4[2 + (g & 1)], ai4[2 + (g & 1)]);
       }
       gs = ge;
     }
     ++c;
   }
 
+  const double acc_r = (ar4[0] + ar4[1]) + (ar4[2] + ar4[3]);
+  const double acc_i = (ai4[0] + ai4[1]) + (ai4[2] + ai4[3]);
   double e_re = 0.0, e_im = 0.0, nrm = 0.0;
   if (live) {
     const uint64_t t = ia * db + col;
@@ -488,7 +530,7 @@ int device_lds_limit() {
 }
 
 // Fills the sector kernel's arguments and LDS layout for this operator/space.
-Launch plan_sector(const pbs_grouped& h, const pbs_space& sp, SectorArgs* a_out) {
+Launch plan_sector(const pbs_grouped& h, const pbs_space& sp, size_t elem_bytes, SectorArgs* a_out, bool* r16) {
   SectorArgs a{};
   a.n_orb = sp.n_orb;
   a.n_alpha = sp.n_alpha;
@@ -500,13 +542,9 @@ Launch plan_sector(const pbs_grouped& h, const pbs_space& sp, SectorArgs* a_out)
   a.n_moves = sp.n_beta * (sp.n_orb - sp.n_beta);
   a.str_a = sp.str_alpha.get();
   a.str_b = sp.str_beta.get();
-  a.rank_tab = sp.rank_tab.get();
-  a.cls_xa = h.cls_xa.get();
-  a.cls_g0 = h.cls_g0.get();
-  a.cls_zg = h.cls_zg.get();
-  a.cls_p0 = h.cls_p0.get();
-  a.cls_p1 = h.cls_p1.get();
-  a.cls_pm = h.cls_pm.get();
+  a.rank16 = sp.rank_tab16.get();
+  a.rank32 = sp.rank_tab.get();
+  a.meta = h.cls_meta.get();
   a.pmap = h.pmap.get();
   a.pg_xb = h.pg_xb.get();
   a.pg_u0 = h.pg_u0.get();
@@ -515,27 +553,26 @@ Launch plan_sector(const pbs_grouped& h, const pbs_space& sp, SectorArgs* a_out)
   a.pt_za = h.pt_za.get();
   a.pt_c = reinterpret_cast<const double2*>(h.pt_c.get());
 
-  const int limit = device_lds_limit() - 512;  // static shared of the reduction
-  const uint32_t rank_bytes = sp.n_chunks * (sp.n_orb + 1) * 256 * 4;
-  const uint32_t f_bytes = kFCap * 16 + kFCap * 4;
+  const uint32_t limit = static_cast<uint32_t>(device_lds_limit()) - 512u;  // reduction scratch
+  *r16 = sp.n_orb <= 16;
+  const uint32_t rank_bytes = *r16 ? align16(sp.n_chunks * (sp.n_orb + 1) * 256 * 2) : 0u;
+  const uint32_t f_bytes = (kFCap + 1) * 16 + align16((kFCap + 1) * 4);
   a.enum_ok = (h.n_pmap > 0 && a.n_moves <= static_cast<uint32_t>(kMaxMoves) && sp.dim_beta < 65536 &&
                h.n_pairs < 65536)
                   ? 1u
                   : 0u;
-  const uint32_t pu_bytes = a.enum_ok ? align16(h.n_pairs * 4) : 0u;
-  a.rank_lds = (sp.n_orb <= 16 && rank_bytes + f_bytes + pu_bytes <= static_cast<uint32_t>(limit)) ? 1u : 0u;
-  const uint32_t base = (a.rank_lds ? align16(rank_bytes) : 0u) + f_bytes + pu_bytes;
-  const uint64_t row_bytes = sp.dim_beta * 16ull;
-  a.row_lds = (row_bytes <= kRowCapBytes && base + row_bytes <= static_cast<uint64_t>(limit)) ? 1u : 0u;
+  const uint32_t pu_bytes = a.enum_ok ? align16((h.n_pairs + 1) * 4) : 0u;
+  const uint64_t row_bytes = sp.dim_beta * elem_bytes;
+  a.row_lds = (row_bytes <= kRowCapBytes && rank_bytes + f_bytes + pu_bytes + row_bytes <= limit) ? 1u : 0u;
   uint32_t off = 0;
   a.off_rank = off;
-  off += a.rank_lds ? align16(rank_bytes) : 0u;
+  off += rank_bytes;
   a.off_row = off;
   off += a.row_lds ? align16(static_cast<uint32_t>(row_bytes)) : 0u;
   a.off_f = off;
-  off += kFCap * 16;
+  off += (kFCap + 1) * 16;
   a.off_fz = off;
-  off += kFCap * 4;
+  off += align16((kFCap + 1) * 4);
   a.off_pu = off;
   off += pu_bytes;
   *a_out = a;
@@ -579,8 +616,10 @@ void launch(const pbs_grouped& h, const pbs_space& sp, const void* psi, void* ou
                        reinterpret_cast<const double2*>(h.ck.get()), p, o, partial);
   } else {
     SectorArgs a;
-    const Launch L = plan_sector(h, sp, &a);
-    auto kern = k_apply_sector<T, EXPVAL>;
+    bool r16 = false;
+    const Launch L = plan_sector(h, sp, sizeof(T), &a, &r16);
+    auto kern = r16 ? (a.row_lds ? k_apply_sector<T, EXPVAL, true, true> : k_apply_sector<T, EXPVAL, true, false>)
+                    : (a.row_lds ? k_apply_sector<T, EXPVAL, false, true> : k_apply_sector<T, EXPVAL, false, false>);
     if (L.lds > 64 * 1024)
       PBS_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
                                   static_cast<int>(L.lds)));

@@ -152,6 +152,32 @@ __global__ void k_pair_rows(uint32_t n_class, const uint32_t* has_pairs, const u
     pm[c] = has_pairs[c] ? static_cast<int32_t>(slot[c]) : -1;
 }
 
+__global__ void k_class_pack(uint32_t n_class, const uint32_t* cls_xa, const uint32_t* cls_g0, const int32_t* zg,
+                             const int32_t* p1, const int32_t* pm, const uint32_t* pg_u0, ClassMeta* meta) {
+  for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < n_class; c += gridDim.x * blockDim.x) {
+    ClassMeta m;
+    m.xa = cls_xa[c];
+    m.g0 = cls_g0[c];
+    m.g1 = cls_g0[c + 1];
+    m.zg = zg[c];
+    m.p1 = static_cast<uint32_t>(p1[c]);
+    m.pm = pm[c];
+    const uint32_t gz_end = m.zg >= 0 ? m.g0 + 1 : m.g0;
+    m.ua = pg_u0[m.g0];
+    m.u_z = pg_u0[gz_end];
+    m.u_p = pg_u0[m.p1];
+    m.u_end = pg_u0[m.g1];
+    uint32_t f = 0;
+    if (m.zg >= 0 && m.g1 == m.g0 + 1 && m.u_end - m.ua <= kSimpleCap) f |= kClassSimple;
+    bool single = true;
+    for (uint32_t g = gz_end; g < m.p1; ++g) single = single && (pg_u0[g + 1] - pg_u0[g] == 1);
+    if (single) f |= kClassPairsSingle;
+    m.flags = f;
+    m.pad = 0;
+    meta[c] = m;
+  }
+}
+
 __global__ void k_fill_i32(int32_t* p, uint64_t n, int32_t v) {
   for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < n;
        i += static_cast<uint64_t>(gridDim.x) * blockDim.x)
@@ -262,6 +288,10 @@ static void build_sector_tables(pbs_grouped& g, const uint64_t* x, hipStream_t s
     hipLaunchKernelGGL(k_pair_map, dim3(grid_for(g.n_class, 256, 65536)), dim3(256), 0, s, g.n_class,
                        g.cls_p0.get(), g.cls_p1.get(), g.cls_pm.get(), g.pg_xb.get(), g.n_pairs, g.pmap.get());
   }
+  g.cls_meta.alloc(g.n_class);
+  hipLaunchKernelGGL(k_class_pack, dim3(grid_for(g.n_class, 256, 65536)), dim3(256), 0, s, g.n_class,
+                     g.cls_xa.get(), g.cls_g0.get(), g.cls_zg.get(), g.cls_p1.get(), g.cls_pm.get(), g.pg_u0.get(),
+                     g.cls_meta.get());
   PBS_HIP(hipGetLastError());
   PBS_HIP(hipStreamSynchronize(s));
 }

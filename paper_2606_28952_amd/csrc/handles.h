@@ -36,6 +36,26 @@
 //    strings, which each thread already holds.
 // Terms with equal z_beta' share one unique entry, whose alpha parities are
 // folded per target row at run time.
+namespace pbs {
+// Per-class record read by the sector kernel in one load.
+struct ClassMeta {
+  uint32_t xa;      // X_alpha of the class
+  uint32_t g0, g1;  // its groups
+  int32_t zg;       // the X_beta = 0 group, or -1
+  uint32_t p1;      // end of the popcount-2 groups (they start after zg)
+  int32_t pm;       // pair-map row, or -1
+  uint32_t ua;      // first unique of the class
+  uint32_t u_z;     // end of the X_beta = 0 group's uniques
+  uint32_t u_p;     // end of the pair groups' uniques
+  uint32_t u_end;   // end of the class's uniques
+  uint32_t flags;   // kClassSimple | kClassPairsSingle
+  uint32_t pad;
+};
+constexpr uint32_t kClassSimple = 1u;       // only an X_beta = 0 group, few uniques
+constexpr uint32_t kClassPairsSingle = 2u;  // every pair group has exactly one unique
+constexpr uint32_t kSimpleCap = 64;         // uniques of a "simple" class
+}  // namespace pbs
+
 struct pbs_grouped {
   uint32_t n_qubits = 0;
   uint64_t n_groups = 0;
@@ -52,6 +72,7 @@ struct pbs_grouped {
   pbs::DevBuf<uint32_t> cls_xa, cls_g0;
   pbs::DevBuf<int32_t> cls_zg, cls_p0, cls_p1, cls_pm, pmap;
   pbs::DevBuf<uint32_t> pg_pc;  // popcount(X_beta) of each group
+  pbs::DevBuf<pbs::ClassMeta> cls_meta;
   pbs::DevBuf<uint32_t> pg_xb, pg_u0;
   pbs::DevBuf<uint32_t> u_zb, u_t0;
   pbs::DevBuf<uint32_t> pt_za;
@@ -71,6 +92,8 @@ struct pbs_space {
   // rank_tab[(c * (n_orb + 1) + k) * 256 + b]: contribution of byte b of chunk c
   // to the combinatorial rank when k ones lie below the chunk.
   pbs::DevBuf<uint32_t> rank_tab;
+  // the same tables as uint16 when n_orb <= 16 (every entry is below 2^16)
+  pbs::DevBuf<uint16_t> rank_tab16;
 };
 
 namespace pbs {

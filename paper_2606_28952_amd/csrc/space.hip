@@ -57,6 +57,12 @@ __global__ void k_unrank_all(uint32_t n_orb, uint32_t n_ones, uint64_t count, ui
   }
 }
 
+__global__ void k_narrow_u16(const uint32_t* in, uint64_t n, uint16_t* out) {
+  for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<uint64_t>(gridDim.x) * blockDim.x)
+    out[i] = static_cast<uint16_t>(in[i]);
+}
+
 __device__ inline uint32_t rank_string(uint32_t s, uint32_t n_orb, uint32_t n_chunks, const uint32_t* tab) {
   uint32_t r = 0;
   uint32_t below = 0;
@@ -161,6 +167,11 @@ pbs_status pbs_space_sector(uint32_t n_orb, uint32_t n_alpha, uint32_t n_beta, v
       sp->str_beta.alloc(db);
       hipLaunchKernelGGL(k_rank_tables, dim3(grid_for(nt, 256, 4096)), dim3(256), 0, s, n_orb, sp->n_chunks,
                          sp->rank_tab.get());
+      if (n_orb <= 16) {
+        sp->rank_tab16.alloc(nt);
+        hipLaunchKernelGGL(k_narrow_u16, dim3(grid_for(nt, 256, 4096)), dim3(256), 0, s, sp->rank_tab.get(), nt,
+                           sp->rank_tab16.get());
+      }
       hipLaunchKernelGGL(k_unrank_all, dim3(grid_for(da, 256, 65536)), dim3(256), 0, s, n_orb, n_alpha, da,
                          sp->str_alpha.get());
       hipLaunchKernelGGL(k_unrank_all, dim3(grid_for(db, 256, 65536)), dim3(256), 0, s, n_orb, n_beta, db,
