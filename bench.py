@@ -109,12 +109,131 @@ def cpu_baseline(h1, h2, n_orb, n_alpha, n_beta, psi, budget_s=20.0):
                       f"sector configurations (NumPy float64 scatter), {elapsed:.1f} s"}
 
 
+def batched_jobs():
+    """64 molecular jobs over uneven sectors: job i has n_orb = 10 + i % 4,
+    N_e = n_orb + (-2, -1, 0, 1)[(i // 4) % 4], 2 S_z = N_e % 2 + 2 ((i // 16) % 2),
+    its own integrals (seed 3000 + i) and state (seed 3100 + i)."""
+    out = []
+    for i in range(64):
+        n_orb = 10 + i % 4
+        n_e = n_orb + (-2, -1, 0, 1)[(i // 4) % 4]
+        two_sz = n_e % 2 + 2 * ((i // 16) % 2)
+        out.append((n_orb, (n_e + two_sz) // 2, (n_e - two_sz) // 2, 3000 + i, 3100 + i))
+    return out
+
+
+def bench_batched(args):
+    """Batched complex64 apply + energies in one launch vs per-job FP64 launches."""
+    import torch
+
+    import synth
+    from paper_2606_28952_amd import api
+
+    dev = torch.device("cuda:0")
+    jobs32, jobs64, work = [], [], 0.0
+    handles = []
+    for n_orb, na, nb, hs, ps in batched_jobs():
+        h1, h2 = synth.molecular_spin_integrals(n_orb, hs)
+        H = api.jw_transform(torch.from_numpy(h1).to(dev), torch.from_numpy(h2).to(dev))
+        G = H.group()
+        sp = api.Space.sector(n_orb, na, nb)
+        psi = torch.from_numpy(synth.random_state(sp.dim, ps)).to(dev)
+        p32 = psi.to(torch.complex64)
+        jobs32.append((G, sp, p32, torch.empty_like(p32)))
+        jobs64.append((G, sp, psi, torch.empty_like(psi)))
+        handles.append(H)
+        work += sp.dim * H.n_terms
+    batch = api.Batch(jobs32)
+    energies = torch.zeros(3 * len(jobs32), dtype=torch.float64, device=dev)
+    for _ in range(args.warmup):
+        batch.run(energies)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        batch.run(energies)
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / args.steps
+
+    def per_job():
+        for G, sp, psi, out in jobs64:
+            api.apply_pauli_sum(G, sp, psi, out=out)
+    for _ in range(args.warmup):
+        per_job()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        per_job()
+    torch.cuda.synchronize()
+    t_single = (time.perf_counter() - t0) / args.steps
+    # accuracy of the batched complex64 results against FP64 on the same input
+    worst = 0.0
+    for (G, sp, p32, o32) in jobs32:
+        ref = api.apply_pauli_sum(G, sp, p32.to(torch.complex128))
+        worst = max(worst, (torch.linalg.vector_norm(o32.to(torch.complex128) - ref) /
+                            torch.linalg.vector_norm(ref)).item())
+    line = {
+        "metric": "batched H|psi> amplitude*terms/s (64 jobs, complex64 storage, float64 accumulation)",
+        "value": work / t_batch, "unit": "amplitude*terms/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": t_batch * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "batched-64", "jobs": len(jobs32), "amplitude_terms": work,
+                   "dims": [j[1].dim for j in jobs32]},
+        "ms_per_job_fp64_launches": t_single * 1e3,
+        "speedup_batched_c64_vs_per_job_fp64": t_single / t_batch,
+        "max_rel_err_c64_vs_fp64_same_input": worst,
+    }
+    print(json.dumps(line))
+
+
+def bench_krylov(args):
+    """4x4 periodic Hubbard (U = 4), (8, 8) sector: short-iterative Lanczos
+    steps (12 vectors, dt = 0.05) from the Neel state, complex64 and complex128."""
+    import torch
+
+    import synth
+    from paper_2606_28952_amd import api
+
+    dev = torch.device("cuda:0")
+    h1, h2 = synth.hubbard_spin_integrals(4, 4, t=1.0, u=4.0)
+    G = api.jw_transform(torch.from_numpy(h1).to(dev), torch.from_numpy(h2).to(dev)).group()
+    sp = api.Space.sector(16, 8, 8)
+    na, nb = synth.neel_occupations(4, 4)
+    start = sp.rank(torch.tensor([na | (nb << 16)], dtype=torch.int64, device=dev)).item()
+    res = {}
+    for name, dtype in (("c64", torch.complex64), ("c128", torch.complex128)):
+        psi = torch.zeros(sp.dim, dtype=dtype, device=dev)
+        psi[start] = 1.0
+        prop = api.KrylovPropagator(G, sp, dtype=dtype, m=12)
+        energies, norms = [], []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.krylov_steps):
+            info = prop.step(psi, 0.05)
+            norms.append(info[0])
+            energies.append(info[1])
+        torch.cuda.synchronize()
+        dt_total = time.perf_counter() - t0
+        res[name] = {"seconds": dt_total, "ms_per_step": dt_total * 1e3 / args.krylov_steps,
+                     "norm_drift": max(abs(n - 1.0) for n in norms),
+                     "energy_drift": max(energies) - min(energies), "energy0": energies[0], "psi": psi}
+        del prop
+    diff = (torch.linalg.vector_norm(res["c64"]["psi"].to(torch.complex128) - res["c128"]["psi"]) /
+            torch.linalg.vector_norm(res["c128"]["psi"])).item()
+    for r in res.values():
+        r.pop("psi")
+    print(json.dumps({"workload": "hubbard-32q-krylov", "steps": args.krylov_steps, "dt": 0.05, "vectors": 12,
+                      "dim": sp.dim, "c64": res["c64"], "c128": res["c128"],
+                      "final_state_rel_diff_c64_vs_c128": diff}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="molecular-28q-sector", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="molecular-28q-sector",
+                    choices=sorted(WORKLOADS) + ["batched-64", "hubbard-krylov"])
+    ap.add_argument("--krylov-steps", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--apply-only", type=int, default=0,
                     help="profiling mode: run only N sector applies (complex64) after setup, print nothing else")
@@ -123,6 +242,11 @@ def main():
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); this path has no multi-GPU mode.",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "batched-64":
+        return bench_batched(args)
+    if args.workload == "hubbard-krylov":
+        return bench_krylov(args)
 
     import torch
 

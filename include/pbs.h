@@ -78,6 +78,7 @@ typedef enum { PBS_C128 = 0, PBS_C64 = 1 } pbs_dtype;
 typedef struct pbs_sum pbs_sum;         /* Pauli sum: strings + letter-form coefficients */
 typedef struct pbs_grouped pbs_grouped; /* sum grouped by X-mask, kernel tables */
 typedef struct pbs_space pbs_space;     /* configuration space (full or spin sector) */
+typedef struct pbs_batch pbs_batch;     /* prepared launch of many operator-state products */
 
 /* Message describing the calling thread's last failure ("" after success). */
 const char* pbs_last_error(void);
@@ -136,7 +137,7 @@ pbs_status pbs_pauli_sum_mul(const pbs_sum* a, const pbs_sum* b, double eps_drop
  * Each integral with |h| > eps expands into its 4 or 16 Pauli strings and
  * phase-corrected coefficients by the product rule; the contributions are
  * reduced to canonical form.
- *  n_spin_orb  1..256 (qubits).
+ *  n_spin_orb  1..255 (qubits).
  *  h1          device, n^2 doubles, row-major [P][Q].
  *  h2          device, n^4 doubles, row-major [P][Q][R][S] (may be NULL = 0).
  * Output: new canonical sum.  Synchronizes. */
@@ -215,6 +216,31 @@ pbs_status pbs_expval_workspace_bytes(const pbs_space* sp, uint64_t* bytes);
  * least pbs_expval_workspace_bytes.  Asynchronous; allocates nothing. */
 pbs_status pbs_expval(const pbs_grouped* h, const pbs_space* sp, pbs_dtype dt, const void* psi, double* result,
                       void* work, uint64_t work_bytes, void* stream);
+
+/* ------------------------------------------------------------------ batched apply */
+
+/* Prepares one launch that applies n operators to n states in spin sectors:
+ * job i computes out[i] = P h[i] P psi[i] on sp[i] exactly as
+ * pbs_apply_pauli_sum does (target-driven summation, Eq. sreverse_sum), with
+ * every job's workgroups in a single grid (largest jobs first).  Sectors may
+ * differ in size and shape, and each job has its own operator.
+ *  h, sp, psi, out  host arrays of n handles / device pointers; all states
+ *                   have storage type dt; out[i] must not overlap psi[i] or
+ *                   any other job's output.  The pointers are recorded: the
+ *                   batch always runs on these buffers.
+ * Allocates the job table and a partial-sum buffer once.  Synchronizes. */
+pbs_status pbs_batch_create(uint32_t n, const pbs_grouped* const* h, const pbs_space* const* sp, pbs_dtype dt,
+                            const void* const* psi, void* const* out, pbs_batch** batch);
+
+/* Runs a prepared batch on the stream.  With energies == NULL only the
+ * products are written; otherwise the same single pass also writes, for each
+ * job i, energies[3i..3i+2] = (Re <psi|H|psi>, Im <psi|H|psi>, <psi|psi>)
+ * accumulated in float64 (device array of 3n doubles).  Asynchronous;
+ * allocates nothing and may be captured in a HIP graph.  Two runs of one
+ * batch must not overlap in time (they share the partial-sum buffer). */
+pbs_status pbs_batch_run(const pbs_batch* b, double* energies, void* stream);
+
+void pbs_batch_destroy(pbs_batch* b);
 
 /* ------------------------------------------------------------------ propagation */
 

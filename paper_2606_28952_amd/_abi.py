@@ -44,6 +44,9 @@ SIGNATURES = {
     "pbs_apply_pauli_sum": (c_int32, [_vp, _vp, c_int32, _vp, _vp, _vp]),
     "pbs_expval_workspace_bytes": (c_int32, [_vp, POINTER(c_uint64)]),
     "pbs_expval": (c_int32, [_vp, _vp, c_int32, _vp, _vp, _vp, c_uint64, _vp]),
+    "pbs_batch_create": (c_int32, [c_uint32, _vp, _vp, c_int32, _vp, _vp, POINTER(_vp)]),
+    "pbs_batch_run": (c_int32, [_vp, _vp, _vp]),
+    "pbs_batch_destroy": (None, [_vp]),
     "pbs_krylov_workspace_bytes": (c_int32, [_vp, c_int32, c_uint32, POINTER(c_uint64)]),
     "pbs_krylov_step": (c_int32, [_vp, _vp, c_int32, _vp, c_double, c_uint32, _vp, c_uint64, _vp, _vp]),
 }

@@ -17,7 +17,7 @@ from ._abi import PBS_C64, PBS_C128, call
 
 __all__ = [
     "PauliSum", "Grouped", "Space", "pauli_mul", "jw_transform", "apply_pauli_sum", "expval",
-    "words_for", "PBS_C64", "PBS_C128", "KrylovPropagator",
+    "words_for", "PBS_C64", "PBS_C128", "KrylovPropagator", "Batch",
 ]
 
 
@@ -264,3 +264,38 @@ class KrylovPropagator:
         call("pbs_krylov_step", self.grouped._h, self.space._h, self.code, _ptr(psi), float(dt), self.m,
              _ptr(self.work), self.work.numel(), _ptr(self.info), _stream())
         return tuple(float(v) for v in self.info)
+
+
+class Batch:
+    """One launch applying job i's operator to job i's state (spin sectors).
+
+    jobs: list of (Grouped, Space, psi, out) with device state tensors of one
+    dtype; the tensors must stay alive (the batch records their pointers)."""
+
+    def __init__(self, jobs):
+        n = len(jobs)
+        self._keep = jobs
+        code = _dtype_code(jobs[0][2])
+        hs = (c_void_p * n)(*[j[0]._h.value for j in jobs])
+        sps = (c_void_p * n)(*[j[1]._h.value for j in jobs])
+        ps = (c_void_p * n)(*[j[2].data_ptr() for j in jobs])
+        os_ = (c_void_p * n)(*[j[3].data_ptr() for j in jobs])
+        for j in jobs:
+            if _dtype_code(j[2]) != code or _dtype_code(j[3]) != code:
+                raise TypeError("all batch states must share one dtype")
+        out = c_void_p()
+        call("pbs_batch_create", n, hs, sps, code, ps, os_, byref(out))
+        self._h = out
+        self.n = n
+
+    def run(self, energies=None):
+        """Applies every job; with a float64 device tensor of 3n, also writes
+        each job's (Re E, Im E, <psi|psi>) from the same pass."""
+        call("pbs_batch_run", self._h, _ptr(energies), _stream())
+        return energies
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _abi._LIB is not None:
+            _abi._LIB.pbs_batch_destroy(h)
+            self._h = None

@@ -246,11 +246,12 @@ __device__ inline void ld_amp(const T* p, uint64_t i, double& r, double& m) {
   Amp<T>::load(p, i, r, m);
 }
 
-// One workgroup: target alpha string ia (one row of the state), kSB beta
-// columns, one target per lane.  See the file header for the scheme.
+// One workgroup: target alpha string ia (one row of the state), beta columns
+// chunk*kSB .. chunk*kSB + kSB - 1, one target per lane.  See the file header
+// for the scheme.  `slot` receives the workgroup's energy partials.
 template <class T, bool EXPVAL, bool R16, bool ROWLDS>
-__global__ __launch_bounds__(kSB) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_apply_sector(SectorArgs P, const T* __restrict__ psi, T* __restrict__ out,
-                                                      double* __restrict__ partial) {
+__device__ __forceinline__ void sector_body(const SectorArgs& P, const T* __restrict__ psi, T* __restrict__ out,
+                                            double* __restrict__ slot, uint64_t ia, uint32_t chunk) {
   extern __shared__ __align__(16) unsigned char smem[];
   uint16_t* s_rank = reinterpret_cast<uint16_t*>(smem + P.off_rank);
   T* s_row = reinterpret_cast<T*>(smem + P.off_row);
@@ -269,8 +270,7 @@ __global__ __launch_bounds__(kSB) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
   __syncthreads();
 
   const uint32_t db = P.dim_beta;
-  const uint64_t ia = blockIdx.x;
-  const uint32_t col = blockIdx.y * kSB + threadIdx.x;
+  const uint32_t col = chunk * kSB + threadIdx.x;
   const bool live = col < db;
   const uint32_t colc = live ? col : 0u;  // in-bounds column for idle lanes
   const uint32_t ta = P.str_a[ia];
@@ -495,7 +495,71 @@ __global__ __launch_bounds__(kSB) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
       Amp<T>::store(out, t, acc_r, acc_i);
     }
   }
-  if (EXPVAL) block_reduce3_store<kSB>(e_re, e_im, nrm, partial + 3ull * (blockIdx.y * gridDim.x + blockIdx.x));
+  if (EXPVAL) block_reduce3_store<kSB>(e_re, e_im, nrm, slot);
+}
+
+template <class T, bool EXPVAL, bool R16, bool ROWLDS>
+__global__ __launch_bounds__(kSB) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_apply_sector(
+    SectorArgs P, const T* __restrict__ psi, T* __restrict__ out, double* __restrict__ partial) {
+  sector_body<T, EXPVAL, R16, ROWLDS>(P, psi, out, partial + 3ull * (blockIdx.y * gridDim.x + blockIdx.x),
+                                      blockIdx.x, blockIdx.y);
+}
+
+// A job of a batched launch: one operator on one sector state.
+struct BatchJob {
+  SectorArgs args;
+  const void* psi;
+  void* out;
+  uint32_t block_base;  // first workgroup of the job
+  uint32_t chunks;      // beta-column chunks per row
+  uint64_t pad;
+};
+
+template <class X>
+__device__ inline X ld_words(const X* p) {
+  static_assert(sizeof(X) % 4 == 0, "word-sized record");
+  constexpr int kW = sizeof(X) / 4;
+  const uint32_t* q = reinterpret_cast<const uint32_t*>(p);
+  uint32_t w[kW];
+#pragma unroll
+  for (int i = 0; i < kW; ++i) w[i] = ldc(q + i);
+  X v;
+  memcpy(&v, w, sizeof(v));
+  return v;
+}
+
+// All jobs of a batch in one launch: workgroup b belongs to the job with the
+// largest block_base <= b (jobs are stored in block order).
+template <class T, bool EXPVAL, bool R16, bool ROWLDS>
+__global__ __launch_bounds__(kSB) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_apply_sector_batch(
+    const BatchJob* __restrict__ jobs, uint32_t n_jobs, double* __restrict__ partial) {
+  uint32_t lo = 0, hi = n_jobs;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) / 2;
+    if (ldc(&jobs[mid].block_base) <= blockIdx.x)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  const BatchJob J = ld_words(jobs + lo);
+  const uint32_t b = blockIdx.x - J.block_base;
+  sector_body<T, EXPVAL, R16, ROWLDS>(J.args, static_cast<const T*>(J.psi), static_cast<T*>(J.out),
+                                      partial + 3ull * blockIdx.x, b / J.chunks, b % J.chunks);
+}
+
+// Per-job sums of workgroup partials (one workgroup per job, fixed order).
+__global__ __launch_bounds__(kBlock) void k_batch_finish(const BatchJob* jobs, uint32_t n_jobs, uint32_t total_blocks,
+                                                         const double* partial, double* result) {
+  const uint32_t j = blockIdx.x;
+  const uint32_t b0 = jobs[j].block_base;
+  const uint32_t b1 = j + 1 < n_jobs ? jobs[j + 1].block_base : total_blocks;
+  double a = 0, b = 0, c = 0;
+  for (uint32_t i = b0 + threadIdx.x; i < b1; i += kBlock) {
+    a += partial[3ull * i];
+    b += partial[3ull * i + 1];
+    c += partial[3ull * i + 2];
+  }
+  block_reduce3_store<kBlock>(a, b, c, result + 3ull * jobs[j].pad);
 }
 
 // Sums per-workgroup partials in a fixed order (deterministic).
@@ -530,7 +594,8 @@ int device_lds_limit() {
 }
 
 // Fills the sector kernel's arguments and LDS layout for this operator/space.
-Launch plan_sector(const pbs_grouped& h, const pbs_space& sp, size_t elem_bytes, SectorArgs* a_out, bool* r16) {
+Launch plan_sector(const pbs_grouped& h, const pbs_space& sp, size_t elem_bytes, bool allow_row, SectorArgs* a_out,
+                   bool* r16) {
   SectorArgs a{};
   a.n_orb = sp.n_orb;
   a.n_alpha = sp.n_alpha;
@@ -563,7 +628,7 @@ Launch plan_sector(const pbs_grouped& h, const pbs_space& sp, size_t elem_bytes,
                   : 0u;
   const uint32_t pu_bytes = a.enum_ok ? align16((h.n_pairs + 1) * 4) : 0u;
   const uint64_t row_bytes = sp.dim_beta * elem_bytes;
-  a.row_lds = (row_bytes <= kRowCapBytes && rank_bytes + f_bytes + pu_bytes + row_bytes <= limit) ? 1u : 0u;
+  a.row_lds = (allow_row && row_bytes <= kRowCapBytes && rank_bytes + f_bytes + pu_bytes + row_bytes <= limit) ? 1u : 0u;
   uint32_t off = 0;
   a.off_rank = off;
   off += rank_bytes;
@@ -617,7 +682,7 @@ void launch(const pbs_grouped& h, const pbs_space& sp, const void* psi, void* ou
   } else {
     SectorArgs a;
     bool r16 = false;
-    const Launch L = plan_sector(h, sp, sizeof(T), &a, &r16);
+    const Launch L = plan_sector(h, sp, sizeof(T), true, &a, &r16);
     auto kern = r16 ? (a.row_lds ? k_apply_sector<T, EXPVAL, true, true> : k_apply_sector<T, EXPVAL, true, false>)
                     : (a.row_lds ? k_apply_sector<T, EXPVAL, false, true> : k_apply_sector<T, EXPVAL, false, false>);
     if (L.lds > 64 * 1024)
@@ -686,5 +751,141 @@ pbs_status pbs_expval(const pbs_grouped* h, const pbs_space* sp, pbs_dtype dt, c
     PBS_HIP(hipGetLastError());
   });
 }
+
+}  // extern "C"
+
+struct pbs_batch {
+  uint32_t n_jobs = 0;
+  uint32_t total_blocks = 0;
+  pbs_dtype dt = PBS_C64;
+  bool r16 = false, row_lds = false;
+  size_t lds = 0;
+  pbs::DevBuf<pbs::BatchJob> jobs;
+  pbs::DevBuf<double> partial;
+};
+
+namespace pbs {
+namespace {
+template <class T, bool EXPVAL>
+void* batch_kernel(bool r16, bool rowlds) {
+  if (r16)
+    return rowlds ? reinterpret_cast<void*>(k_apply_sector_batch<T, EXPVAL, true, true>)
+                  : reinterpret_cast<void*>(k_apply_sector_batch<T, EXPVAL, true, false>);
+  return rowlds ? reinterpret_cast<void*>(k_apply_sector_batch<T, EXPVAL, false, true>)
+                : reinterpret_cast<void*>(k_apply_sector_batch<T, EXPVAL, false, false>);
+}
+
+void* pick_batch_kernel(pbs_dtype dt, bool expval, bool r16, bool rowlds) {
+  if (dt == PBS_C128) return expval ? batch_kernel<double2, true>(r16, rowlds) : batch_kernel<double2, false>(r16, rowlds);
+  return expval ? batch_kernel<float2, true>(r16, rowlds) : batch_kernel<float2, false>(r16, rowlds);
+}
+}  // namespace
+}  // namespace pbs
+
+extern "C" {
+
+pbs_status pbs_batch_create(uint32_t n, const pbs_grouped* const* h, const pbs_space* const* sp, pbs_dtype dt,
+                            const void* const* psi, void* const* out, pbs_batch** batch) {
+  return guarded([&] {
+    PBS_REQUIRE(batch != nullptr, PBS_ERR_ARG, "null output handle");
+    *batch = nullptr;
+    PBS_REQUIRE(n >= 1 && h && sp && psi && out, PBS_ERR_ARG, "empty batch or null array");
+    const size_t esz = dt == PBS_C128 ? 16 : 8;
+    std::vector<BatchJob> jobs(n);
+    std::vector<double> cost(n);
+    std::vector<uint32_t> order(n);
+    for (uint32_t i = 0; i < n; ++i) {
+      validate(h[i], sp[i], dt);
+      PBS_REQUIRE(sp[i]->sector, PBS_ERR_UNSUPPORTED, "batched apply runs on spin-sector spaces");
+      PBS_REQUIRE(psi[i] && out[i], PBS_ERR_ARG, "null state pointer in job " + std::to_string(i));
+      const uint64_t bytes = sp[i]->dim * esz;
+      const auto a = reinterpret_cast<uintptr_t>(psi[i]), b = reinterpret_cast<uintptr_t>(out[i]);
+      PBS_REQUIRE(a + bytes <= b || b + bytes <= a, PBS_ERR_ARG, "out overlaps psi in job " + std::to_string(i));
+    }
+    for (uint32_t i = 0; i < n; ++i) {  // outputs of different jobs must not overlap
+      const uint64_t bi = sp[i]->dim * esz;
+      for (uint32_t j = i + 1; j < n; ++j) {
+        const uint64_t bj = sp[j]->dim * esz;
+        const auto x = reinterpret_cast<uintptr_t>(out[i]), y = reinterpret_cast<uintptr_t>(out[j]);
+        PBS_REQUIRE(x + bi <= y || y + bj <= x, PBS_ERR_ARG, "outputs of jobs overlap");
+      }
+    }
+    // one launch shares one kernel variant: rows staged only if every job's
+    // row fits, LDS rank tables only if every job has n_orb <= 16
+    bool r16 = true, rowlds = true;
+    for (uint32_t i = 0; i < n; ++i) {
+      bool job_r16 = false;
+      plan_sector(*h[i], *sp[i], esz, true, &jobs[i].args, &job_r16);
+      r16 = r16 && job_r16;
+      rowlds = rowlds && jobs[i].args.row_lds;
+    }
+    size_t lds = 0;
+    for (uint32_t i = 0; i < n; ++i) {
+      bool job_r16 = false;
+      const Launch L = plan_sector(*h[i], *sp[i], esz, rowlds, &jobs[i].args, &job_r16);
+      if (!r16) jobs[i].args.rank16 = nullptr;
+      jobs[i].psi = psi[i];
+      jobs[i].out = out[i];
+      jobs[i].chunks = L.grid.y;
+      jobs[i].block_base = 0;
+      jobs[i].pad = i;  // original position (energies are written there)
+      lds = std::max(lds, L.lds);
+      cost[i] = static_cast<double>(sp[i]->dim) * static_cast<double>(h[i]->n_pterm + 1);
+      order[i] = i;
+    }
+    // largest jobs first, so the launch does not end on a long straggler
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return cost[a] > cost[b]; });
+    std::vector<BatchJob> sorted(n);
+    uint64_t base = 0;
+    for (uint32_t k = 0; k < n; ++k) {
+      BatchJob J = jobs[order[k]];
+      J.block_base = static_cast<uint32_t>(base);
+      base += static_cast<uint64_t>(sp[order[k]]->dim_alpha) * J.chunks;
+      sorted[k] = J;
+    }
+    PBS_REQUIRE(base < (1ull << 31), PBS_ERR_RANGE, "batch needs more than 2^31 workgroups");
+    auto* B = new pbs_batch();
+    try {
+      B->n_jobs = n;
+      B->total_blocks = static_cast<uint32_t>(base);
+      B->dt = dt;
+      B->r16 = r16;
+      B->row_lds = rowlds;
+      B->lds = lds;
+      B->jobs.alloc(n);
+      B->partial.alloc(3ull * base);
+      PBS_HIP(hipMemcpy(B->jobs.get(), sorted.data(), n * sizeof(BatchJob), hipMemcpyHostToDevice));
+      if (lds > 64 * 1024) {
+        for (bool ev : {false, true})
+          PBS_HIP(hipFuncSetAttribute(pick_batch_kernel(dt, ev, r16, rowlds),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
+      }
+    } catch (...) {
+      delete B;
+      throw;
+    }
+    *batch = B;
+  });
+}
+
+pbs_status pbs_batch_run(const pbs_batch* b, double* energies, void* stream) {
+  return guarded([&] {
+    PBS_REQUIRE(b != nullptr, PBS_ERR_ARG, "null pbs_batch");
+    hipStream_t s = as_stream(stream);
+    const bool ev = energies != nullptr;
+    void* kern = pick_batch_kernel(b->dt, ev, b->r16, b->row_lds);
+    const BatchJob* jobs = b->jobs.get();
+    uint32_t n = b->n_jobs;
+    double* partial = b->partial.get();
+    void* args[] = {&jobs, &n, &partial};
+    PBS_HIP(hipLaunchKernel(kern, dim3(b->total_blocks), dim3(kSB), args, b->lds, s));
+    if (ev) {
+      hipLaunchKernelGGL(k_batch_finish, dim3(n), dim3(kBlock), 0, s, jobs, n, b->total_blocks, partial, energies);
+      PBS_HIP(hipGetLastError());
+    }
+  });
+}
+
+void pbs_batch_destroy(pbs_batch* b) { delete b; }
 
 }  // extern "C"

@@ -1,0 +1,116 @@
+"""GPU tests of the batched launch (pbs_batch_*): parity with single launches
+and with the oracle, fused energies, and replay inside a captured HIP graph."""
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import apply as oapply
+from oracle import jw as ojw
+from oracle import space as ospace
+from tests.conftest import rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+def _api():
+    from paper_2606_28952_amd import api
+
+    return api
+
+
+# (n_orb, N_alpha, N_beta, integral seed, state seed): uneven sectors, own operators
+JOBS = [(4, 2, 2, 11, 21), (5, 2, 3, 12, 22), (6, 3, 3, 13, 23), (7, 3, 2, 14, 24), (6, 1, 4, 15, 25),
+        (7, 4, 3, 16, 26), (3, 1, 1, 17, 27), (8, 4, 4, 18, 28)]
+
+
+def _build(dev, dtype):
+    api = _api()
+    jobs, refs = [], []
+    for n_o, na, nb, hs, ps in JOBS:
+        h1, h2 = synth.molecular_spin_integrals(n_o, hs)
+        G = api.jw_transform(torch.from_numpy(h1).to(dev), torch.from_numpy(h2).to(dev)).group()
+        sp = api.Space.sector(n_o, na, nb)
+        psi_np = synth.random_state(sp.dim, ps)
+        if dtype == torch.complex64:
+            psi_np = psi_np.astype(np.complex64).astype(np.complex128)
+        psi = torch.from_numpy(psi_np).to(dev).to(dtype)
+        out = torch.empty_like(psi)
+        jobs.append((G, sp, psi, out))
+        refs.append((h1, h2, n_o, na, nb, psi_np))
+    return jobs, refs
+
+
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+def test_batch_matches_single_launches_and_oracle(dev, dtype):
+    api = _api()
+    jobs, refs = _build(dev, dtype)
+    batch = api.Batch(jobs)
+    energies = torch.zeros(3 * len(jobs), dtype=torch.float64, device=dev)
+    batch.run()
+    torch.cuda.synchronize()
+    outs = [j[3].clone() for j in jobs]
+    batch.run(energies)
+    torch.cuda.synchronize()
+    e = energies.cpu().numpy().reshape(-1, 3)
+    for k, ((G, sp, psi, out), (h1, h2, n_o, na, nb, psi_np)) in enumerate(zip(jobs, refs)):
+        single = api.apply_pauli_sum(G, sp, psi)
+        assert torch.equal(torch.view_as_real(single), torch.view_as_real(outs[k])), f"job {k} differs from single"
+        assert torch.equal(torch.view_as_real(out), torch.view_as_real(outs[k])), f"job {k} differs between runs"
+        ref = oapply.apply_scatter(ojw.jw_sum(h1, h2), ospace.SectorSpace(n_o, na, nb), psi_np)
+        tol = 1e-12 if dtype == torch.complex128 else 1e-6
+        assert rel_err(out.cpu().numpy(), ref) < tol
+        e_ref = np.vdot(psi_np, ref)
+        assert abs(e[k, 0] - e_ref.real) < 1e-11 * max(1.0, abs(e_ref))
+        assert abs(e[k, 2] - np.vdot(psi_np, psi_np).real) < 1e-12
+        ev_single = api.expval(G, sp, psi).cpu().numpy()
+        assert abs(ev_single[0] - e[k, 0]) < 1e-12 * max(1.0, abs(e_ref))
+
+
+def test_batch_graph_replay(dev):
+    api = _api()
+    jobs, _ = _build(dev, torch.complex64)
+    batch = api.Batch(jobs)
+    energies = torch.zeros(3 * len(jobs), dtype=torch.float64, device=dev)
+    batch.run(energies)
+    torch.cuda.synchronize()
+    eager_out = [j[3].clone() for j in jobs]
+    eager_e = energies.clone()
+    stream = torch.cuda.Stream()
+    graph = torch.cuda.CUDAGraph()
+    for j in jobs:
+        j[3].zero_()
+    with torch.cuda.stream(stream):
+        with torch.cuda.graph(graph, stream=stream):
+            batch.run(energies)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        for j in jobs:
+            j[3].zero_()          # eager work between replays
+        energies.zero_()
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        for k, j in enumerate(jobs):
+            assert torch.equal(torch.view_as_real(j[3]), torch.view_as_real(eager_out[k])), f"replay {rep} job {k}"
+        assert torch.equal(energies, eager_e), f"replay {rep} energies"
+
+
+def test_batch_rejects_bad_jobs(dev):
+    api = _api()
+    from paper_2606_28952_amd._abi import PbsError
+
+    jobs, _ = _build(dev, torch.complex128)
+    G, sp, psi, out = jobs[0]
+    with pytest.raises(PbsError, match="overlaps"):
+        api.Batch([(G, sp, psi, psi)])
+    with pytest.raises(PbsError, match="outputs of jobs overlap"):
+        api.Batch([(G, sp, psi, out), (G, sp, psi.clone(), out)])
+    with pytest.raises(PbsError, match="spin-sector"):
+        h1, h2 = synth.molecular_spin_integrals(3, 1)
+        Gf = api.jw_transform(torch.from_numpy(h1).to(dev), torch.from_numpy(h2).to(dev)).group()
+        x = torch.zeros(64, dtype=torch.complex128, device=dev)
+        api.Batch([(Gf, api.Space.full(6), x, torch.zeros_like(x))])
+    with pytest.raises(TypeError):
+        api.Batch([(G, sp, psi, out), (G, sp, psi.to(torch.complex64), out.to(torch.complex64))])
