@@ -234,6 +234,8 @@ def main():
     ap.add_argument("--workload", default="molecular-28q-sector",
                     choices=sorted(WORKLOADS) + ["batched-64", "hubbard-krylov"])
     ap.add_argument("--krylov-steps", type=int, default=200)
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="counter calibration: one device-to-device copy of this many bytes, nothing else")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--apply-only", type=int, default=0,
                     help="profiling mode: run only N sector applies (complex64) after setup, print nothing else")
@@ -243,6 +245,16 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    if args.copy_bytes:
+        import torch
+
+        src = torch.ones(args.copy_bytes // 4, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"copied {src.numel() * 4} bytes")
+        return
     if args.workload == "batched-64":
         return bench_batched(args)
     if args.workload == "hubbard-krylov":
@@ -278,8 +290,9 @@ def main():
 
     if args.apply_only:
         _, G, sp = build()
+        work0 = torch.empty(max(1, sp.workspace_bytes() // 8), dtype=torch.float64, device=dev)
         for _ in range(args.apply_only):
-            api.apply_pauli_sum(G, sp, psi32, out=out32)
+            api.expval(G, sp, psi32, work=work0, result=res, out=out32)
         torch.cuda.synchronize()
         print(f"apply-only done: {args.apply_only} launches")
         return
@@ -293,13 +306,13 @@ def main():
     del H, G, sp
 
     def step(ev0=None, ev1=None):
+        # H|psi> and <psi|H|psi> come from one fused pass of the sector kernel
         H, G, sp = build()
         if ev0 is not None:
             ev0.record()
-        api.apply_pauli_sum(G, sp, psi32, out=out32)
+        api.expval(G, sp, psi32, work=work, result=res, out=out32)
         if ev1 is not None:
             ev1.record()
-        api.expval(G, sp, psi32, work=work, result=res)
         return H, G, sp
 
     for _ in range(args.warmup):
@@ -363,7 +376,7 @@ def main():
         "data": "synthetic (seeded Gaussian integrals and states)",
         "config": {"workload": args.workload, "n_orb": n_orb, "n_alpha": na, "n_beta": nb, "dim": D,
                    "n_strings": M, "groups_connected_per_target": round(g_conn, 3), "storage": "complex64",
-                   "step": "jw_transform+group_by_xmask+space_sector+apply_pauli_sum+expval"},
+                   "step": "jw_transform+group_by_xmask+space_sector+fused(apply_pauli_sum+expval)"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
         "apply_ms_c64": c64_ms,

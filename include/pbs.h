@@ -212,10 +212,12 @@ pbs_status pbs_expval_workspace_bytes(const pbs_space* sp, uint64_t* bytes);
 /* Energy of Eq. vqe_energy: result[0..2] = (Re <psi|H|psi>, Im <psi|H|psi>,
  * <psi|psi>), with the operator-state gather of pbs_apply_pauli_sum fused
  * into a float64 reduction (the gathered H psi is never rounded to storage
- * precision).  result: device, 3 doubles; work: device workspace of at
- * least pbs_expval_workspace_bytes.  Asynchronous; allocates nothing. */
-pbs_status pbs_expval(const pbs_grouped* h, const pbs_space* sp, pbs_dtype dt, const void* psi, double* result,
-                      void* work, uint64_t work_bytes, void* stream);
+ * precision before the dot product).  When out is not NULL the same pass also
+ * stores H psi there (as pbs_apply_pauli_sum would; out must not overlap psi).
+ * result: device, 3 doubles; work: device workspace of at least
+ * pbs_expval_workspace_bytes.  Asynchronous; allocates nothing. */
+pbs_status pbs_expval(const pbs_grouped* h, const pbs_space* sp, pbs_dtype dt, const void* psi, void* out,
+                      double* result, void* work, uint64_t work_bytes, void* stream);
 
 /* ------------------------------------------------------------------ batched apply */
 

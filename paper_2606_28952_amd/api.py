@@ -226,21 +226,34 @@ def _dtype_code(t):
     raise TypeError(f"state must be complex64 or complex128, got {t.dtype}")
 
 
+def _check_states(space, psi, out):
+    """The C ABI takes bare pointers: check lengths, dtypes and devices here."""
+    code = _dtype_code(psi)
+    if psi.device.type != "cuda" or psi.numel() != space.dim:
+        raise ValueError(f"state must be a device vector of length {space.dim}")
+    if out is not None and (out.dtype != psi.dtype or out.numel() != psi.numel() or out.device != psi.device):
+        raise ValueError("out must match psi in dtype, length and device")
+    return code
+
+
 def apply_pauli_sum(grouped, space, psi, out=None):
     """out = P H P psi on the device (asynchronous on the current stream)."""
+    _check_states(space, psi, out)
     if out is None:
         out = torch.empty_like(psi)
     call("pbs_apply_pauli_sum", grouped._h, space._h, _dtype_code(psi), _ptr(psi), _ptr(out), _stream())
     return out
 
 
-def expval(grouped, space, psi, work=None, result=None):
-    """(Re <psi|H|psi>, Im <psi|H|psi>, <psi|psi>) as a float64 device tensor of 3."""
+def expval(grouped, space, psi, work=None, result=None, out=None):
+    """(Re <psi|H|psi>, Im <psi|H|psi>, <psi|psi>) as a float64 device tensor of 3.
+    With ``out`` the same pass also stores H psi there."""
+    _check_states(space, psi, out)
     if work is None:
         work = torch.empty(max(1, space.workspace_bytes() // 8), dtype=torch.float64, device=psi.device)
     if result is None:
         result = torch.empty(3, dtype=torch.float64, device=psi.device)
-    call("pbs_expval", grouped._h, space._h, _dtype_code(psi), _ptr(psi), _ptr(result), _ptr(work),
+    call("pbs_expval", grouped._h, space._h, _dtype_code(psi), _ptr(psi), _ptr(out), _ptr(result), _ptr(work),
          work.numel() * 8, _stream())
     return result
 

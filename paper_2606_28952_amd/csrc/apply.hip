@@ -138,6 +138,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_full(uint64_t dim, uint32_t n_
       e_re = fma(pr, acc_r, fma(pi, acc_i, e_re));
       e_im = fma(pr, acc_i, fma(-pi, acc_r, e_im));
       nrm = fma(pr, pr, fma(pi, pi, nrm));
+      if (out) Amp<T>::store(out, t, acc_r, acc_i);
     } else {
       Amp<T>::store(out, t, acc_r, acc_i);
     }
@@ -733,20 +734,25 @@ pbs_status pbs_expval_workspace_bytes(const pbs_space* sp, uint64_t* bytes) {
   });
 }
 
-pbs_status pbs_expval(const pbs_grouped* h, const pbs_space* sp, pbs_dtype dt, const void* psi, double* result,
-                      void* work, uint64_t work_bytes, void* stream) {
+pbs_status pbs_expval(const pbs_grouped* h, const pbs_space* sp, pbs_dtype dt, const void* psi, void* out,
+                      double* result, void* work, uint64_t work_bytes, void* stream) {
   return guarded([&] {
     validate(h, sp, dt);
     PBS_REQUIRE(psi != nullptr && result != nullptr && work != nullptr, PBS_ERR_ARG, "null pointer");
+    if (out) {
+      const uint64_t bytes = sp->dim * (dt == PBS_C128 ? 16ull : 8ull);
+      const auto a = reinterpret_cast<uintptr_t>(psi), b = reinterpret_cast<uintptr_t>(out);
+      PBS_REQUIRE(a + bytes <= b || b + bytes <= a, PBS_ERR_ARG, "out overlaps psi");
+    }
     const uint64_t need = partial_count(*sp) * 3 * sizeof(double);
     PBS_REQUIRE(work_bytes >= need, PBS_ERR_ARG,
                 "workspace of " + std::to_string(work_bytes) + " bytes, need " + std::to_string(need));
     hipStream_t s = as_stream(stream);
     double* partial = static_cast<double*>(work);
     if (dt == PBS_C128)
-      launch<double2, true>(*h, *sp, psi, nullptr, partial, s);
+      launch<double2, true>(*h, *sp, psi, out, partial, s);
     else
-      launch<float2, true>(*h, *sp, psi, nullptr, partial, s);
+      launch<float2, true>(*h, *sp, psi, out, partial, s);
     hipLaunchKernelGGL(k_expval_finish, dim3(1), dim3(kBlock), 0, s, partial, partial_count(*sp), result);
     PBS_HIP(hipGetLastError());
   });

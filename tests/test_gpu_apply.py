@@ -80,7 +80,11 @@ def test_twelve_qubit_molecular_full_and_sector(dev):
         psi32 = psi.astype(np.complex64)
         ref32 = oapply.apply_scatter(op, ospace_, psi32.astype(np.complex128))
         assert rel_err(_run(dev, G, space, psi32, np.complex64), ref32) < 1e-6
-        e = api.expval(G, space, torch.from_numpy(psi).to(dev)).cpu().numpy()
+        tpsi = torch.from_numpy(psi).to(dev)
+        fused = torch.empty_like(tpsi)
+        e = api.expval(G, space, tpsi, out=fused).cpu().numpy()
+        # the fused pass stores exactly what the plain apply stores
+        assert torch.equal(torch.view_as_real(fused), torch.view_as_real(api.apply_pauli_sum(G, space, tpsi)))
         e_ref = np.vdot(psi, ref)
         assert abs(e[0] - e_ref.real) < 1e-12 * abs(e_ref) and abs(e[1]) < 1e-12 * abs(e_ref)
         assert abs(e[2] - 1.0) < 1e-13
@@ -183,6 +187,8 @@ def test_argument_errors(dev):
     with pytest.raises(PbsError, match="workspace"):
         work = torch.zeros(1, dtype=torch.float64, device=dev)
         api.expval(G, sp, psi, work=work)
+    with pytest.raises(PbsError, match="overlaps"):
+        api.expval(G, sp, psi, out=psi)
 
 
 def _sampled_targets(rng, dim, k, extra=()):
@@ -224,7 +230,9 @@ def test_28_qubit_sector_sampled(dev):
     e = api.expval(G, sp, tpsi).cpu().numpy()
     e_dot = torch.vdot(tpsi, out).item()
     assert abs(e[0] - e_dot.real) < 1e-11 * abs(e_dot) and abs(e[1]) < 1e-11 * abs(e_dot)
-    e32 = api.expval(G, sp, t32).cpu().numpy()
+    fused32 = torch.empty_like(t32)
+    e32 = api.expval(G, sp, t32, out=fused32).cpu().numpy()
+    assert torch.equal(torch.view_as_real(fused32), torch.view_as_real(out32))
     h32 = api.apply_pauli_sum(G, sp, t32.to(torch.complex128))
     e32_dot = torch.vdot(t32.to(torch.complex128), h32).item()
     assert abs(e32[0] - e32_dot.real) < 1e-11 * abs(e32_dot)
