@@ -151,12 +151,14 @@ constexpr int kSB = 512;              // lanes per sector workgroup = beta colum
 constexpr int kMaxMoves = 56;         // pair moves cached per lane (N_beta (n_orb - N_beta) <= 56)
 constexpr uint32_t kFCap = 1536;      // folded uniques held in LDS at once (+1 zero slot)
 constexpr uint32_t kRowCapBytes = 64u * 1024u;
+constexpr uint32_t kListMinBytes = 4096u;  // simple-class row list when no row is staged
 
 struct SectorArgs {
   uint32_t n_orb, n_alpha, n_beta, n_chunks;
   uint32_t dim_beta;
   uint32_t n_class, n_pairs, n_moves;
   uint32_t row_lds, enum_ok;
+  uint32_t list_cap;  // entries of the simple-class row list (in the row space)
   uint32_t off_rank, off_row, off_f, off_fz, off_pu;  // LDS byte offsets
   const uint32_t* str_a;
   const uint32_t* str_b;
@@ -247,6 +249,65 @@ __device__ inline void ld_amp(const T* p, uint64_t i, double& r, double& m) {
   Amp<T>::load(p, i, r, m);
 }
 
+// One group of a scanned chunk: validity of X_beta for this lane's target,
+// source column rank, phase sum from the folded uniques; invalid targets are
+// predicated off (column 0 is read, the coefficient is zeroed).
+template <bool R16, class T>
+__device__ __forceinline__ void scan_group(const SectorArgs& P, uint32_t g, uint32_t us, uint32_t tb,
+                                           const uint16_t* s_rank, const double2* s_F, const uint32_t* s_Fz,
+                                           const T* rowp, double& acc_r, double& acc_i) {
+  const uint32_t xb = ldc(P.pg_xb + g);
+  const uint32_t u0 = ldc(P.pg_u0 + g), u1 = ldc(P.pg_u0 + g + 1);
+  const bool valid = 2u * __popc(tb & xb) == static_cast<uint32_t>(__popc(xb));
+  const uint32_t jb = valid ? rank_of<R16>(tb ^ xb, P, s_rank) : 0u;
+  double fr = 0.0, fi = 0.0;
+  phase_sum_lds(s_F, s_Fz, u0 - us, u1 - u0, tb, fr, fi);
+  double a_r, a_i;
+  ld_amp<T>(rowp, jb, a_r, a_i);
+  if (!valid) fr = fi = 0.0;
+  cmul_acc(fr, fi, a_r, a_i, acc_r, acc_i);
+}
+
+// Lists, in class order, the simple classes c0 .. c1-1 whose source alpha
+// string ta ^ X_alpha lies in the sector: entry = (source row rank, first
+// folded unique relative to ua | unique count << 16).  The list is padded to
+// a multiple of four with entries that read row 0 against the zero slot.
+// Returns the padded length; ends with the list visible to the workgroup.
+template <bool R16>
+__device__ uint32_t list_valid_rows(const SectorArgs& P, uint32_t c0, uint32_t c1, uint32_t ua, uint32_t ta,
+                                    const uint16_t* s_rank, uint2* s_list, uint32_t* s_wcnt) {
+  const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+  const uint64_t below = (1ull << lane) - 1ull;
+  uint32_t base = 0;
+  for (uint32_t i0 = c0; i0 < c1; i0 += kSB) {
+    const uint32_t cc = i0 + threadIdx.x;
+    bool v = false;
+    uint2 entry = make_uint2(0u, 0u);
+    if (cc < c1) {
+      const ClassMeta* m = P.meta + cc;
+      const uint32_t sa = ta ^ m->xa;
+      v = static_cast<uint32_t>(__popc(sa)) == P.n_alpha;
+      if (v) entry = make_uint2(rank_of<R16>(sa, P, s_rank), (m->ua - ua) | ((m->u_end - m->ua) << 16));
+    }
+    const uint64_t bal = __ballot(v);
+    if (lane == 0) s_wcnt[wave] = static_cast<uint32_t>(__popcll(bal));
+    __syncthreads();
+    uint32_t off = base, total = 0;
+    for (uint32_t w = 0; w < kSB / 64; ++w) {
+      const uint32_t n = s_wcnt[w];
+      off += w < wave ? n : 0u;
+      total += n;
+    }
+    if (v) s_list[off + static_cast<uint32_t>(__popcll(bal & below))] = entry;
+    base += total;
+    __syncthreads();
+  }
+  const uint32_t padded = (base + 3u) & ~3u;
+  if (threadIdx.x < padded - base) s_list[base + threadIdx.x] = make_uint2(0u, kFCap | (1u << 16));
+  __syncthreads();
+  return padded;
+}
+
 // One workgroup: target alpha string ia (one row of the state), beta columns
 // chunk*kSB .. chunk*kSB + kSB - 1, one target per lane.  See the file header
 // for the scheme.  `slot` receives the workgroup's energy partials.
@@ -259,6 +320,8 @@ __device__ __forceinline__ void sector_body(const SectorArgs& P, const T* __rest
   double2* s_F = reinterpret_cast<double2*>(smem + P.off_f);
   uint32_t* s_Fz = reinterpret_cast<uint32_t*>(smem + P.off_fz);
   uint32_t* s_pu = reinterpret_cast<uint32_t*>(smem + P.off_pu);
+  uint2* s_list = reinterpret_cast<uint2*>(smem + P.off_row);  // shares the staged row's space
+  __shared__ uint32_t s_wcnt[kSB / 64];
 
   if (R16) {
     const uint32_t n = P.n_chunks * (P.n_orb + 1) * 256;
@@ -313,11 +376,13 @@ __device__ __forceinline__ void sector_body(const SectorArgs& P, const T* __rest
   while (c < P.n_class) {
     const ClassMeta M = ld_meta(P.meta + c);
     if (M.flags & kClassSimple) {
-      // consecutive single-group classes share one cooperative fold
+      // consecutive single-group classes share one cooperative fold; their
+      // valid source rows are listed (in class order) in LDS and gathered
+      // four at a time so the row loads overlap
       const uint32_t ua = M.ua;
       uint32_t ce = c + 1;
       uint32_t ub = M.u_end;
-      while (ce < P.n_class) {
+      while (ce < P.n_class && ce - c + 3 < P.list_cap) {
         const ClassMeta N = ld_meta(P.meta + ce);
         if (!(N.flags & kClassSimple) || N.u_end - ua > kFCap) break;
         ub = N.u_end;
@@ -325,17 +390,24 @@ __device__ __forceinline__ void sector_body(const SectorArgs& P, const T* __rest
       }
       __syncthreads();
       fold_uniques(P, ua, ub, ta, s_F, s_Fz);
-      __syncthreads();
-      for (uint32_t cc = c; cc < ce; ++cc) {
-        const ClassMeta N = ld_meta(P.meta + cc);
-        const uint32_t sa = ta ^ N.xa;
-        if (static_cast<uint32_t>(__popc(sa)) != P.n_alpha) continue;
-        const uint64_t rowoff = static_cast<uint64_t>(rank_of<R16>(sa, P, s_rank)) * db;
-        double fr = 0.0, fi = 0.0;
-        phase_sum_lds(s_F, s_Fz, N.ua - ua, N.u_end - N.ua, tb, fr, fi);
-        double a_r, a_i;
-        ld_amp<T>(psi, rowoff + colc, a_r, a_i);
-        cmul_acc(fr, fi, a_r, a_i, ar4[cc & 3], ai4[cc & 3]);
+      const uint32_t n_list = list_valid_rows<R16>(P, c, ce, ua, ta, s_rank, s_list, s_wcnt);
+      for (uint32_t e0 = 0; e0 < n_list; e0 += 4) {
+        uint32_t rk[4], w[4];
+        double a_r[4], a_i[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const uint2 L = s_list[e0 + i];
+          rk[i] = __builtin_amdgcn_readfirstlane(L.x);
+          w[i] = __builtin_amdgcn_readfirstlane(L.y);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) ld_amp<T>(psi, static_cast<uint64_t>(rk[i]) * db + colc, a_r[i], a_i[i]);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          double fr = 0.0, fi = 0.0;
+          phase_sum_lds(s_F, s_Fz, w[i] & 0xffffu, w[i] >> 16, tb, fr, fi);
+          cmul_acc(fr, fi, a_r[i], a_i[i], ar4[i], ai4[i]);
+        }
       }
       c = ce;
       continue;
@@ -462,19 +534,12 @@ __device__ __forceinline__ void sector_body(const SectorArgs& P, const T* __rest
       __syncthreads();
       fold_uniques(P, us, P.pg_u0[ge], ta, s_F, s_Fz);
       __syncthreads();
-#pragma unroll 2
-      for (uint32_t g = gs; g < ge; ++g) {
-        const uint32_t xb = ldc(P.pg_xb + g);
-        const uint32_t u0 = ldc(P.pg_u0 + g), u1 = ldc(P.pg_u0 + g + 1);
-        const bool valid = 2u * __popc(tb & xb) == static_cast<uint32_t>(__popc(xb));
-        const uint32_t jb = valid ? rank_of<R16>(tb ^ xb, P, s_rank) : 0u;
-        double fr = 0.0, fi = 0.0;
-        phase_sum_lds(s_F, s_Fz, u0 - us, u1 - u0, tb, fr, fi);
-        double a_r, a_i;
-        ld_amp<T>(rowp, jb, a_r, a_i);
-        if (!valid) fr = fi = 0.0;
-        cmul_acc(fr, fi, a_r, a_i, ar4[2 + (g & 1)], ai4[2 + (g & 1)]);
+      uint32_t g = gs;
+      for (; g + 1 < ge; g += 2) {
+        scan_group<R16>(P, g, us, tb, s_rank, s_F, s_Fz, rowp, ar4[2], ai4[2]);
+        scan_group<R16>(P, g + 1, us, tb, s_rank, s_F, s_Fz, rowp, ar4[3], ai4[3]);
       }
+      if (g < ge) scan_group<R16>(P, g, us, tb, s_rank, s_F, s_Fz, rowp, ar4[2], ai4[2]);
       gs = ge;
     }
     ++c;
@@ -629,12 +694,15 @@ Launch plan_sector(const pbs_grouped& h, const pbs_space& sp, size_t elem_bytes,
                   : 0u;
   const uint32_t pu_bytes = a.enum_ok ? align16((h.n_pairs + 1) * 4) : 0u;
   const uint64_t row_bytes = sp.dim_beta * elem_bytes;
-  a.row_lds = (allow_row && row_bytes <= kRowCapBytes && rank_bytes + f_bytes + pu_bytes + row_bytes <= limit) ? 1u : 0u;
+  const uint64_t row_space = row_bytes > kListMinBytes ? row_bytes : kListMinBytes;
+  a.row_lds = (allow_row && row_bytes <= kRowCapBytes && rank_bytes + f_bytes + pu_bytes + row_space <= limit) ? 1u : 0u;
+  const uint32_t row_region = align16(static_cast<uint32_t>(a.row_lds ? row_space : kListMinBytes));
+  a.list_cap = row_region / 8u;
   uint32_t off = 0;
   a.off_rank = off;
   off += rank_bytes;
   a.off_row = off;
-  off += a.row_lds ? align16(static_cast<uint32_t>(row_bytes)) : 0u;
+  off += row_region;
   a.off_f = off;
   off += (kFCap + 1) * 16;
   a.off_fz = off;
