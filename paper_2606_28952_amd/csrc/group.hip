@@ -129,6 +129,13 @@ __global__ void k_plan_fill(const uint64_t* keys_soa, uint64_t ma, const uint32_
   }
 }
 
+// Flags any coefficient with a nonzero imaginary part.
+__global__ void k_any_imag(const double* c, uint64_t m, uint32_t* flag) {
+  for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < m;
+       i += static_cast<uint64_t>(gridDim.x) * blockDim.x)
+    if (c[2 * i + 1] != 0.0) atomicOr(flag, 1u);
+}
+
 // Per class: the X_beta = 0 group, the popcount-2 range, and whether the
 // class needs a pair-map row (flag written for a scan).
 __global__ void k_class_meta(uint32_t n_class, const uint32_t* cls_g0, const uint32_t* pg_pc, int32_t* zg,
@@ -218,6 +225,7 @@ static void build_sector_tables(pbs_grouped& g, const uint64_t* x, hipStream_t s
   g.n_pterm = static_cast<uint32_t>(ma);
   g.has_sector = true;
   if (ma == 0) {
+    g.real_coef = true;
     g.n_class = g.n_pgroup = g.n_unique = 0;
     g.n_pmap = 0;
     g.cls_g0.alloc(1);
@@ -266,7 +274,10 @@ static void build_sector_tables(pbs_grouped& g, const uint64_t* x, hipStream_t s
   hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, s, g.cls_g0.get() + g.n_class, g.n_pgroup);
   hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, s, g.pg_u0.get() + g.n_pgroup, g.n_unique);
   hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, s, g.u_t0.get() + g.n_unique, static_cast<uint32_t>(ma));
+  hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, s, cnt.get(), 0u);
+  hipLaunchKernelGGL(k_any_imag, dim3(grid_for(ma, 256, 65536)), dim3(256), 0, s, g.pt_c.get(), ma, cnt.get());
   PBS_HIP(hipGetLastError());
+  g.real_coef = read_scalar(cnt.get(), s) == 0u;
 
   // bucket metadata and the pair map
   g.cls_zg.alloc(g.n_class);

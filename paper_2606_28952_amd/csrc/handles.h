@@ -77,6 +77,7 @@ struct pbs_grouped {
   pbs::DevBuf<uint32_t> u_zb, u_t0;
   pbs::DevBuf<uint32_t> pt_za;
   pbs::DevBuf<double> pt_c;
+  bool real_coef = false;  // every sector-form coefficient has a zero imaginary part
 };
 
 // Full space (D = 2^n) or spin sector.

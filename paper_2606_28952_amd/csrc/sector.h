@@ -1,0 +1,642 @@
+// Device code of the operator-state product by target-driven summation over
+// X-mask groups (Section 2.4, Eq. reverse_sum) and, in spin sectors, over the
+// spin-resolved product basis (Eq. sreverse_sum); the fused energy of
+// Eq. vqe_energy.  Shared by the library's translation units; each sector
+// kernel variant is instantiated in exactly one of the sector_*.hip files.
+//
+// Every output amplitude is produced by exactly one thread, which gathers
+// the source amplitudes psi[t ^ X_g] of all groups and multiplies each by
+// its group's phase sum sum_k C_k (-1)^popcount(Z_k & s); there are no
+// atomics and results are bitwise reproducible.  Amplitudes are read in
+// their storage type (complex128 or complex64) and everything else --
+// coefficients, phase sums, accumulators, reductions -- is float64.  When
+// every coefficient of the operator is real (real Hamiltonians in XZ form:
+// Section 2.3), phase sums are real float64 and each gather costs two FMAs.
+//
+// Sector kernel layout: a workgroup owns one target alpha string t_a (one
+// row of the alpha-major state) and kSB consecutive beta columns, one target
+// per lane.  Groups are visited class by class (a class shares X_alpha), so
+// the source row s_a = t_a ^ X_alpha, its validity and its rank are uniform
+// across the workgroup, and so are the alpha parities of every term: the
+// coefficients of each unique beta Z-mask are folded over their terms' alpha
+// parities cooperatively into LDS once per class.  Per class:
+//  * the group with X_beta = 0 gathers from the lane's own column;
+//  * groups whose X_beta flips two orbitals are visited by enumerating the
+//    lane's valid pair moves (occupied -> empty, the same count for every
+//    target of a sector), cached in registers with their source ranks, and a
+//    per-class pair map; invalid moves are never visited;
+//  * other groups are scanned with a per-lane validity test;
+//  * consecutive classes holding only an X_beta = 0 group share one fold,
+//    and their valid source rows are listed in LDS and gathered four at a
+//    time;
+//  * the source row is staged in LDS when it fits.
+// Parities are evaluated against the target strings each lane holds; the
+// constant (-1)^popcount(z & X) factors were moved into the coefficients
+// when the tables were built.
+#pragma once
+
+#include "handles.h"
+
+namespace pbs {
+namespace {
+
+constexpr int kBlock = 256;
+
+template <class T>
+struct Amp;
+template <>
+struct Amp<double2> {
+  __device__ static inline void load(const double2* p, uint64_t i, double& r, double& m) {
+    const double2 v = p[i];
+    r = v.x;
+    m = v.y;
+  }
+  __device__ static inline void store(double2* p, uint64_t i, double r, double m) { p[i] = make_double2(r, m); }
+};
+template <>
+struct Amp<float2> {
+  __device__ static inline void load(const float2* p, uint64_t i, double& r, double& m) {
+    const float2 v = p[i];
+    r = static_cast<double>(v.x);
+    m = static_cast<double>(v.y);
+  }
+  __device__ static inline void store(float2* p, uint64_t i, double r, double m) {
+    p[i] = make_float2(static_cast<float>(r), static_cast<float>(m));
+  }
+};
+
+// v * (-1)^(p & 1) by flipping the sign bit.
+__device__ inline double signed_by(double v, uint32_t p) {
+  return __hiloint2double(__double2hiint(v) ^ static_cast<int>((p & 1u) << 31), __double2loint(v));
+}
+
+// Read-only load through the constant address space: uniform addresses
+// become scalar loads (the tables are never written by the kernels).
+__device__ inline uint32_t ldc(const uint32_t* p) { return *((const __attribute__((address_space(4))) uint32_t*)(p)); }
+
+__device__ inline ClassMeta ld_meta(const ClassMeta* p) {
+  static_assert(sizeof(ClassMeta) == 12 * sizeof(uint32_t), "ClassMeta layout");
+  const uint32_t* q = reinterpret_cast<const uint32_t*>(p);
+  uint32_t w[12];
+#pragma unroll
+  for (int i = 0; i < 12; ++i) w[i] = ldc(q + i);
+  ClassMeta m;
+  memcpy(&m, w, sizeof(m));
+  return m;
+}
+
+template <int B>
+__device__ inline void block_reduce3_store(double a, double b, double c, double* dst) {
+  __shared__ double red[3][B / 64];
+  for (int d = 32; d > 0; d >>= 1) {
+    a += __shfl_xor(a, d, 64);
+    b += __shfl_xor(b, d, 64);
+    c += __shfl_xor(c, d, 64);
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+    red[0][wave] = a;
+    red[1][wave] = b;
+    red[2][wave] = c;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s0 = 0, s1 = 0, s2 = 0;
+    for (int w = 0; w < B / 64; ++w) {
+      s0 += red[0][w];
+      s1 += red[1][w];
+      s2 += red[2][w];
+    }
+    dst[0] = s0;
+    dst[1] = s1;
+    dst[2] = s2;
+  }
+}
+
+// ---------------------------------------------------------------- coefficients
+// Phase-sum arithmetic for complex (double2) or real (double) coefficients.
+template <bool REALC>
+struct Coef;
+template <>
+struct Coef<false> {
+  using V = double2;
+  __device__ static inline V zero() { return make_double2(0.0, 0.0); }
+  __device__ static inline V term(const double2* c, uint32_t t) { return c[t]; }
+  __device__ static inline void add_signed(V& acc, V c, uint32_t par) {
+    acc.x += signed_by(c.x, par);
+    acc.y += signed_by(c.y, par);
+  }
+  __device__ static inline V sign(V c, uint32_t par) { return make_double2(signed_by(c.x, par), signed_by(c.y, par)); }
+  __device__ static inline V zeroed_unless(V f, bool keep) { return keep ? f : zero(); }
+  // acc += f * a
+  __device__ static inline void mac(V f, double ar, double ai, double& acc_r, double& acc_i) {
+    acc_r = fma(ar, f.x, fma(-ai, f.y, acc_r));
+    acc_i = fma(ar, f.y, fma(ai, f.x, acc_i));
+  }
+};
+template <>
+struct Coef<true> {
+  using V = double;
+  __device__ static inline V zero() { return 0.0; }
+  __device__ static inline V term(const double2* c, uint32_t t) { return c[t].x; }
+  __device__ static inline void add_signed(V& acc, V c, uint32_t par) { acc += signed_by(c, par); }
+  __device__ static inline V sign(V c, uint32_t par) { return signed_by(c, par); }
+  __device__ static inline V zeroed_unless(V f, bool keep) { return keep ? f : 0.0; }
+  __device__ static inline void mac(V f, double ar, double ai, double& acc_r, double& acc_i) {
+    acc_r = fma(ar, f, acc_r);
+    acc_i = fma(ai, f, acc_i);
+  }
+};
+
+// ---------------------------------------------------------------- spin sector
+constexpr int kSB = 512;              // lanes per sector workgroup = beta columns per workgroup
+constexpr int kMaxMoves = 56;         // pair moves cached per lane (N_beta (n_orb - N_beta) <= 56)
+constexpr uint32_t kRowCapBytes = 64u * 1024u;
+constexpr uint32_t kListMinBytes = 4096u;  // simple-class row list when no row is staged
+// LDS copy of the uint16 rank tables (n_orb <= 16): chunk 0 with no ones
+// below it, then chunk 1 for 0..8 ones below it
+constexpr uint32_t kRank16Lds = 10u * 256u;
+
+struct SectorArgs {
+  uint32_t n_orb, n_alpha, n_beta, n_chunks;
+  uint32_t dim_beta;
+  uint32_t n_class, n_pairs, n_moves;
+  uint32_t row_lds, enum_ok;
+  uint32_t list_cap;  // entries of the simple-class row list (in the row space)
+  uint32_t f_cap;     // folded uniques held in LDS at once; slot f_cap holds a zero
+  uint32_t off_rank, off_row, off_f, off_fz, off_pu;  // LDS byte offsets
+  const uint32_t* str_a;
+  const uint32_t* str_b;
+  const uint16_t* rank16;  // n_orb <= 16
+  const uint32_t* rank32;
+  const ClassMeta* meta;
+  const int32_t* pmap;
+  const uint32_t* pg_xb;
+  const uint32_t* pg_u0;
+  const uint32_t* u_zb;
+  const uint32_t* u_t0;
+  const uint32_t* pt_za;
+  const double2* pt_c;
+};
+
+// Combinatorial rank of a spin string: uint16 tables in LDS (n_orb <= 16,
+// at most two byte chunks) or uint32 tables in global memory.
+template <bool R16>
+__device__ inline uint32_t rank_of(uint32_t s, const SectorArgs& P, const uint16_t* t16) {
+  if (R16) {
+    const uint32_t lo = s & 255u;
+    uint32_t r = t16[lo];
+    if (P.n_chunks > 1) r += t16[256u + (static_cast<uint32_t>(__popc(lo)) << 8) + ((s >> 8) & 255u)];
+    return r;
+  }
+  uint32_t r = 0, below = 0;
+  for (uint32_t c = 0; c < P.n_chunks; ++c) {
+    const uint32_t byte = (s >> (8 * c)) & 255u;
+    r += P.rank32[(c * (P.n_orb + 1) + below) * 256 + byte];
+    below += __popc(byte);
+  }
+  return r;
+}
+
+// F[u - ua] = sum over the unique's terms of C_t (-1)^popcount(za_t & ta).
+template <bool REALC>
+__device__ inline void fold_uniques(const SectorArgs& P, uint32_t ua, uint32_t ub, uint32_t ta,
+                                    typename Coef<REALC>::V* F, uint32_t* Fz) {
+  using C = Coef<REALC>;
+  for (uint32_t u = ua + threadIdx.x; u < ub; u += kSB) {
+    typename C::V f = C::zero();
+    const uint32_t t1 = P.u_t0[u + 1];
+    for (uint32_t t = P.u_t0[u]; t < t1; ++t) C::add_signed(f, C::term(P.pt_c, t), __popc(P.pt_za[t] & ta));
+    F[u - ua] = f;
+    Fz[u - ua] = P.u_zb[u];
+  }
+}
+
+template <bool REALC>
+__device__ inline void phase_sum_lds(const typename Coef<REALC>::V* F, const uint32_t* Fz, uint32_t b, uint32_t cnt,
+                                     uint32_t tb, typename Coef<REALC>::V& f) {
+  for (uint32_t i = 0; i < cnt; ++i) Coef<REALC>::add_signed(f, F[b + i], __popc(Fz[b + i] & tb));
+}
+
+// Phase sum of group g straight from the term tables (groups too large for LDS).
+template <bool REALC>
+__device__ inline void phase_sum_direct(const SectorArgs& P, uint32_t g, uint32_t ta, uint32_t tb,
+                                        typename Coef<REALC>::V& f) {
+  using C = Coef<REALC>;
+  const uint32_t u1 = P.pg_u0[g + 1];
+  for (uint32_t u = P.pg_u0[g]; u < u1; ++u) {
+    typename C::V h = C::zero();
+    const uint32_t t1 = P.u_t0[u + 1];
+    for (uint32_t t = P.u_t0[u]; t < t1; ++t) C::add_signed(h, C::term(P.pt_c, t), __popc(P.pt_za[t] & ta));
+    C::add_signed(f, h, __popc(P.u_zb[u] & tb));
+  }
+}
+
+template <class T>
+__device__ inline void ld_amp(const T* p, uint64_t i, double& r, double& m) {
+  Amp<T>::load(p, i, r, m);
+}
+
+// One group of a scanned chunk: validity of X_beta for this lane's target,
+// source column rank, phase sum from the folded uniques; invalid targets are
+// predicated off (column 0 is read, the coefficient is zeroed).
+template <bool R16, bool REALC, class T>
+__device__ __forceinline__ void scan_group(const SectorArgs& P, uint32_t g, uint32_t us, uint32_t tb,
+                                           const uint16_t* s_rank, const typename Coef<REALC>::V* s_F,
+                                           const uint32_t* s_Fz, const T* rowp, double& acc_r, double& acc_i) {
+  using C = Coef<REALC>;
+  const uint32_t xb = ldc(P.pg_xb + g);
+  const uint32_t u0 = ldc(P.pg_u0 + g), u1 = ldc(P.pg_u0 + g + 1);
+  const bool valid = 2u * __popc(tb & xb) == static_cast<uint32_t>(__popc(xb));
+  const uint32_t jb = valid ? rank_of<R16>(tb ^ xb, P, s_rank) : 0u;
+  typename C::V f = C::zero();
+  phase_sum_lds<REALC>(s_F, s_Fz, u0 - us, u1 - u0, tb, f);
+  double a_r, a_i;
+  ld_amp<T>(rowp, jb, a_r, a_i);
+  C::mac(C::zeroed_unless(f, valid), a_r, a_i, acc_r, acc_i);
+}
+
+// Lists, in class order, the simple classes c0 .. c1-1 whose source alpha
+// string ta ^ X_alpha lies in the sector: entry = (source row rank, first
+// folded unique relative to ua | unique count << 16).  The list is padded to
+// a multiple of four with entries that read row 0 against the zero slot.
+// Returns the padded length; ends with the list visible to the workgroup.
+template <bool R16>
+__device__ uint32_t list_valid_rows(const SectorArgs& P, uint32_t c0, uint32_t c1, uint32_t ua, uint32_t ta,
+                                    const uint16_t* s_rank, uint2* s_list, uint32_t* s_wcnt) {
+  const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+  const uint64_t below = (1ull << lane) - 1ull;
+  uint32_t base = 0;
+  for (uint32_t i0 = c0; i0 < c1; i0 += kSB) {
+    const uint32_t cc = i0 + threadIdx.x;
+    bool v = false;
+    uint2 entry = make_uint2(0u, 0u);
+    if (cc < c1) {
+      const ClassMeta* m = P.meta + cc;
+      const uint32_t sa = ta ^ m->xa;
+      v = static_cast<uint32_t>(__popc(sa)) == P.n_alpha;
+      if (v) entry = make_uint2(rank_of<R16>(sa, P, s_rank), (m->ua - ua) | ((m->u_end - m->ua) << 16));
+    }
+    const uint64_t bal = __ballot(v);
+    if (lane == 0) s_wcnt[wave] = static_cast<uint32_t>(__popcll(bal));
+    __syncthreads();
+    uint32_t off = base, total = 0;
+    for (uint32_t w = 0; w < kSB / 64; ++w) {
+      const uint32_t n = s_wcnt[w];
+      off += w < wave ? n : 0u;
+      total += n;
+    }
+    if (v) s_list[off + static_cast<uint32_t>(__popcll(bal & below))] = entry;
+    base += total;
+    __syncthreads();
+  }
+  const uint32_t padded = (base + 3u) & ~3u;
+  if (threadIdx.x < padded - base) s_list[base + threadIdx.x] = make_uint2(0u, P.f_cap | (1u << 16));
+  __syncthreads();
+  return padded;
+}
+
+// One workgroup: target alpha string ia (one row of the state), beta columns
+// chunk*kSB .. chunk*kSB + kSB - 1, one target per lane.  See the file header
+// for the scheme.  `slot` receives the workgroup's energy partials.
+template <class T, bool EXPVAL, bool R16, bool ROWLDS, bool REALC>
+__device__ __forceinline__ void sector_body(const SectorArgs& P, const T* __restrict__ psi, T* __restrict__ out,
+                                            double* __restrict__ slot, uint64_t ia, uint32_t chunk) {
+  using C = Coef<REALC>;
+  using V = typename C::V;
+  extern __shared__ __align__(16) unsigned char smem[];
+  uint16_t* s_rank = reinterpret_cast<uint16_t*>(smem + P.off_rank);
+  T* s_row = reinterpret_cast<T*>(smem + P.off_row);
+  V* s_F = reinterpret_cast<V*>(smem + P.off_f);
+  uint32_t* s_Fz = reinterpret_cast<uint32_t*>(smem + P.off_fz);
+  uint32_t* s_pu = reinterpret_cast<uint32_t*>(smem + P.off_pu);
+  uint2* s_list = reinterpret_cast<uint2*>(smem + P.off_row);  // shares the staged row's space
+  __shared__ uint32_t s_wcnt[kSB / 64];
+  const uint32_t f_cap = P.f_cap;
+
+  if (R16) {
+    const uint32_t n = P.n_chunks > 1 ? kRank16Lds : 256u;
+    for (uint32_t i = threadIdx.x; i < n; i += kSB)
+      s_rank[i] = P.rank16[i < 256u ? i : (P.n_orb + 1) * 256u + (i - 256u)];
+  }
+  if (threadIdx.x == 0) {  // zero slot for absent pair groups and padding entries
+    s_F[f_cap] = C::zero();
+    s_Fz[f_cap] = 0u;
+  }
+  __syncthreads();
+
+  const uint32_t db = P.dim_beta;
+  const uint32_t col = chunk * kSB + threadIdx.x;
+  const bool live = col < db;
+  const uint32_t colc = live ? col : 0u;  // in-bounds column for idle lanes
+  const uint32_t ta = P.str_a[ia];
+  const uint32_t tb = P.str_b[colc];
+  const uint32_t n_orb = P.n_orb;
+
+  // Pair moves of this lane's target (occupied p -> empty q), packed as
+  // source rank | pair index << 16, occupied-major.
+  uint32_t mv[kMaxMoves];
+  // padding moves point at pair index n_pairs (the zero slot) and column 0
+  const uint32_t pad_move = P.n_pairs << 16;
+  if (P.enum_ok) {
+    const uint32_t full = (n_orb == 32) ? 0xffffffffu : ((1u << n_orb) - 1u);
+    const uint32_t emp = ~tb & full;
+    const uint32_t ne = n_orb - P.n_beta;
+    uint32_t pm_occ = tb, pm_emp = emp, j = 0;
+    uint32_t p = __ffs(pm_occ) - 1;
+#pragma unroll
+    for (int k = 0; k < kMaxMoves; ++k) {
+      mv[k] = pad_move;
+      if (static_cast<uint32_t>(k) < P.n_moves) {
+        const uint32_t q = __ffs(pm_emp) - 1;
+        pm_emp &= pm_emp - 1;
+        const uint32_t lo = p < q ? p : q, hi = p < q ? q : p;
+        const uint32_t pair = hi * (hi - 1) / 2 + lo;
+        mv[k] = rank_of<R16>(tb ^ (1u << p) ^ (1u << q), P, s_rank) | (pair << 16);
+        if (++j == ne) {
+          j = 0;
+          pm_emp = emp;
+          pm_occ &= pm_occ - 1;
+          p = __ffs(pm_occ) - 1;
+        }
+      }
+    }
+  }
+
+  double ar4[4] = {0.0, 0.0, 0.0, 0.0}, ai4[4] = {0.0, 0.0, 0.0, 0.0};
+  uint32_t c = 0;
+  while (c < P.n_class) {
+    const ClassMeta M = ld_meta(P.meta + c);
+    if (M.flags & kClassSimple) {
+      // consecutive single-group classes share one cooperative fold; their
+      // valid source rows are listed (in class order) in LDS and gathered
+      // four at a time so the row loads overlap
+      const uint32_t ua = M.ua;
+      uint32_t ce = c + 1;
+      uint32_t ub = M.u_end;
+      while (ce < P.n_class && ce - c + 3 < P.list_cap) {
+        const ClassMeta N = ld_meta(P.meta + ce);
+        if (!(N.flags & kClassSimple) || N.u_end - ua > f_cap) break;
+        ub = N.u_end;
+        ++ce;
+      }
+      __syncthreads();
+      fold_uniques<REALC>(P, ua, ub, ta, s_F, s_Fz);
+      const uint32_t n_list = list_valid_rows<R16>(P, c, ce, ua, ta, s_rank, s_list, s_wcnt);
+      for (uint32_t e0 = 0; e0 < n_list; e0 += 4) {
+        uint32_t rk[4], w[4];
+        double a_r[4], a_i[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const uint2 L = s_list[e0 + i];
+          rk[i] = __builtin_amdgcn_readfirstlane(L.x);
+          w[i] = __builtin_amdgcn_readfirstlane(L.y);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) ld_amp<T>(psi, static_cast<uint64_t>(rk[i]) * db + colc, a_r[i], a_i[i]);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          V f = C::zero();
+          phase_sum_lds<REALC>(s_F, s_Fz, w[i] & 0xffffu, w[i] >> 16, tb, f);
+          C::mac(f, a_r[i], a_i[i], ar4[i], ai4[i]);
+        }
+      }
+      c = ce;
+      continue;
+    }
+
+    const uint32_t sa = ta ^ M.xa;
+    if (static_cast<uint32_t>(__popc(sa)) != P.n_alpha) {
+      ++c;
+      continue;
+    }
+    const uint64_t rowoff = static_cast<uint64_t>(rank_of<R16>(sa, P, s_rank)) * db;
+    const uint32_t gz_end = M.zg >= 0 ? M.g0 + 1 : M.g0;
+    // enumerate pair moves when the class's pair groups are dense enough
+    const bool penum = P.enum_ok && M.pm >= 0 && (M.u_p - M.ua) <= f_cap && 2 * (M.p1 - gz_end) >= P.n_moves;
+    const bool single = penum && (M.flags & kClassPairsSingle);
+    const uint32_t ub_a = penum ? M.u_p : M.u_z;
+    const bool fold_a = ub_a > M.ua && ub_a - M.ua <= f_cap;
+    const bool stage = P.row_lds && gz_end < M.g1;
+    const T* rowg = psi + rowoff;
+
+    // phase A: X_beta = 0 group and, when enumerated, the pair groups
+    if (stage || fold_a) {
+      __syncthreads();
+      if (stage)
+        for (uint32_t j = threadIdx.x; j < db; j += kSB) s_row[j] = rowg[j];
+      if (fold_a) fold_uniques<REALC>(P, M.ua, ub_a, ta, s_F, s_Fz);
+      if (penum) {
+        const int32_t* pm = P.pmap + static_cast<uint64_t>(M.pm) * P.n_pairs;
+        for (uint32_t q = threadIdx.x; q <= P.n_pairs; q += kSB) {
+          const int32_t g = q < P.n_pairs ? pm[q] : -1;  // entry n_pairs serves the padding moves
+          uint32_t v;
+          if (single)
+            v = g >= 0 ? P.pg_u0[g] - M.ua : f_cap;
+          else
+            v = g >= 0 ? ((P.pg_u0[g] - M.ua) | ((P.pg_u0[g + 1] - P.pg_u0[g]) << 16)) : 0u;
+          s_pu[q] = v;
+        }
+      }
+      __syncthreads();
+    }
+    if (M.zg >= 0) {
+      V f = C::zero();
+      if (fold_a)
+        phase_sum_lds<REALC>(s_F, s_Fz, 0, M.u_z - M.ua, tb, f);
+      else
+        phase_sum_direct<REALC>(P, static_cast<uint32_t>(M.zg), ta, tb, f);
+      double a_r, a_i;
+      if (ROWLDS && stage)
+        ld_amp<T>(s_row, colc, a_r, a_i);
+      else
+        ld_amp<T>(rowg, colc, a_r, a_i);
+      C::mac(f, a_r, a_i, ar4[0], ai4[0]);
+    }
+    const T* rowp = ROWLDS ? s_row : rowg;  // pair and scanned groups need the staged row
+    if (penum) {
+      uint32_t n_moves = P.n_moves;
+      asm volatile("" : "+s"(n_moves));  // keep the move predicates inside the class loop
+      if (single) {
+        // straight-line groups of four moves: one unique per pair group; absent
+        // groups and padding moves hit the zero slot, so loads issue together
+#pragma unroll
+        for (int k0 = 0; k0 < kMaxMoves; k0 += 4) {
+          if (static_cast<uint32_t>(k0) < n_moves) {
+            uint32_t e[4], sl[4], z[4];
+            V f[4];
+            double a_r[4], a_i[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              e[i] = mv[k0 + i];
+              asm volatile("" : "+v"(e[i]));  // keep per-move address arithmetic inside the class loop
+              sl[i] = s_pu[e[i] >> 16];
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              f[i] = s_F[sl[i]];
+              z[i] = s_Fz[sl[i]];
+              ld_amp<T>(rowp, e[i] & 0xffffu, a_r[i], a_i[i]);
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) C::mac(C::sign(f[i], __popc(z[i] & tb)), a_r[i], a_i[i], ar4[i], ai4[i]);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < kMaxMoves; ++k) {
+          if (static_cast<uint32_t>(k) < n_moves) {
+            uint32_t e = mv[k];
+            asm volatile("" : "+v"(e));
+            const uint32_t w = s_pu[e >> 16];
+            V f = C::zero();
+            phase_sum_lds<REALC>(s_F, s_Fz, w & 0xffffu, w >> 16, tb, f);
+            double a_r, a_i;
+            ld_amp<T>(rowp, e & 0xffffu, a_r, a_i);
+            C::mac(f, a_r, a_i, ar4[k & 3], ai4[k & 3]);
+          }
+        }
+      }
+    }
+
+    // phase B: remaining groups, scanned in chunks whose uniques fit in LDS;
+    // invalid targets are predicated off (source index clamped, coefficient 0)
+    uint32_t gs = penum ? M.p1 : gz_end;
+    while (gs < M.g1) {
+      const uint32_t us = ldc(P.pg_u0 + gs);
+      uint32_t ge = gs;
+      while (ge < M.g1 && ldc(P.pg_u0 + ge + 1) - us <= f_cap) ++ge;
+      if (ge == gs) {
+        const uint32_t xb = P.pg_xb[gs];
+        const bool valid = live && 2u * __popc(tb & xb) == static_cast<uint32_t>(__popc(xb));
+        if (valid) {
+          V f = C::zero();
+          phase_sum_direct<REALC>(P, gs, ta, tb, f);
+          double a_r, a_i;
+          ld_amp<T>(rowp, rank_of<R16>(tb ^ xb, P, s_rank), a_r, a_i);
+          C::mac(f, a_r, a_i, ar4[1], ai4[1]);
+        }
+        ++gs;
+        continue;
+      }
+      __syncthreads();
+      fold_uniques<REALC>(P, us, P.pg_u0[ge], ta, s_F, s_Fz);
+      __syncthreads();
+      uint32_t g = gs;
+      for (; g + 1 < ge; g += 2) {
+        scan_group<R16, REALC>(P, g, us, tb, s_rank, s_F, s_Fz, rowp, ar4[2], ai4[2]);
+        scan_group<R16, REALC>(P, g + 1, us, tb, s_rank, s_F, s_Fz, rowp, ar4[3], ai4[3]);
+      }
+      if (g < ge) scan_group<R16, REALC>(P, g, us, tb, s_rank, s_F, s_Fz, rowp, ar4[2], ai4[2]);
+      gs = ge;
+    }
+    ++c;
+  }
+
+  const double acc_r = (ar4[0] + ar4[1]) + (ar4[2] + ar4[3]);
+  const double acc_i = (ai4[0] + ai4[1]) + (ai4[2] + ai4[3]);
+  double e_re = 0.0, e_im = 0.0, nrm = 0.0;
+  if (live) {
+    const uint64_t t = ia * db + col;
+    if (EXPVAL) {
+      double pr, pi;
+      Amp<T>::load(psi, t, pr, pi);
+      e_re = fma(pr, acc_r, pi * acc_i);
+      e_im = fma(pr, acc_i, -pi * acc_r);
+      nrm = fma(pr, pr, pi * pi);
+      if (out) Amp<T>::store(out, t, acc_r, acc_i);
+    } else {
+      Amp<T>::store(out, t, acc_r, acc_i);
+    }
+  }
+  if (EXPVAL) block_reduce3_store<kSB>(e_re, e_im, nrm, slot);
+}
+
+template <class T, bool EXPVAL, bool R16, bool ROWLDS, bool REALC>
+__global__ __launch_bounds__(kSB) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_apply_sector(
+    SectorArgs P, const T* __restrict__ psi, T* __restrict__ out, double* __restrict__ partial) {
+  sector_body<T, EXPVAL, R16, ROWLDS, REALC>(P, psi, out, partial + 3ull * (blockIdx.y * gridDim.x + blockIdx.x),
+                                             blockIdx.x, blockIdx.y);
+}
+
+// A job of a batched launch: one operator on one sector state.
+struct BatchJob {
+  SectorArgs args;
+  const void* psi;
+  void* out;
+  uint32_t block_base;  // first workgroup of the job
+  uint32_t chunks;      // beta-column chunks per row
+  uint64_t pad;
+};
+
+template <class X>
+__device__ inline X ld_words(const X* p) {
+  static_assert(sizeof(X) % 4 == 0, "word-sized record");
+  constexpr int kW = sizeof(X) / 4;
+  const uint32_t* q = reinterpret_cast<const uint32_t*>(p);
+  uint32_t w[kW];
+#pragma unroll
+  for (int i = 0; i < kW; ++i) w[i] = ldc(q + i);
+  X v;
+  memcpy(&v, w, sizeof(v));
+  return v;
+}
+
+// All jobs of a batch in one launch: workgroup b belongs to the job with the
+// largest block_base <= b (jobs are stored in block order).
+template <class T, bool EXPVAL, bool R16, bool ROWLDS, bool REALC>
+__global__ __launch_bounds__(kSB) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_apply_sector_batch(
+    const BatchJob* __restrict__ jobs, uint32_t n_jobs, double* __restrict__ partial) {
+  uint32_t lo = 0, hi = n_jobs;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) / 2;
+    if (ldc(&jobs[mid].block_base) <= blockIdx.x)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  const BatchJob J = ld_words(jobs + lo);
+  const uint32_t b = blockIdx.x - J.block_base;
+  sector_body<T, EXPVAL, R16, ROWLDS, REALC>(J.args, static_cast<const T*>(J.psi), static_cast<T*>(J.out),
+                                             partial + 3ull * blockIdx.x, b / J.chunks, b % J.chunks);
+}
+
+// Address of one sector kernel variant (single launch or batch).
+template <class T, bool EXPVAL, bool R16, bool ROWLDS, bool REALC>
+void* sector_variant(bool batch) {
+  return batch ? reinterpret_cast<void*>(k_apply_sector_batch<T, EXPVAL, R16, ROWLDS, REALC>)
+               : reinterpret_cast<void*>(k_apply_sector<T, EXPVAL, R16, ROWLDS, REALC>);
+}
+
+template <class T, bool EXPVAL>
+void* sector_variants(bool batch, bool r16, bool rowlds, bool realc) {
+  if (r16) {
+    if (rowlds) return realc ? sector_variant<T, EXPVAL, true, true, true>(batch)
+                             : sector_variant<T, EXPVAL, true, true, false>(batch);
+    return realc ? sector_variant<T, EXPVAL, true, false, true>(batch)
+                 : sector_variant<T, EXPVAL, true, false, false>(batch);
+  }
+  if (rowlds) return realc ? sector_variant<T, EXPVAL, false, true, true>(batch)
+                           : sector_variant<T, EXPVAL, false, true, false>(batch);
+  return realc ? sector_variant<T, EXPVAL, false, false, true>(batch)
+               : sector_variant<T, EXPVAL, false, false, false>(batch);
+}
+
+}  // namespace
+
+// Each is defined in its own translation unit (sector_<storage>_<mode>.hip)
+// so the variants compile in parallel.
+void* sector_kernel_c64_apply(bool batch, bool r16, bool rowlds, bool realc);
+void* sector_kernel_c64_expval(bool batch, bool r16, bool rowlds, bool realc);
+void* sector_kernel_c128_apply(bool batch, bool r16, bool rowlds, bool realc);
+void* sector_kernel_c128_expval(bool batch, bool r16, bool rowlds, bool realc);
+
+inline void* sector_kernel(pbs_dtype dt, bool expval, bool batch, bool r16, bool rowlds, bool realc) {
+  if (dt == PBS_C128)
+    return expval ? sector_kernel_c128_expval(batch, r16, rowlds, realc)
+                  : sector_kernel_c128_apply(batch, r16, rowlds, realc);
+  return expval ? sector_kernel_c64_expval(batch, r16, rowlds, realc)
+                : sector_kernel_c64_apply(batch, r16, rowlds, realc);
+}
+
+}  // namespace pbs
