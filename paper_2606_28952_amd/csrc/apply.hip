@@ -118,6 +118,7 @@ Launch plan_sector(const pbs_grouped& h, const pbs_space& sp, size_t elem_bytes,
   a.rank32 = sp.rank_tab.get();
   a.meta = h.cls_meta.get();
   a.pmap = h.pmap.get();
+  a.qmap = h.qmap.get();
   a.pg_xb = h.pg_xb.get();
   a.pg_u0 = h.pg_u0.get();
   a.u_zb = h.u_zb.get();
@@ -136,12 +137,19 @@ Launch plan_sector(const pbs_grouped& h, const pbs_space& sp, size_t elem_bytes,
                   ? 1u
                   : 0u;
   const uint32_t pu_bytes = a.enum_ok ? align16((h.n_pairs + 1) * 4) : 0u;
+  const uint64_t n_ep = host_binom(sp.n_orb - sp.n_beta, 2), n_op = host_binom(sp.n_beta, 2);
+  a.qenum_ok = (*r16 && a.enum_ok && h.n_qmap > 0 && h.n_quads > 0 && n_op * n_ep > 0) ? 1u : 0u;
+  a.n_quads = h.n_quads;
+  a.n_qmoves = static_cast<uint32_t>(n_op * n_ep);
+  const uint32_t qu_bytes = a.qenum_ok ? align16(h.n_quads * 4) : 0u;
   const uint64_t row_bytes = sp.dim_beta * elem_bytes;
   const uint64_t row_space = row_bytes > kListMinBytes ? row_bytes : kListMinBytes;
-  a.row_lds = (allow_row && row_bytes <= kRowCapBytes && rank_bytes + f_min + pu_bytes + row_space <= limit) ? 1u : 0u;
+  a.row_lds =
+      (allow_row && row_bytes <= kRowCapBytes && rank_bytes + f_min + pu_bytes + qu_bytes + row_space <= limit) ? 1u
+                                                                                                               : 0u;
   const uint32_t row_region = align16(static_cast<uint32_t>(a.row_lds ? row_space : kListMinBytes));
   a.list_cap = row_region / 8u;
-  const uint32_t fixed = rank_bytes + row_region + pu_bytes;
+  const uint32_t fixed = rank_bytes + row_region + pu_bytes + qu_bytes;
   const uint32_t budget = fixed + f_min <= half ? half : limit;
   a.f_cap = std::min(kFCapMax, (budget - fixed - 64u) / per_unique - 1u);
   uint32_t off = 0;
@@ -155,6 +163,8 @@ Launch plan_sector(const pbs_grouped& h, const pbs_space& sp, size_t elem_bytes,
   off += align16((a.f_cap + 1) * 4u);
   a.off_pu = off;
   off += pu_bytes;
+  a.off_qu = off;
+  off += qu_bytes;
   *a_out = a;
 
   Launch L;

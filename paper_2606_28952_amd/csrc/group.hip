@@ -136,10 +136,12 @@ __global__ void k_any_imag(const double* c, uint64_t m, uint32_t* flag) {
     if (c[2 * i + 1] != 0.0) atomicOr(flag, 1u);
 }
 
-// Per class: the X_beta = 0 group, the popcount-2 range, and whether the
-// class needs a pair-map row (flag written for a scan).
-__global__ void k_class_meta(uint32_t n_class, const uint32_t* cls_g0, const uint32_t* pg_pc, int32_t* zg,
-                             int32_t* p0, int32_t* p1, uint32_t* has_pairs) {
+// Per class: the X_beta = 0 group, the popcount-2 and popcount-4 ranges,
+// and whether the class needs a pair-map and a quad-map row (flags written
+// for scans).
+__global__ void k_class_meta(uint32_t n_class, const uint32_t* cls_g0, const uint32_t* pg_pc, bool quads,
+                             int32_t* zg, int32_t* p0, int32_t* p1, int32_t* q1, uint32_t* has_pairs,
+                             uint32_t* has_quads) {
   for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < n_class; c += gridDim.x * blockDim.x) {
     const uint32_t g0 = cls_g0[c], g1 = cls_g0[c + 1];
     uint32_t g = g0;
@@ -147,10 +149,39 @@ __global__ void k_class_meta(uint32_t n_class, const uint32_t* cls_g0, const uin
     if (g < g1 && pg_pc[g] == 0) z = static_cast<int32_t>(g++);
     const uint32_t a = g;
     while (g < g1 && pg_pc[g] == 2) ++g;
+    const uint32_t b = g;
+    while (g < g1 && pg_pc[g] == 4) ++g;
     zg[c] = z;
     p0[c] = static_cast<int32_t>(a);
-    p1[c] = static_cast<int32_t>(g);
-    has_pairs[c] = g > a ? 1u : 0u;
+    p1[c] = static_cast<int32_t>(b);
+    q1[c] = static_cast<int32_t>(g);
+    has_pairs[c] = b > a ? 1u : 0u;
+    has_quads[c] = quads && g > b ? 1u : 0u;
+  }
+}
+
+__device__ inline uint32_t small_binom(uint32_t n, uint32_t r) {
+  if (r > n) return 0;
+  uint32_t v = 1;
+  for (uint32_t i = 1; i <= r; ++i) v = v * (n - r + i) / i;  // exact at every step
+  return v;
+}
+
+// Quad map: the group of each popcount-4 X_beta in its class, at the
+// colexicographic rank of X_beta.
+__global__ void k_quad_map(uint32_t n_class, const int32_t* p1, const int32_t* q1, const int32_t* qm,
+                           const uint32_t* pg_xb, uint32_t n_quads, int32_t* qmap) {
+  for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < n_class; c += gridDim.x * blockDim.x) {
+    if (qm[c] < 0) continue;
+    for (int32_t g = p1[c]; g < q1[c]; ++g) {
+      uint32_t xb = pg_xb[g], id = 0;
+      for (uint32_t j = 1; j <= 4; ++j) {
+        const uint32_t b = __ffs(xb) - 1;
+        xb &= xb - 1;
+        id += small_binom(b, j);
+      }
+      qmap[static_cast<uint64_t>(qm[c]) * n_quads + id] = g;
+    }
   }
 }
 
@@ -160,7 +191,8 @@ __global__ void k_pair_rows(uint32_t n_class, const uint32_t* has_pairs, const u
 }
 
 __global__ void k_class_pack(uint32_t n_class, const uint32_t* cls_xa, const uint32_t* cls_g0, const int32_t* zg,
-                             const int32_t* p1, const int32_t* pm, const uint32_t* pg_u0, ClassMeta* meta) {
+                             const int32_t* p1, const int32_t* pm, const int32_t* q1, const int32_t* qm,
+                             const uint32_t* pg_u0, ClassMeta* meta) {
   for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < n_class; c += gridDim.x * blockDim.x) {
     ClassMeta m;
     m.xa = cls_xa[c];
@@ -180,7 +212,10 @@ __global__ void k_class_pack(uint32_t n_class, const uint32_t* cls_xa, const uin
     for (uint32_t g = gz_end; g < m.p1; ++g) single = single && (pg_u0[g + 1] - pg_u0[g] == 1);
     if (single) f |= kClassPairsSingle;
     m.flags = f;
-    m.pad = 0;
+    m.q1 = static_cast<uint32_t>(q1[c]);
+    m.qm = qm[c];
+    m.u_q = pg_u0[m.q1];
+    m.pad[0] = m.pad[1] = 0;
     meta[c] = m;
   }
 }
@@ -279,14 +314,19 @@ static void build_sector_tables(pbs_grouped& g, const uint64_t* x, hipStream_t s
   PBS_HIP(hipGetLastError());
   g.real_coef = read_scalar(cnt.get(), s) == 0u;
 
-  // bucket metadata and the pair map
+  // bucket metadata, the pair map and the quad map
   g.cls_zg.alloc(g.n_class);
   g.cls_p0.alloc(g.n_class);
   g.cls_p1.alloc(g.n_class);
   g.cls_pm.alloc(g.n_class);
-  DevBuf<uint32_t> has_pairs(g.n_class), slot(g.n_class);
+  g.cls_q1.alloc(g.n_class);
+  g.cls_qm.alloc(g.n_class);
+  const uint64_t n_quads = host_binom(h, 4);
+  g.n_quads = n_quads <= kMaxQuads ? static_cast<uint32_t>(n_quads) : 0u;
+  DevBuf<uint32_t> has_pairs(g.n_class), has_quads(g.n_class), slot(g.n_class);
   hipLaunchKernelGGL(k_class_meta, dim3(grid_for(g.n_class, 256, 65536)), dim3(256), 0, s, g.n_class,
-                     g.cls_g0.get(), g.pg_pc.get(), g.cls_zg.get(), g.cls_p0.get(), g.cls_p1.get(), has_pairs.get());
+                     g.cls_g0.get(), g.pg_pc.get(), g.n_quads > 0, g.cls_zg.get(), g.cls_p0.get(), g.cls_p1.get(),
+                     g.cls_q1.get(), has_pairs.get(), has_quads.get());
   exclusive_scan_u32(has_pairs.get(), slot.get(), g.n_class, cnt.get(), s);
   g.n_pmap = read_scalar(cnt.get(), s);
   hipLaunchKernelGGL(k_pair_rows, dim3(grid_for(g.n_class, 256, 65536)), dim3(256), 0, s, g.n_class, has_pairs.get(),
@@ -299,10 +339,22 @@ static void build_sector_tables(pbs_grouped& g, const uint64_t* x, hipStream_t s
     hipLaunchKernelGGL(k_pair_map, dim3(grid_for(g.n_class, 256, 65536)), dim3(256), 0, s, g.n_class,
                        g.cls_p0.get(), g.cls_p1.get(), g.cls_pm.get(), g.pg_xb.get(), g.n_pairs, g.pmap.get());
   }
+  exclusive_scan_u32(has_quads.get(), slot.get(), g.n_class, cnt.get(), s);
+  g.n_qmap = read_scalar(cnt.get(), s);
+  hipLaunchKernelGGL(k_pair_rows, dim3(grid_for(g.n_class, 256, 65536)), dim3(256), 0, s, g.n_class, has_quads.get(),
+                     slot.get(), g.cls_qm.get());
+  const uint64_t qm_entries = static_cast<uint64_t>(g.n_qmap) * g.n_quads;
+  g.qmap.alloc(qm_entries);
+  if (qm_entries) {
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(qm_entries, 256, 65536)), dim3(256), 0, s, g.qmap.get(), qm_entries,
+                       -1);
+    hipLaunchKernelGGL(k_quad_map, dim3(grid_for(g.n_class, 256, 65536)), dim3(256), 0, s, g.n_class,
+                       g.cls_p1.get(), g.cls_q1.get(), g.cls_qm.get(), g.pg_xb.get(), g.n_quads, g.qmap.get());
+  }
   g.cls_meta.alloc(g.n_class);
   hipLaunchKernelGGL(k_class_pack, dim3(grid_for(g.n_class, 256, 65536)), dim3(256), 0, s, g.n_class,
-                     g.cls_xa.get(), g.cls_g0.get(), g.cls_zg.get(), g.cls_p1.get(), g.cls_pm.get(), g.pg_u0.get(),
-                     g.cls_meta.get());
+                     g.cls_xa.get(), g.cls_g0.get(), g.cls_zg.get(), g.cls_p1.get(), g.cls_pm.get(), g.cls_q1.get(),
+                     g.cls_qm.get(), g.pg_u0.get(), g.cls_meta.get());
   PBS_HIP(hipGetLastError());
   PBS_HIP(hipStreamSynchronize(s));
 }

@@ -22,6 +22,10 @@
 //   pair map     : pmap[cls_pm[c] * n_pairs + pair(p, q)] = group with
 //                  X_beta = {p, q} in class c, or -1; pair(p, q) = q(q-1)/2 + p
 //                  for p < q
+//   quad map     : qmap[cls_qm[c] * n_quads + quad(X_beta)] = group with that
+//                  four-orbital X_beta in class c, or -1; quad(X) is the
+//                  colexicographic rank sum_j C(b_j, j + 1) of X's bits
+//                  b_0 < b_1 < b_2 < b_3 (built when C(h, 4) <= kMaxQuads)
 // Exact rewrites valid inside any fixed-(N_alpha, N_beta) sector:
 //  * a term whose X_alpha or X_beta has odd popcount never maps a sector
 //    configuration into the sector and is removed;
@@ -49,11 +53,15 @@ struct ClassMeta {
   uint32_t u_p;     // end of the pair groups' uniques
   uint32_t u_end;   // end of the class's uniques
   uint32_t flags;   // kClassSimple | kClassPairsSingle
-  uint32_t pad;
+  uint32_t q1;      // end of the popcount-4 groups (they start at p1)
+  int32_t qm;       // quad-map row, or -1
+  uint32_t u_q;     // end of the quad groups' uniques
+  uint32_t pad[2];
 };
 constexpr uint32_t kClassSimple = 1u;       // only an X_beta = 0 group, few uniques
 constexpr uint32_t kClassPairsSingle = 2u;  // every pair group has exactly one unique
 constexpr uint32_t kSimpleCap = 64;         // uniques of a "simple" class
+constexpr uint32_t kMaxQuads = 2048;        // largest C(h, 4) given a quad map (h <= 16)
 }  // namespace pbs
 
 struct pbs_grouped {
@@ -69,8 +77,10 @@ struct pbs_grouped {
   uint32_t half = 0;
   uint32_t n_class = 0, n_pgroup = 0, n_unique = 0, n_pterm = 0;
   uint32_t n_pairs = 0, n_pmap = 0;
+  uint32_t n_quads = 0, n_qmap = 0;
   pbs::DevBuf<uint32_t> cls_xa, cls_g0;
   pbs::DevBuf<int32_t> cls_zg, cls_p0, cls_p1, cls_pm, pmap;
+  pbs::DevBuf<int32_t> cls_q1, cls_qm, qmap;
   pbs::DevBuf<uint32_t> pg_pc;  // popcount(X_beta) of each group
   pbs::DevBuf<pbs::ClassMeta> cls_meta;
   pbs::DevBuf<uint32_t> pg_xb, pg_u0;
@@ -98,6 +108,8 @@ struct pbs_space {
 };
 
 namespace pbs {
+uint64_t host_binom(uint32_t n, uint32_t r);  // exact binomial coefficient (space.hip)
+
 inline size_t rank_tab_entries(uint32_t n_orb) {
   return static_cast<size_t>((n_orb + 7) / 8) * (n_orb + 1) * 256;
 }

@@ -75,13 +75,14 @@ __device__ inline double signed_by(double v, uint32_t p) {
 __device__ inline uint32_t ldc(const uint32_t* p) { return *((const __attribute__((address_space(4))) uint32_t*)(p)); }
 
 __device__ inline ClassMeta ld_meta(const ClassMeta* p) {
-  static_assert(sizeof(ClassMeta) == 12 * sizeof(uint32_t), "ClassMeta layout");
+  static_assert(sizeof(ClassMeta) == 16 * sizeof(uint32_t), "ClassMeta layout");
   const uint32_t* q = reinterpret_cast<const uint32_t*>(p);
-  uint32_t w[12];
+  uint32_t w[14];  // the last two words are padding
 #pragma unroll
-  for (int i = 0; i < 12; ++i) w[i] = ldc(q + i);
+  for (int i = 0; i < 14; ++i) w[i] = ldc(q + i);
   ClassMeta m;
-  memcpy(&m, w, sizeof(m));
+  memcpy(&m, w, sizeof(w));
+  m.pad[0] = m.pad[1] = 0;
   return m;
 }
 
@@ -164,13 +165,15 @@ struct SectorArgs {
   uint32_t row_lds, enum_ok;
   uint32_t list_cap;  // entries of the simple-class row list (in the row space)
   uint32_t f_cap;     // folded uniques held in LDS at once; slot f_cap holds a zero
-  uint32_t off_rank, off_row, off_f, off_fz, off_pu;  // LDS byte offsets
+  uint32_t qenum_ok, n_quads, n_qmoves;  // double-move enumeration (n_orb <= 16)
+  uint32_t off_rank, off_row, off_f, off_fz, off_pu, off_qu;  // LDS byte offsets
   const uint32_t* str_a;
   const uint32_t* str_b;
   const uint16_t* rank16;  // n_orb <= 16
   const uint32_t* rank32;
   const ClassMeta* meta;
   const int32_t* pmap;
+  const int32_t* qmap;
   const uint32_t* pg_xb;
   const uint32_t* pg_u0;
   const uint32_t* u_zb;
@@ -256,6 +259,63 @@ __device__ __forceinline__ void scan_group(const SectorArgs& P, uint32_t g, uint
   C::mac(C::zeroed_unless(f, valid), a_r, a_i, acc_r, acc_i);
 }
 
+// One double move of this lane's target: X_beta = X (two occupied and two
+// empty orbitals).  The quad map slot gives the folded uniques of X's group
+// (absent groups point at the zero slot).
+template <bool R16, bool REALC, class T>
+__device__ __forceinline__ void quad_move(const SectorArgs& P, uint32_t X, uint32_t tb, const uint16_t* s_rank,
+                                          const typename Coef<REALC>::V* s_F, const uint32_t* s_Fz,
+                                          const uint32_t* s_qu, const T* rowp, double& acc_r, double& acc_i) {
+  using C = Coef<REALC>;
+  const uint32_t w = s_qu[rank_of<R16>(X, P, s_rank)];
+  const uint32_t src = rank_of<R16>(tb ^ X, P, s_rank);
+  typename C::V f = C::zero();
+  phase_sum_lds<REALC>(s_F, s_Fz, w & 0xffffu, w >> 16, tb, f);
+  double a_r, a_i;
+  ld_amp<T>(rowp, src, a_r, a_i);
+  C::mac(f, a_r, a_i, acc_r, acc_i);
+}
+
+// All C(N_beta, 2) C(n_orb - N_beta, 2) double moves of this lane's target,
+// occupied pairs outer, empty pairs inner (two per step).  Every loop bound
+// is uniform across the workgroup.
+template <bool R16, bool REALC, class T>
+__device__ __forceinline__ void quad_moves(const SectorArgs& P, uint32_t tb, const uint16_t* s_rank,
+                                           const typename Coef<REALC>::V* s_F, const uint32_t* s_Fz,
+                                           const uint32_t* s_qu, const T* rowp, double (&ar4)[4],
+                                           double (&ai4)[4]) {
+  const uint32_t nb = P.n_beta, ne = P.n_orb - P.n_beta;
+  const uint32_t full = (P.n_orb == 32) ? 0xffffffffu : ((1u << P.n_orb) - 1u);
+  const uint32_t emp = ~tb & full;
+  uint32_t oa = tb;
+  for (uint32_t i = 1; i < nb; ++i) {
+    const uint32_t o1 = oa & (0u - oa);
+    oa ^= o1;
+    uint32_t ob = oa;
+    for (uint32_t j = i; j < nb; ++j) {
+      const uint32_t o2 = ob & (0u - ob);
+      ob ^= o2;
+      uint32_t ea = emp;
+      for (uint32_t k = 1; k < ne; ++k) {
+        const uint32_t e1 = ea & (0u - ea);
+        ea ^= e1;
+        const uint32_t base = o1 | o2 | e1;
+        uint32_t eb = ea;
+        uint32_t l = k;
+        for (; l + 1 < ne; l += 2) {
+          const uint32_t e2 = eb & (0u - eb);
+          eb ^= e2;
+          const uint32_t e3 = eb & (0u - eb);
+          eb ^= e3;
+          quad_move<R16, REALC>(P, base | e2, tb, s_rank, s_F, s_Fz, s_qu, rowp, ar4[2], ai4[2]);
+          quad_move<R16, REALC>(P, base | e3, tb, s_rank, s_F, s_Fz, s_qu, rowp, ar4[3], ai4[3]);
+        }
+        if (l < ne) quad_move<R16, REALC>(P, base | (eb & (0u - eb)), tb, s_rank, s_F, s_Fz, s_qu, rowp, ar4[1], ai4[1]);
+      }
+    }
+  }
+}
+
 // Lists, in class order, the simple classes c0 .. c1-1 whose source alpha
 // string ta ^ X_alpha lies in the sector: entry = (source row rank, first
 // folded unique relative to ua | unique count << 16).  The list is padded to
@@ -310,6 +370,7 @@ __device__ __forceinline__ void sector_body(const SectorArgs& P, const T* __rest
   V* s_F = reinterpret_cast<V*>(smem + P.off_f);
   uint32_t* s_Fz = reinterpret_cast<uint32_t*>(smem + P.off_fz);
   uint32_t* s_pu = reinterpret_cast<uint32_t*>(smem + P.off_pu);
+  uint32_t* s_qu = reinterpret_cast<uint32_t*>(smem + P.off_qu);
   uint2* s_list = reinterpret_cast<uint2*>(smem + P.off_row);  // shares the staged row's space
   __shared__ uint32_t s_wcnt[kSB / 64];
   const uint32_t f_cap = P.f_cap;
@@ -499,9 +560,25 @@ __device__ __forceinline__ void sector_body(const SectorArgs& P, const T* __rest
       }
     }
 
+    // phase Q: groups whose X_beta flips four orbitals, by enumerating the
+    // lane's valid double moves against a per-class quad map
+    const bool qenum =
+        penum && P.qenum_ok && M.qm >= 0 && M.u_q - M.u_p <= f_cap && 2 * (M.q1 - M.p1) >= P.n_qmoves;
+    if (qenum) {
+      __syncthreads();
+      fold_uniques<REALC>(P, M.u_p, M.u_q, ta, s_F, s_Fz);
+      const int32_t* qm = P.qmap + static_cast<uint64_t>(M.qm) * P.n_quads;
+      for (uint32_t q = threadIdx.x; q < P.n_quads; q += kSB) {
+        const int32_t g = qm[q];
+        s_qu[q] = g >= 0 ? ((P.pg_u0[g] - M.u_p) | ((P.pg_u0[g + 1] - P.pg_u0[g]) << 16)) : (f_cap | (1u << 16));
+      }
+      __syncthreads();
+      quad_moves<R16, REALC>(P, tb, s_rank, s_F, s_Fz, s_qu, rowp, ar4, ai4);
+    }
+
     // phase B: remaining groups, scanned in chunks whose uniques fit in LDS;
     // invalid targets are predicated off (source index clamped, coefficient 0)
-    uint32_t gs = penum ? M.p1 : gz_end;
+    uint32_t gs = qenum ? M.q1 : (penum ? M.p1 : gz_end);
     while (gs < M.g1) {
       const uint32_t us = ldc(P.pg_u0 + gs);
       uint32_t ge = gs;
