@@ -42,9 +42,11 @@ WORKLOADS = {
 
 def _source_hash():
     h = hashlib.sha256()
-    for f in ("apply.hip", "handles.h"):
-        with open(os.path.join(ROOT, "paper_2606_28952_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+    csrc = os.path.join(ROOT, "paper_2606_28952_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".h")):
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(fh.read())
     return h.hexdigest()[:16]
 
 

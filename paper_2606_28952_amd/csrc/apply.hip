@@ -141,15 +141,24 @@ Launch plan_sector(const pbs_grouped& h, const pbs_space& sp, size_t elem_bytes,
   a.qenum_ok = (*r16 && a.enum_ok && h.n_qmap > 0 && h.n_quads > 0 && n_op * n_ep > 0) ? 1u : 0u;
   a.n_quads = h.n_quads;
   a.n_qmoves = static_cast<uint32_t>(n_op * n_ep);
-  const uint32_t qu_bytes = a.qenum_ok ? align16(h.n_quads * 4) : 0u;
   const uint64_t row_bytes = sp.dim_beta * elem_bytes;
   const uint64_t row_space = row_bytes > kListMinBytes ? row_bytes : kListMinBytes;
-  a.row_lds =
-      (allow_row && row_bytes <= kRowCapBytes && rank_bytes + f_min + pu_bytes + qu_bytes + row_space <= limit) ? 1u
-                                                                                                               : 0u;
+  a.row_lds = (allow_row && row_bytes <= kRowCapBytes && rank_bytes + f_min + pu_bytes + row_space <= limit) ? 1u : 0u;
   const uint32_t row_region = align16(static_cast<uint32_t>(a.row_lds ? row_space : kListMinBytes));
   a.list_cap = row_region / 8u;
-  const uint32_t fixed = rank_bytes + row_region + pu_bytes + qu_bytes;
+  // The double-move phase needs its quad map and every quad unique of a
+  // class in LDS at once; it is kept only if that still lets two workgroups
+  // share a compute unit (or if two never fit anyway).
+  const uint32_t base_fixed = rank_bytes + row_region + pu_bytes;
+  const uint32_t qu_need = align16(h.n_quads * 4);
+  const uint32_t q_need = (h.max_quad_uniques + 1) * per_unique + 64u;
+  if (a.qenum_ok) {
+    const bool two_without = base_fixed + f_min <= half;
+    const uint32_t cap = two_without ? half : limit;
+    if (base_fixed + qu_need + std::max(q_need, f_min) > cap || h.max_quad_uniques >= kFCapMax) a.qenum_ok = 0u;
+  }
+  const uint32_t qu_bytes = a.qenum_ok ? qu_need : 0u;
+  const uint32_t fixed = base_fixed + qu_bytes;
   const uint32_t budget = fixed + f_min <= half ? half : limit;
   a.f_cap = std::min(kFCapMax, (budget - fixed - 64u) / per_unique - 1u);
   uint32_t off = 0;

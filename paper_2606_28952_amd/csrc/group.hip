@@ -192,7 +192,7 @@ __global__ void k_pair_rows(uint32_t n_class, const uint32_t* has_pairs, const u
 
 __global__ void k_class_pack(uint32_t n_class, const uint32_t* cls_xa, const uint32_t* cls_g0, const int32_t* zg,
                              const int32_t* p1, const int32_t* pm, const int32_t* q1, const int32_t* qm,
-                             const uint32_t* pg_u0, ClassMeta* meta) {
+                             const uint32_t* pg_u0, ClassMeta* meta, uint32_t* max_quad_uniques) {
   for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < n_class; c += gridDim.x * blockDim.x) {
     ClassMeta m;
     m.xa = cls_xa[c];
@@ -217,6 +217,7 @@ __global__ void k_class_pack(uint32_t n_class, const uint32_t* cls_xa, const uin
     m.u_q = pg_u0[m.q1];
     m.pad[0] = m.pad[1] = 0;
     meta[c] = m;
+    if (m.qm >= 0) atomicMax(max_quad_uniques, m.u_q - m.u_p);
   }
 }
 
@@ -352,10 +353,12 @@ static void build_sector_tables(pbs_grouped& g, const uint64_t* x, hipStream_t s
                        g.cls_p1.get(), g.cls_q1.get(), g.cls_qm.get(), g.pg_xb.get(), g.n_quads, g.qmap.get());
   }
   g.cls_meta.alloc(g.n_class);
+  hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, s, cnt.get(), 0u);
   hipLaunchKernelGGL(k_class_pack, dim3(grid_for(g.n_class, 256, 65536)), dim3(256), 0, s, g.n_class,
                      g.cls_xa.get(), g.cls_g0.get(), g.cls_zg.get(), g.cls_p1.get(), g.cls_pm.get(), g.cls_q1.get(),
-                     g.cls_qm.get(), g.pg_u0.get(), g.cls_meta.get());
+                     g.cls_qm.get(), g.pg_u0.get(), g.cls_meta.get(), cnt.get());
   PBS_HIP(hipGetLastError());
+  g.max_quad_uniques = read_scalar(cnt.get(), s);
   PBS_HIP(hipStreamSynchronize(s));
 }
 

@@ -78,6 +78,7 @@ struct pbs_grouped {
   uint32_t n_class = 0, n_pgroup = 0, n_unique = 0, n_pterm = 0;
   uint32_t n_pairs = 0, n_pmap = 0;
   uint32_t n_quads = 0, n_qmap = 0;
+  uint32_t max_quad_uniques = 0;  // largest u_q - u_p over classes with a quad-map row
   pbs::DevBuf<uint32_t> cls_xa, cls_g0;
   pbs::DevBuf<int32_t> cls_zg, cls_p0, cls_p1, cls_pm, pmap;
   pbs::DevBuf<int32_t> cls_q1, cls_qm, qmap;
