@@ -78,6 +78,7 @@ __global__ __launch_bounds__(kBlock) void k_expval_finish(const double* partial,
 
 // ---------------------------------------------------------------- launch planning
 struct Launch {
+  uint32_t chunks = 0;  // beta-column chunks per row
   dim3 grid;
   dim3 block;
   uint64_t parts = 0;
@@ -178,7 +179,8 @@ Launch plan_sector(const pbs_grouped& h, const pbs_space& sp, size_t elem_bytes,
 
   Launch L;
   const uint64_t chunks = (sp.dim_beta + kSB - 1) / kSB;
-  L.grid = dim3(static_cast<unsigned>(sp.dim_alpha), static_cast<unsigned>(chunks));
+  L.grid = dim3(static_cast<unsigned>(sp.dim_alpha * chunks));
+  L.chunks = static_cast<uint32_t>(chunks);
   L.block = dim3(kSB);
   L.parts = sp.dim_alpha * chunks;
   L.lds = off;
@@ -199,8 +201,8 @@ void validate(const pbs_grouped* h, const pbs_space* sp, pbs_dtype dt) {
               "operator has " + std::to_string(h->n_qubits) + " qubits, space has " + std::to_string(sp->n_qubits));
   if (sp->sector) {
     PBS_REQUIRE(h->has_sector && h->half == sp->n_orb, PBS_ERR_ARG, "operator lacks sector tables for this split");
-    PBS_REQUIRE(sp->dim_beta < (1ull << 31) && sp->dim_alpha < (1ull << 31), PBS_ERR_RANGE,
-                "spin-string count exceeds the launch grid");
+    PBS_REQUIRE(sp->dim_alpha * ((sp->dim_beta + kSB - 1) / kSB) < (1ull << 31), PBS_ERR_RANGE,
+                "sector needs more than 2^31 workgroups");
   }
 }
 
@@ -348,7 +350,7 @@ pbs_status pbs_batch_create(uint32_t n, const pbs_grouped* const* h, const pbs_s
       if (!r16) jobs[i].args.rank16 = nullptr;
       jobs[i].psi = psi[i];
       jobs[i].out = out[i];
-      jobs[i].chunks = L.grid.y;
+      jobs[i].chunks = L.chunks;
       jobs[i].block_base = 0;
       jobs[i].pad = i;  // original position (energies are written there)
       lds = std::max(lds, L.lds);

@@ -629,11 +629,23 @@ __device__ __forceinline__ void sector_body(const SectorArgs& P, const T* __rest
   if (EXPVAL) block_reduce3_store<kSB>(e_re, e_im, nrm, slot);
 }
 
+// Workgroup b takes row b mod dim_alpha and column chunk b / dim_alpha, so
+// the workgroups in flight at any time share one column chunk across many
+// rows.  (Keeping a row's chunks together on one XCD, or giving each XCD a
+// contiguous row range, measured 3-4% slower on the 28-qubit sector.)
+__device__ inline void row_chunk_of(uint32_t b, uint32_t rows, uint32_t& row, uint32_t& chunk) {
+  row = b % rows;
+  chunk = b / rows;
+}
+
+// One-dimensional grid of dim_alpha * chunks workgroups.
 template <class T, bool EXPVAL, bool R16, bool ROWLDS, bool REALC>
 __global__ __launch_bounds__(kSB) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_apply_sector(
     SectorArgs P, const T* __restrict__ psi, T* __restrict__ out, double* __restrict__ partial) {
-  sector_body<T, EXPVAL, R16, ROWLDS, REALC>(P, psi, out, partial + 3ull * (blockIdx.y * gridDim.x + blockIdx.x),
-                                             blockIdx.x, blockIdx.y);
+  const uint32_t chunks = (P.dim_beta + kSB - 1) / kSB;
+  uint32_t row, chunk;
+  row_chunk_of(blockIdx.x, gridDim.x / chunks, row, chunk);
+  sector_body<T, EXPVAL, R16, ROWLDS, REALC>(P, psi, out, partial + 3ull * blockIdx.x, row, chunk);
 }
 
 // A job of a batched launch: one operator on one sector state.
