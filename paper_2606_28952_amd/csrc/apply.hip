@@ -120,6 +120,11 @@ Launch plan_sector(const pbs_grouped& h, const pbs_space& sp, size_t elem_bytes,
   a.meta = h.cls_meta.get();
   a.pmap = h.pmap.get();
   a.qmap = h.qmap.get();
+  a.quad_cnt = h.quad_cnt;
+  a.n_runs = h.n_runs;
+  a.n_ns = h.n_ns;
+  a.runs = h.runs.get();
+  a.ns_list = h.ns_list.get();
   a.pg_xb = h.pg_xb.get();
   a.pg_u0 = h.pg_u0.get();
   a.u_zb = h.u_zb.get();
@@ -130,9 +135,9 @@ Launch plan_sector(const pbs_grouped& h, const pbs_space& sp, size_t elem_bytes,
   const uint32_t limit = static_cast<uint32_t>(device_lds_limit()) - 1024u;  // static shared arrays
   const uint32_t half = limit / 2u - 512u;
   *r16 = sp.n_orb <= 16;
-  const uint32_t rank_bytes = *r16 ? align16((sp.n_chunks > 1 ? kRank16Lds : 256u) * 2u) : 0u;
+  const uint32_t rank_bytes = *r16 ? align16(kRank16Lds * 2u) : 0u;
   const uint32_t per_unique = (realc ? 8u : 16u) + 4u;
-  const uint32_t f_min = kFCapMin * per_unique + 64u;
+  const uint32_t f_min = (kFCapMin + kZeroSlots) * per_unique + 64u;
   a.enum_ok = (h.n_pmap > 0 && a.n_moves <= static_cast<uint32_t>(kMaxMoves) && sp.dim_beta < 65536 &&
                h.n_pairs < 65536)
                   ? 1u
@@ -152,7 +157,7 @@ Launch plan_sector(const pbs_grouped& h, const pbs_space& sp, size_t elem_bytes,
   // share a compute unit (or if two never fit anyway).
   const uint32_t base_fixed = rank_bytes + row_region + pu_bytes;
   const uint32_t qu_need = align16(h.n_quads * 4);
-  const uint32_t q_need = (h.max_quad_uniques + 1) * per_unique + 64u;
+  const uint32_t q_need = (h.max_quad_uniques + kZeroSlots) * per_unique + 64u;
   if (a.qenum_ok) {
     const bool two_without = base_fixed + f_min <= half;
     const uint32_t cap = two_without ? half : limit;
@@ -161,16 +166,16 @@ Launch plan_sector(const pbs_grouped& h, const pbs_space& sp, size_t elem_bytes,
   const uint32_t qu_bytes = a.qenum_ok ? qu_need : 0u;
   const uint32_t fixed = base_fixed + qu_bytes;
   const uint32_t budget = fixed + f_min <= half ? half : limit;
-  a.f_cap = std::min(kFCapMax, (budget - fixed - 64u) / per_unique - 1u);
+  a.f_cap = std::min(kFCapMax, (budget - fixed - 64u) / per_unique - kZeroSlots);
   uint32_t off = 0;
   a.off_rank = off;
   off += rank_bytes;
   a.off_row = off;
   off += row_region;
   a.off_f = off;
-  off += align16((a.f_cap + 1) * (per_unique - 4u));
+  off += align16((a.f_cap + kZeroSlots) * (per_unique - 4u));
   a.off_fz = off;
-  off += align16((a.f_cap + 1) * 4u);
+  off += align16((a.f_cap + kZeroSlots) * 4u);
   a.off_pu = off;
   off += pu_bytes;
   a.off_qu = off;

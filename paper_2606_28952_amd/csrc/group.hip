@@ -359,7 +359,41 @@ static void build_sector_tables(pbs_grouped& g, const uint64_t* x, hipStream_t s
                      g.cls_qm.get(), g.pg_u0.get(), g.cls_meta.get(), cnt.get());
   PBS_HIP(hipGetLastError());
   g.max_quad_uniques = read_scalar(cnt.get(), s);
+
+  // class schedule (host side, once per operator)
+  std::vector<ClassMeta> meta(g.n_class);
+  std::vector<uint32_t> u0(g.n_pgroup + 1);
+  PBS_HIP(hipMemcpyAsync(meta.data(), g.cls_meta.get(), meta.size() * sizeof(ClassMeta), hipMemcpyDeviceToHost, s));
+  PBS_HIP(hipMemcpyAsync(u0.data(), g.pg_u0.get(), u0.size() * 4, hipMemcpyDeviceToHost, s));
   PBS_HIP(hipStreamSynchronize(s));
+  std::vector<uint32_t> runs, ns;
+  int64_t qcnt = -1;
+  for (uint32_t c = 0; c < g.n_class; ++c) {
+    const ClassMeta& m = meta[c];
+    if (m.flags & kClassSimple) {
+      if (!runs.empty() && runs.back() == c) {
+        runs.back() = c + 1;
+      } else {
+        runs.push_back(c);
+        runs.push_back(c + 1);
+      }
+    } else {
+      ns.push_back(c);
+    }
+    if (m.qm >= 0) {
+      for (uint32_t q = m.p1; q < m.q1; ++q) {
+        const int64_t n = u0[q + 1] - u0[q];
+        qcnt = (qcnt == -1 || qcnt == n) ? n : 0;
+      }
+    }
+  }
+  g.n_runs = static_cast<uint32_t>(runs.size() / 2);
+  g.n_ns = static_cast<uint32_t>(ns.size());
+  g.quad_cnt = qcnt > 0 ? static_cast<uint32_t>(qcnt) : 0u;
+  g.runs.alloc(runs.size());
+  g.ns_list.alloc(ns.size());
+  if (!runs.empty()) PBS_HIP(hipMemcpy(g.runs.get(), runs.data(), runs.size() * 4, hipMemcpyHostToDevice));
+  if (!ns.empty()) PBS_HIP(hipMemcpy(g.ns_list.get(), ns.data(), ns.size() * 4, hipMemcpyHostToDevice));
 }
 
 }  // namespace pbs

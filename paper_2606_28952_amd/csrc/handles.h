@@ -84,6 +84,11 @@ struct pbs_grouped {
   pbs::DevBuf<int32_t> cls_q1, cls_qm, qmap;
   pbs::DevBuf<uint32_t> pg_pc;  // popcount(X_beta) of each group
   pbs::DevBuf<pbs::ClassMeta> cls_meta;
+  // class schedule of the sector kernel: maximal runs of consecutive simple
+  // classes as (first, end) pairs, then the other classes in order
+  uint32_t n_runs = 0, n_ns = 0;
+  pbs::DevBuf<uint32_t> runs, ns_list;
+  uint32_t quad_cnt = 0;  // uniques of every mapped quad group when all are equal, else 0
   pbs::DevBuf<uint32_t> pg_xb, pg_u0;
   pbs::DevBuf<uint32_t> u_zb, u_t0;
   pbs::DevBuf<uint32_t> pt_za;

@@ -155,8 +155,10 @@ constexpr int kMaxMoves = 56;         // pair moves cached per lane (N_beta (n_o
 constexpr uint32_t kRowCapBytes = 64u * 1024u;
 constexpr uint32_t kListMinBytes = 4096u;  // simple-class row list when no row is staged
 // LDS copy of the uint16 rank tables (n_orb <= 16): chunk 0 with no ones
-// below it, then chunk 1 for 0..8 ones below it
+// below it, then chunk 1 for 0..8 ones below it (zeros when n_orb <= 8)
 constexpr uint32_t kRank16Lds = 10u * 256u;
+constexpr int kGather = 8;  // simple-class row loads in flight per lane
+constexpr uint32_t kZeroSlots = 4;  // zero entries after the folded uniques (absent groups, padding)
 
 struct SectorArgs {
   uint32_t n_orb, n_alpha, n_beta, n_chunks;
@@ -164,8 +166,12 @@ struct SectorArgs {
   uint32_t n_class, n_pairs, n_moves;
   uint32_t row_lds, enum_ok;
   uint32_t list_cap;  // entries of the simple-class row list (in the row space)
-  uint32_t f_cap;     // folded uniques held in LDS at once; slot f_cap holds a zero
+  uint32_t f_cap;     // folded uniques held in LDS at once; kZeroSlots zeros follow
   uint32_t qenum_ok, n_quads, n_qmoves;  // double-move enumeration (n_orb <= 16)
+  uint32_t quad_cnt;                     // uniques of every quad group when all are equal, else 0
+  uint32_t n_runs, n_ns;                 // class schedule: simple-class runs, other classes
+  const uint32_t* runs;                  // (first, end) per run
+  const uint32_t* ns_list;
   uint32_t off_rank, off_row, off_f, off_fz, off_pu, off_qu;  // LDS byte offsets
   const uint32_t* str_a;
   const uint32_t* str_b;
@@ -186,11 +192,9 @@ struct SectorArgs {
 // at most two byte chunks) or uint32 tables in global memory.
 template <bool R16>
 __device__ inline uint32_t rank_of(uint32_t s, const SectorArgs& P, const uint16_t* t16) {
-  if (R16) {
+  if (R16) {  // the chunk-1 tables are zero when n_orb <= 8
     const uint32_t lo = s & 255u;
-    uint32_t r = t16[lo];
-    if (P.n_chunks > 1) r += t16[256u + (static_cast<uint32_t>(__popc(lo)) << 8) + ((s >> 8) & 255u)];
-    return r;
+    return t16[lo] + t16[256u + (static_cast<uint32_t>(__popc(lo)) << 8) + ((s >> 8) & 255u)];
   }
   uint32_t r = 0, below = 0;
   for (uint32_t c = 0; c < P.n_chunks; ++c) {
@@ -262,7 +266,9 @@ __device__ __forceinline__ void scan_group(const SectorArgs& P, uint32_t g, uint
 // One double move of this lane's target: X_beta = X (two occupied and two
 // empty orbitals).  The quad map slot gives the folded uniques of X's group
 // (absent groups point at the zero slot).
-template <bool R16, bool REALC, class T>
+// QC > 0: every quad group has QC uniques (absent groups point at QC zero
+// slots), so the phase sum is straight-line; QC = 0: counts from the map.
+template <int QC, bool R16, bool REALC, class T>
 __device__ __forceinline__ void quad_move(const SectorArgs& P, uint32_t X, uint32_t tb, const uint16_t* s_rank,
                                           const typename Coef<REALC>::V* s_F, const uint32_t* s_Fz,
                                           const uint32_t* s_qu, const T* rowp, double& acc_r, double& acc_i) {
@@ -270,7 +276,13 @@ __device__ __forceinline__ void quad_move(const SectorArgs& P, uint32_t X, uint3
   const uint32_t w = s_qu[rank_of<R16>(X, P, s_rank)];
   const uint32_t src = rank_of<R16>(tb ^ X, P, s_rank);
   typename C::V f = C::zero();
-  phase_sum_lds<REALC>(s_F, s_Fz, w & 0xffffu, w >> 16, tb, f);
+  if (QC > 0) {
+    const uint32_t b = w & 0xffffu;
+#pragma unroll
+    for (int i = 0; i < QC; ++i) C::add_signed(f, s_F[b + i], __popc(s_Fz[b + i] & tb));
+  } else {
+    phase_sum_lds<REALC>(s_F, s_Fz, w & 0xffffu, w >> 16, tb, f);
+  }
   double a_r, a_i;
   ld_amp<T>(rowp, src, a_r, a_i);
   C::mac(f, a_r, a_i, acc_r, acc_i);
@@ -279,7 +291,7 @@ __device__ __forceinline__ void quad_move(const SectorArgs& P, uint32_t X, uint3
 // All C(N_beta, 2) C(n_orb - N_beta, 2) double moves of this lane's target,
 // occupied pairs outer, empty pairs inner (two per step).  Every loop bound
 // is uniform across the workgroup.
-template <bool R16, bool REALC, class T>
+template <int QC, bool R16, bool REALC, class T>
 __device__ __forceinline__ void quad_moves(const SectorArgs& P, uint32_t tb, const uint16_t* s_rank,
                                            const typename Coef<REALC>::V* s_F, const uint32_t* s_Fz,
                                            const uint32_t* s_qu, const T* rowp, double (&ar4)[4],
@@ -307,10 +319,10 @@ __device__ __forceinline__ void quad_moves(const SectorArgs& P, uint32_t tb, con
           eb ^= e2;
           const uint32_t e3 = eb & (0u - eb);
           eb ^= e3;
-          quad_move<R16, REALC>(P, base | e2, tb, s_rank, s_F, s_Fz, s_qu, rowp, ar4[2], ai4[2]);
-          quad_move<R16, REALC>(P, base | e3, tb, s_rank, s_F, s_Fz, s_qu, rowp, ar4[3], ai4[3]);
+          quad_move<QC, R16, REALC>(P, base | e2, tb, s_rank, s_F, s_Fz, s_qu, rowp, ar4[2], ai4[2]);
+          quad_move<QC, R16, REALC>(P, base | e3, tb, s_rank, s_F, s_Fz, s_qu, rowp, ar4[3], ai4[3]);
         }
-        if (l < ne) quad_move<R16, REALC>(P, base | (eb & (0u - eb)), tb, s_rank, s_F, s_Fz, s_qu, rowp, ar4[1], ai4[1]);
+        if (l < ne) quad_move<QC, R16, REALC>(P, base | (eb & (0u - eb)), tb, s_rank, s_F, s_Fz, s_qu, rowp, ar4[1], ai4[1]);
       }
     }
   }
@@ -319,7 +331,7 @@ __device__ __forceinline__ void quad_moves(const SectorArgs& P, uint32_t tb, con
 // Lists, in class order, the simple classes c0 .. c1-1 whose source alpha
 // string ta ^ X_alpha lies in the sector: entry = (source row rank, first
 // folded unique relative to ua | unique count << 16).  The list is padded to
-// a multiple of four with entries that read row 0 against the zero slot.
+// a multiple of kGather with entries that read row 0 against the zero slot.
 // Returns the padded length; ends with the list visible to the workgroup.
 template <bool R16>
 __device__ uint32_t list_valid_rows(const SectorArgs& P, uint32_t c0, uint32_t c1, uint32_t ua, uint32_t ta,
@@ -350,7 +362,7 @@ __device__ uint32_t list_valid_rows(const SectorArgs& P, uint32_t c0, uint32_t c
     base += total;
     __syncthreads();
   }
-  const uint32_t padded = (base + 3u) & ~3u;
+  const uint32_t padded = (base + kGather - 1u) / kGather * kGather;
   if (threadIdx.x < padded - base) s_list[base + threadIdx.x] = make_uint2(0u, P.f_cap | (1u << 16));
   __syncthreads();
   return padded;
@@ -376,13 +388,12 @@ __device__ __forceinline__ void sector_body(const SectorArgs& P, const T* __rest
   const uint32_t f_cap = P.f_cap;
 
   if (R16) {
-    const uint32_t n = P.n_chunks > 1 ? kRank16Lds : 256u;
-    for (uint32_t i = threadIdx.x; i < n; i += kSB)
-      s_rank[i] = P.rank16[i < 256u ? i : (P.n_orb + 1) * 256u + (i - 256u)];
+    for (uint32_t i = threadIdx.x; i < kRank16Lds; i += kSB)
+      s_rank[i] = i < 256u ? P.rank16[i] : (P.n_chunks > 1 ? P.rank16[(P.n_orb + 1) * 256u + (i - 256u)] : 0);
   }
-  if (threadIdx.x == 0) {  // zero slot for absent pair groups and padding entries
-    s_F[f_cap] = C::zero();
-    s_Fz[f_cap] = 0u;
+  if (threadIdx.x < kZeroSlots) {  // zero slots for absent groups and padding entries
+    s_F[f_cap + threadIdx.x] = C::zero();
+    s_Fz[f_cap + threadIdx.x] = 0u;
   }
   __syncthreads();
 
@@ -393,6 +404,51 @@ __device__ __forceinline__ void sector_body(const SectorArgs& P, const T* __rest
   const uint32_t ta = P.str_a[ia];
   const uint32_t tb = P.str_b[colc];
   const uint32_t n_orb = P.n_orb;
+
+  double ar4[4] = {0.0, 0.0, 0.0, 0.0}, ai4[4] = {0.0, 0.0, 0.0, 0.0};
+
+  // pass A: runs of consecutive simple classes.  A batch of classes shares
+  // one cooperative fold; its valid source rows are listed (in class order)
+  // in LDS and gathered kGather at a time, so the row loads overlap.  This
+  // pass runs before the move cache below exists, leaving registers for the
+  // loads in flight.
+  for (uint32_t r = 0; r < P.n_runs; ++r) {
+    uint32_t c = P.runs[2 * r];
+    const uint32_t c_end = P.runs[2 * r + 1];
+    while (c < c_end) {
+      const uint32_t ua = P.meta[c].ua;
+      uint32_t ce = c + 1;
+      uint32_t ub = P.meta[c].u_end;
+      while (ce < c_end && ce - c + kGather - 1 < P.list_cap) {
+        const uint32_t ue = P.meta[ce].u_end;
+        if (ue - ua > f_cap) break;
+        ub = ue;
+        ++ce;
+      }
+      __syncthreads();
+      fold_uniques<REALC>(P, ua, ub, ta, s_F, s_Fz);
+      const uint32_t n_list = list_valid_rows<R16>(P, c, ce, ua, ta, s_rank, s_list, s_wcnt);
+      for (uint32_t e0 = 0; e0 < n_list; e0 += kGather) {
+        uint32_t rk[kGather], w[kGather];
+        double a_r[kGather], a_i[kGather];
+#pragma unroll
+        for (int i = 0; i < kGather; ++i) {
+          const uint2 L = s_list[e0 + i];
+          rk[i] = __builtin_amdgcn_readfirstlane(L.x);
+          w[i] = __builtin_amdgcn_readfirstlane(L.y);
+        }
+#pragma unroll
+        for (int i = 0; i < kGather; ++i) ld_amp<T>(psi, static_cast<uint64_t>(rk[i]) * db + colc, a_r[i], a_i[i]);
+#pragma unroll
+        for (int i = 0; i < kGather; ++i) {
+          V f = C::zero();
+          phase_sum_lds<REALC>(s_F, s_Fz, w[i] & 0xffffu, w[i] >> 16, tb, f);
+          C::mac(f, a_r[i], a_i[i], ar4[i & 3], ai4[i & 3]);
+        }
+      }
+      c = ce;
+    }
+  }
 
   // Pair moves of this lane's target (occupied p -> empty q), packed as
   // source rank | pair index << 16, occupied-major.
@@ -424,53 +480,11 @@ __device__ __forceinline__ void sector_body(const SectorArgs& P, const T* __rest
     }
   }
 
-  double ar4[4] = {0.0, 0.0, 0.0, 0.0}, ai4[4] = {0.0, 0.0, 0.0, 0.0};
-  uint32_t c = 0;
-  while (c < P.n_class) {
-    const ClassMeta M = ld_meta(P.meta + c);
-    if (M.flags & kClassSimple) {
-      // consecutive single-group classes share one cooperative fold; their
-      // valid source rows are listed (in class order) in LDS and gathered
-      // four at a time so the row loads overlap
-      const uint32_t ua = M.ua;
-      uint32_t ce = c + 1;
-      uint32_t ub = M.u_end;
-      while (ce < P.n_class && ce - c + 3 < P.list_cap) {
-        const ClassMeta N = ld_meta(P.meta + ce);
-        if (!(N.flags & kClassSimple) || N.u_end - ua > f_cap) break;
-        ub = N.u_end;
-        ++ce;
-      }
-      __syncthreads();
-      fold_uniques<REALC>(P, ua, ub, ta, s_F, s_Fz);
-      const uint32_t n_list = list_valid_rows<R16>(P, c, ce, ua, ta, s_rank, s_list, s_wcnt);
-      for (uint32_t e0 = 0; e0 < n_list; e0 += 4) {
-        uint32_t rk[4], w[4];
-        double a_r[4], a_i[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const uint2 L = s_list[e0 + i];
-          rk[i] = __builtin_amdgcn_readfirstlane(L.x);
-          w[i] = __builtin_amdgcn_readfirstlane(L.y);
-        }
-#pragma unroll
-        for (int i = 0; i < 4; ++i) ld_amp<T>(psi, static_cast<uint64_t>(rk[i]) * db + colc, a_r[i], a_i[i]);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          V f = C::zero();
-          phase_sum_lds<REALC>(s_F, s_Fz, w[i] & 0xffffu, w[i] >> 16, tb, f);
-          C::mac(f, a_r[i], a_i[i], ar4[i], ai4[i]);
-        }
-      }
-      c = ce;
-      continue;
-    }
-
+  // pass B: every other class, in class order
+  for (uint32_t ic = 0; ic < P.n_ns; ++ic) {
+    const ClassMeta M = ld_meta(P.meta + P.ns_list[ic]);
     const uint32_t sa = ta ^ M.xa;
-    if (static_cast<uint32_t>(__popc(sa)) != P.n_alpha) {
-      ++c;
-      continue;
-    }
+    if (static_cast<uint32_t>(__popc(sa)) != P.n_alpha) continue;
     const uint64_t rowoff = static_cast<uint64_t>(rank_of<R16>(sa, P, s_rank)) * db;
     const uint32_t gz_end = M.zg >= 0 ? M.g0 + 1 : M.g0;
     // enumerate pair moves when the class's pair groups are dense enough
@@ -516,7 +530,7 @@ __device__ __forceinline__ void sector_body(const SectorArgs& P, const T* __rest
     }
     const T* rowp = ROWLDS ? s_row : rowg;  // pair and scanned groups need the staged row
     if (penum) {
-      uint32_t n_moves = P.n_moves;
+      uint32_t n_moves = __builtin_amdgcn_readfirstlane(P.n_moves);
       asm volatile("" : "+s"(n_moves));  // keep the move predicates inside the class loop
       if (single) {
         // straight-line groups of four moves: one unique per pair group; absent
@@ -571,9 +585,13 @@ __device__ __forceinline__ void sector_body(const SectorArgs& P, const T* __rest
       for (uint32_t q = threadIdx.x; q < P.n_quads; q += kSB) {
         const int32_t g = qm[q];
         s_qu[q] = g >= 0 ? ((P.pg_u0[g] - M.u_p) | ((P.pg_u0[g + 1] - P.pg_u0[g]) << 16)) : (f_cap | (1u << 16));
+        // with a uniform count, absent groups read that many zero slots
       }
       __syncthreads();
-      quad_moves<R16, REALC>(P, tb, s_rank, s_F, s_Fz, s_qu, rowp, ar4, ai4);
+      if (P.quad_cnt == 3)
+        quad_moves<3, R16, REALC>(P, tb, s_rank, s_F, s_Fz, s_qu, rowp, ar4, ai4);
+      else
+        quad_moves<0, R16, REALC>(P, tb, s_rank, s_F, s_Fz, s_qu, rowp, ar4, ai4);
     }
 
     // phase B: remaining groups, scanned in chunks whose uniques fit in LDS;
@@ -607,7 +625,6 @@ __device__ __forceinline__ void sector_body(const SectorArgs& P, const T* __rest
       if (g < ge) scan_group<R16, REALC>(P, g, us, tb, s_rank, s_F, s_Fz, rowp, ar4[2], ai4[2]);
       gs = ge;
     }
-    ++c;
   }
 
   const double acc_r = (ar4[0] + ar4[1]) + (ar4[2] + ar4[3]);
@@ -658,19 +675,6 @@ struct BatchJob {
   uint64_t pad;
 };
 
-template <class X>
-__device__ inline X ld_words(const X* p) {
-  static_assert(sizeof(X) % 4 == 0, "word-sized record");
-  constexpr int kW = sizeof(X) / 4;
-  const uint32_t* q = reinterpret_cast<const uint32_t*>(p);
-  uint32_t w[kW];
-#pragma unroll
-  for (int i = 0; i < kW; ++i) w[i] = ldc(q + i);
-  X v;
-  memcpy(&v, w, sizeof(v));
-  return v;
-}
-
 // All jobs of a batch in one launch: workgroup b belongs to the job with the
 // largest block_base <= b (jobs are stored in block order).
 template <class T, bool EXPVAL, bool R16, bool ROWLDS, bool REALC>
@@ -684,7 +688,9 @@ __global__ __launch_bounds__(kSB) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     else
       hi = mid;
   }
-  const BatchJob J = ld_words(jobs + lo);
+  // fields are read from the (read-only) job table where they are used, so
+  // the record is not held in registers for the whole kernel
+  const BatchJob& J = jobs[lo];
   const uint32_t b = blockIdx.x - J.block_base;
   sector_body<T, EXPVAL, R16, ROWLDS, REALC>(J.args, static_cast<const T*>(J.psi), static_cast<T*>(J.out),
                                              partial + 3ull * blockIdx.x, b / J.chunks, b % J.chunks);
