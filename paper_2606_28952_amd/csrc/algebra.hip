@@ -64,12 +64,81 @@ __global__ void k_segment_starts(const uint32_t* heads, const uint32_t* segid, u
     if (heads[i]) start[segid[i]] = static_cast<uint32_t>(i);
 }
 
-// One thread per run of equal keys: correctly rounded sums of its
-// contributions, then the drop test.
+// Fast path of the correctly rounded segment sums.  Cascaded TWO-SUM (the
+// Sum2 scheme of Ogita, Rump and Oishi, 2005) gives s = fl(sum x) and the
+// exact rounding errors q_j, so the exact sum is T = s + sum q_j.  Recursive
+// summation gives |fl(sum q_j) - sum q_j| <= gamma_n sum |q_j| and
+// sum |q_j| <= e / (1 - gamma_n) for e = fl(sum |q_j|), gamma_n = n u / (1 - n u),
+// u = 2^-53; for n u <= 1/4 both together are at most 2 n u e.  With
+// r = fl(s + c) and its exact error er, |T - r| <= |er| + 2 n u e; when this
+// (rounded upward) is below half the smaller gap next to r, r is the
+// round-to-nearest value of T.  When every q_j is zero, s is exact.
+struct Sum2 {
+  double s = 0.0, c = 0.0, e = 0.0;
+};
+
+__device__ inline void sum2_add(Sum2& a, double v) {
+  double t, q;
+  two_sum(a.s, v, t, q);
+  a.s = t;
+  a.c += q;
+  a.e += fabs(q);
+}
+
+// True when r is proven to be the correctly rounded sum of n values.
+__device__ inline bool sum2_round(const Sum2& a, uint32_t n, double& r) {
+  if (a.e == 0.0) {
+    r = a.s + 0.0;
+    return true;
+  }
+  double rr, er;
+  two_sum(a.s, a.c, rr, er);
+  if (rr == 0.0 || !isfinite(rr) || n >= (1u << 30)) return false;
+  const double two_nu = static_cast<double>(n) * 0x1p-52;  // exact: n < 2^30
+  const double bound = (fabs(er) + two_nu * a.e * (1.0 + 0x1p-50)) * (1.0 + 0x1p-50);
+  const double ar = fabs(rr);
+  const double below = __longlong_as_double(__double_as_longlong(ar) - 1);  // next double toward zero
+  if (bound < 0.5 * (ar - below)) {
+    r = rr + 0.0;
+    return true;
+  }
+  return false;
+}
+
+// One thread per run of equal keys: certified fast sums, then the drop test;
+// runs the fast path cannot certify are queued for k_segment_sum_exact.
 __global__ void k_segment_sum(uint32_t nseg, uint64_t m, const uint32_t* start, const uint32_t* order, const double* re,
                               const double* im, double eps_drop, double* out_re, double* out_im, uint32_t* keep,
-                              uint32_t* overflow) {
+                              uint32_t* n_slow, uint32_t* slow) {
   for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < nseg; u += gridDim.x * blockDim.x) {
+    const uint32_t b = start[u];
+    const uint32_t e = (u + 1 < nseg) ? start[u + 1] : static_cast<uint32_t>(m);
+    Sum2 ar, ai;
+    for (uint32_t j = b; j < e; ++j) {
+      const uint32_t v = order[j];
+      sum2_add(ar, re[v]);
+      sum2_add(ai, im[v]);
+    }
+    double r, i;
+    if (sum2_round(ar, e - b, r) && sum2_round(ai, e - b, i)) {
+      out_re[u] = r;
+      out_im[u] = i;
+      keep[u] = (fmax(fabs(r), fabs(i)) > eps_drop) ? 1u : 0u;
+    } else {
+      slow[atomicAdd(n_slow, 1u)] = u;
+    }
+  }
+}
+
+// Exact expansions for the queued runs (their order in the queue does not
+// matter: each run's result depends on its contributions only).
+__global__ void k_segment_sum_exact(uint32_t nseg, uint64_t m, const uint32_t* start, const uint32_t* order,
+                                    const double* re, const double* im, double eps_drop, const uint32_t* n_slow,
+                                    const uint32_t* slow, double* out_re, double* out_im, uint32_t* keep,
+                                    uint32_t* overflow) {
+  const uint32_t n = *n_slow;
+  for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+    const uint32_t u = slow[k];
     const uint32_t b = start[u];
     const uint32_t e = (u + 1 < nseg) ? start[u + 1] : static_cast<uint32_t>(m);
     ExactAcc ar, ai;
@@ -288,17 +357,21 @@ void canonicalize_soa(uint32_t n_qubits, int W, uint64_t m, DevBuf<uint64_t>& ke
   mark_heads(keys.get(), m, nw, heads.get(), s);
   exclusive_scan_u32(heads.get(), segid.get(), m, cnt.get(), s);
   const uint32_t nseg = read_scalar(cnt.get(), s);
-  DevBuf<uint32_t> start(nseg), keep(nseg), pos(nseg), overflow(1);
+  DevBuf<uint32_t> start(nseg), keep(nseg), pos(nseg), flags(2), slow(nseg);
   DevBuf<double> sre(nseg), sim(nseg);
-  PBS_HIP(hipMemsetAsync(overflow.get(), 0, sizeof(uint32_t), s));
+  uint32_t* overflow = flags.get();
+  uint32_t* n_slow = flags.get() + 1;
+  PBS_HIP(hipMemsetAsync(flags.get(), 0, 2 * sizeof(uint32_t), s));
   hipLaunchKernelGGL(k_segment_starts, dim3(grid_for(m, 256, 65536)), dim3(256), 0, s, heads.get(), segid.get(), m,
                      start.get());
   hipLaunchKernelGGL(k_segment_sum, dim3(grid_for(nseg, 128, 65536)), dim3(128), 0, s, nseg, m, start.get(),
-                     order.get(), re.get(), im.get(), eps_drop, sre.get(), sim.get(), keep.get(), overflow.get());
+                     order.get(), re.get(), im.get(), eps_drop, sre.get(), sim.get(), keep.get(), n_slow, slow.get());
+  hipLaunchKernelGGL(k_segment_sum_exact, dim3(64), dim3(64), 0, s, nseg, m, start.get(), order.get(), re.get(),
+                     im.get(), eps_drop, n_slow, slow.get(), sre.get(), sim.get(), keep.get(), overflow);
   PBS_HIP(hipGetLastError());
   exclusive_scan_u32(keep.get(), pos.get(), nseg, cnt.get() + 1, s);
   const uint32_t nkeep = read_scalar(cnt.get() + 1, s);
-  PBS_REQUIRE(read_scalar(overflow.get(), s) == 0, PBS_ERR_RANGE,
+  PBS_REQUIRE(read_scalar(overflow, s) == 0, PBS_ERR_RANGE,
               "exact summation needed more than the supported number of expansion components");
   out.n_terms = nkeep;
   out.x.alloc(static_cast<uint64_t>(nkeep) * W);

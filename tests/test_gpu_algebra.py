@@ -90,6 +90,53 @@ def test_canonicalize_bit_exact(dev, n, m, pool, spread, eps):
     assert s.info()[2]
 
 
+def _adversarial_segments():
+    """Coefficient lists whose correctly rounded sums are decided by ties,
+    tiny tails, cancellation or subnormals (one list per distinct string)."""
+    t = 2.0 ** -53
+    rng = np.random.default_rng(77)
+    lists = [
+        [1.0, t],                          # exact tie: rounds to even (1.0)
+        [1.0, t, 2.0 ** -200],             # just above the tie: 1 + 2^-52
+        [1.0, t, -(2.0 ** -200)],          # just below the tie: 1.0
+        [-1.0, -t, -(2.0 ** -200)],        # mirrored
+        [1e300, 1.0, -1e300],              # cancellation leaves 1.0
+        [1e16, 1.0, -1e16, t],             # cancellation with a tail
+        [2.0 ** -1074, 2.0 ** -1074, -(2.0 ** -1073)],  # subnormals summing to zero
+        [2.0 ** -1074] * 3,                # subnormal sum
+        [0.1] * 10,                        # classic rounding drift
+        list(rng.standard_normal(5000) * 10.0 ** rng.integers(-8, 9, 5000)),  # long run
+        [3.0, -3.0],                       # exact zero
+    ]
+    return lists
+
+
+def test_canonicalize_adversarial_sums(dev):
+    api = _api()
+    n = 6
+    lists = _adversarial_segments()
+    rows, coeffs = [], []
+    for k, vals in enumerate(lists):
+        for j, v in enumerate(vals):
+            rows.append(k)
+            # imaginary parts reuse another list so both parts are exercised
+            other = lists[(k + 3) % len(lists)]
+            coeffs.append(complex(v, other[j % len(other)]))
+    rows = np.array(rows)
+    perm = np.random.default_rng(5).permutation(len(rows))
+    rows = rows[perm]
+    c = np.array(coeffs, dtype=np.complex128)[perm]
+    x = (rows.astype(np.uint64) % 64).reshape(-1, 1)
+    z = (rows.astype(np.uint64) // 64 + 1).reshape(-1, 1)
+    s = api.PauliSum.create(n, x.reshape(-1), z.reshape(-1), c)
+    s.canonicalize(0.0)
+    gx, gz, gc = s.read()
+    rx, rz, rc = opauli.canonicalize_xz(x, z, c.real, c.imag, 0.0)
+    np.testing.assert_array_equal(gx, rx)
+    np.testing.assert_array_equal(gz, rz)
+    assert gc.tobytes() == rc.tobytes()
+
+
 def test_canonicalize_empty(dev):
     api = _api()
     s = api.PauliSum.create(10, np.zeros(0, np.uint64), np.zeros(0, np.uint64), np.zeros(0, np.complex128))
