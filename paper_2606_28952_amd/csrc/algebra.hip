@@ -66,15 +66,20 @@ __global__ void k_segment_starts(const uint32_t* heads, const uint32_t* segid, u
 
 // Fast path of the correctly rounded segment sums.  Cascaded TWO-SUM (the
 // Sum2 scheme of Ogita, Rump and Oishi, 2005) gives s = fl(sum x) and the
-// exact rounding errors q_j, so the exact sum is T = s + sum q_j.  Recursive
-// summation gives |fl(sum q_j) - sum q_j| <= gamma_n sum |q_j| and
-// sum |q_j| <= e / (1 - gamma_n) for e = fl(sum |q_j|), gamma_n = n u / (1 - n u),
-// u = 2^-53; for n u <= 1/4 both together are at most 2 n u e.  With
-// r = fl(s + c) and its exact error er, |T - r| <= |er| + 2 n u e; when this
-// (rounded upward) is below half the smaller gap next to r, r is the
-// round-to-nearest value of T.  When every q_j is zero, s is exact.
+// exact rounding errors q_j, so the exact sum is T = s + sum q_j.  The lanes
+// of a wave sum strided parts of a run and are merged by TWO-SUM as well, so
+// at most N = n + 64 error terms arise; any summation tree of them gives
+// |fl(sum q_j) - sum q_j| <= gamma_N sum |q_j| and sum |q_j| <= e / (1 - gamma_N)
+// for e = fl(sum |q_j|), gamma_N = N u / (1 - N u), u = 2^-53, so for N u <= 1/4
+// the compensation c is within 2 N u e.  With r = fl(s + c) and its exact
+// error er, |T - r| <= |er| + 2 N u e; when this (rounded upward) is below
+// half the smaller gap next to r, r is the round-to-nearest value of T.  T is
+// also a multiple of g, the smallest unit in the last place among the
+// inputs, so r = 0 with a bound below g proves T = 0.  When every q_j is
+// zero, s is exact.
 struct Sum2 {
   double s = 0.0, c = 0.0, e = 0.0;
+  int emin = 2047;  // smallest max(biased exponent, 1) over nonzero inputs
 };
 
 __device__ inline void sum2_add(Sum2& a, double v) {
@@ -83,19 +88,44 @@ __device__ inline void sum2_add(Sum2& a, double v) {
   a.s = t;
   a.c += q;
   a.e += fabs(q);
+  const int be = static_cast<int>((static_cast<uint64_t>(__double_as_longlong(v)) >> 52) & 0x7ffu);
+  if (v != 0.0) a.emin = min(a.emin, max(be, 1));
 }
 
-// True when r is proven to be the correctly rounded sum of n values.
-__device__ inline bool sum2_round(const Sum2& a, uint32_t n, double& r) {
+__device__ inline void sum2_merge(Sum2& a, double s, double c, double e, int emin) {
+  double t, q;
+  two_sum(a.s, s, t, q);
+  a.s = t;
+  a.c = (a.c + c) + q;
+  a.e = (a.e + e) + fabs(q);
+  a.emin = min(a.emin, emin);
+}
+
+__device__ inline void sum2_wave_merge(Sum2& a) {
+  for (int d = 32; d > 0; d >>= 1)
+    sum2_merge(a, __shfl_xor(a.s, d, 64), __shfl_xor(a.c, d, 64), __shfl_xor(a.e, d, 64),
+               __shfl_xor(a.emin, d, 64));
+}
+
+// True when r is proven to be the correctly rounded sum (N error terms at most).
+__device__ inline bool sum2_round(const Sum2& a, uint32_t N, double& r) {
   if (a.e == 0.0) {
     r = a.s + 0.0;
     return true;
   }
+  if (N >= (1u << 30)) return false;
   double rr, er;
   two_sum(a.s, a.c, rr, er);
-  if (rr == 0.0 || !isfinite(rr) || n >= (1u << 30)) return false;
-  const double two_nu = static_cast<double>(n) * 0x1p-52;  // exact: n < 2^30
+  if (!isfinite(rr)) return false;
+  const double two_nu = static_cast<double>(N) * 0x1p-52;  // exact: N < 2^30
   const double bound = (fabs(er) + two_nu * a.e * (1.0 + 0x1p-50)) * (1.0 + 0x1p-50);
+  if (rr == 0.0) {  // s + c = 0 exactly; T is a multiple of g with |T| <= bound
+    if (a.emin < 2047 && bound < ldexp(1.0, a.emin - 1075)) {
+      r = 0.0;
+      return true;
+    }
+    return false;
+  }
   const double ar = fabs(rr);
   const double below = __longlong_as_double(__double_as_longlong(ar) - 1);  // next double toward zero
   if (bound < 0.5 * (ar - below)) {
@@ -105,27 +135,35 @@ __device__ inline bool sum2_round(const Sum2& a, uint32_t n, double& r) {
   return false;
 }
 
-// One thread per run of equal keys: certified fast sums, then the drop test;
+// One wave per run of equal keys: certified fast sums, then the drop test;
 // runs the fast path cannot certify are queued for k_segment_sum_exact.
-__global__ void k_segment_sum(uint32_t nseg, uint64_t m, const uint32_t* start, const uint32_t* order, const double* re,
-                              const double* im, double eps_drop, double* out_re, double* out_im, uint32_t* keep,
-                              uint32_t* n_slow, uint32_t* slow) {
-  for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < nseg; u += gridDim.x * blockDim.x) {
+__global__ __launch_bounds__(256) void k_segment_sum(uint32_t nseg, uint64_t m, const uint32_t* start,
+                                                     const uint32_t* order, const double* re, const double* im,
+                                                     double eps_drop, double* out_re, double* out_im, uint32_t* keep,
+                                                     uint32_t* n_slow, uint32_t* slow) {
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const uint32_t n_waves = (gridDim.x * blockDim.x) >> 6;
+  for (uint32_t u = wave; u < nseg; u += n_waves) {
     const uint32_t b = start[u];
     const uint32_t e = (u + 1 < nseg) ? start[u + 1] : static_cast<uint32_t>(m);
     Sum2 ar, ai;
-    for (uint32_t j = b; j < e; ++j) {
+    for (uint32_t j = b + lane; j < e; j += 64) {
       const uint32_t v = order[j];
       sum2_add(ar, re[v]);
       sum2_add(ai, im[v]);
     }
-    double r, i;
-    if (sum2_round(ar, e - b, r) && sum2_round(ai, e - b, i)) {
-      out_re[u] = r;
-      out_im[u] = i;
-      keep[u] = (fmax(fabs(r), fabs(i)) > eps_drop) ? 1u : 0u;
-    } else {
-      slow[atomicAdd(n_slow, 1u)] = u;
+    sum2_wave_merge(ar);
+    sum2_wave_merge(ai);
+    if (lane == 0) {
+      double r, i;
+      if (sum2_round(ar, e - b + 64, r) && sum2_round(ai, e - b + 64, i)) {
+        out_re[u] = r;
+        out_im[u] = i;
+        keep[u] = (fmax(fabs(r), fabs(i)) > eps_drop) ? 1u : 0u;
+      } else {
+        slow[atomicAdd(n_slow, 1u)] = u;
+      }
     }
   }
 }
@@ -364,10 +402,11 @@ void canonicalize_soa(uint32_t n_qubits, int W, uint64_t m, DevBuf<uint64_t>& ke
   PBS_HIP(hipMemsetAsync(flags.get(), 0, 2 * sizeof(uint32_t), s));
   hipLaunchKernelGGL(k_segment_starts, dim3(grid_for(m, 256, 65536)), dim3(256), 0, s, heads.get(), segid.get(), m,
                      start.get());
-  hipLaunchKernelGGL(k_segment_sum, dim3(grid_for(nseg, 128, 65536)), dim3(128), 0, s, nseg, m, start.get(),
+  hipLaunchKernelGGL(k_segment_sum, dim3(grid_for(64ull * nseg, 256, 65536)), dim3(256), 0, s, nseg, m, start.get(),
                      order.get(), re.get(), im.get(), eps_drop, sre.get(), sim.get(), keep.get(), n_slow, slow.get());
-  hipLaunchKernelGGL(k_segment_sum_exact, dim3(64), dim3(64), 0, s, nseg, m, start.get(), order.get(), re.get(),
-                     im.get(), eps_drop, n_slow, slow.get(), sre.get(), sim.get(), keep.get(), overflow);
+  hipLaunchKernelGGL(k_segment_sum_exact, dim3(grid_for(nseg, 64, 65536)), dim3(64), 0, s, nseg, m, start.get(),
+                     order.get(), re.get(), im.get(), eps_drop, n_slow, slow.get(), sre.get(), sim.get(), keep.get(),
+                     overflow);
   PBS_HIP(hipGetLastError());
   exclusive_scan_u32(keep.get(), pos.get(), nseg, cnt.get() + 1, s);
   const uint32_t nkeep = read_scalar(cnt.get() + 1, s);
