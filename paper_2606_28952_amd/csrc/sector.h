@@ -157,7 +157,7 @@ constexpr uint32_t kListMinBytes = 4096u;  // simple-class row list when no row 
 // LDS copy of the uint16 rank tables (n_orb <= 16): chunk 0 with no ones
 // below it, then chunk 1 for 0..8 ones below it (zeros when n_orb <= 8)
 constexpr uint32_t kRank16Lds = 10u * 256u;
-constexpr int kGather = 8;  // simple-class row loads in flight per lane
+constexpr int kGather = 16;  // simple-class row loads in flight per lane
 constexpr uint32_t kZeroSlots = 4;  // zero entries after the folded uniques (absent groups, padding)
 
 struct SectorArgs {
@@ -328,17 +328,16 @@ __device__ __forceinline__ void quad_moves(const SectorArgs& P, uint32_t tb, con
   }
 }
 
-// Lists, in class order, the simple classes c0 .. c1-1 whose source alpha
-// string ta ^ X_alpha lies in the sector: entry = (source row rank, first
-// folded unique relative to ua | unique count << 16).  The list is padded to
-// a multiple of kGather with entries that read row 0 against the zero slot.
-// Returns the padded length; ends with the list visible to the workgroup.
+// Appends to the list, in class order, the simple classes c0 .. c1-1 whose
+// source alpha string ta ^ X_alpha lies in the sector: entry = (source row
+// rank, first folded unique | unique count << 16), where a class's uniques
+// sit at its unique index minus ubase.  Entries start at index `base`; the
+// new length is returned (uniform).  Ends with a barrier.
 template <bool R16>
-__device__ uint32_t list_valid_rows(const SectorArgs& P, uint32_t c0, uint32_t c1, uint32_t ua, uint32_t ta,
-                                    const uint16_t* s_rank, uint2* s_list, uint32_t* s_wcnt) {
+__device__ uint32_t append_valid_rows(const SectorArgs& P, uint32_t c0, uint32_t c1, uint32_t ubase, uint32_t ta,
+                                      const uint16_t* s_rank, uint2* s_list, uint32_t* s_wcnt, uint32_t base) {
   const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
   const uint64_t below = (1ull << lane) - 1ull;
-  uint32_t base = 0;
   for (uint32_t i0 = c0; i0 < c1; i0 += kSB) {
     const uint32_t cc = i0 + threadIdx.x;
     bool v = false;
@@ -347,7 +346,7 @@ __device__ uint32_t list_valid_rows(const SectorArgs& P, uint32_t c0, uint32_t c
       const ClassMeta* m = P.meta + cc;
       const uint32_t sa = ta ^ m->xa;
       v = static_cast<uint32_t>(__popc(sa)) == P.n_alpha;
-      if (v) entry = make_uint2(rank_of<R16>(sa, P, s_rank), (m->ua - ua) | ((m->u_end - m->ua) << 16));
+      if (v) entry = make_uint2(rank_of<R16>(sa, P, s_rank), (m->ua - ubase) | ((m->u_end - m->ua) << 16));
     }
     const uint64_t bal = __ballot(v);
     if (lane == 0) s_wcnt[wave] = static_cast<uint32_t>(__popcll(bal));
@@ -362,10 +361,7 @@ __device__ uint32_t list_valid_rows(const SectorArgs& P, uint32_t c0, uint32_t c
     base += total;
     __syncthreads();
   }
-  const uint32_t padded = (base + kGather - 1u) / kGather * kGather;
-  if (threadIdx.x < padded - base) s_list[base + threadIdx.x] = make_uint2(0u, P.f_cap | (1u << 16));
-  __syncthreads();
-  return padded;
+  return base;
 }
 
 // One workgroup: target alpha string ia (one row of the state), beta columns
@@ -407,28 +403,42 @@ __device__ __forceinline__ void sector_body(const SectorArgs& P, const T* __rest
 
   double ar4[4] = {0.0, 0.0, 0.0, 0.0}, ai4[4] = {0.0, 0.0, 0.0, 0.0};
 
-  // pass A: runs of consecutive simple classes.  A batch of classes shares
-  // one cooperative fold; its valid source rows are listed (in class order)
-  // in LDS and gathered kGather at a time, so the row loads overlap.  This
-  // pass runs before the move cache below exists, leaving registers for the
-  // loads in flight.
-  for (uint32_t r = 0; r < P.n_runs; ++r) {
-    uint32_t c = P.runs[2 * r];
-    const uint32_t c_end = P.runs[2 * r + 1];
-    while (c < c_end) {
-      const uint32_t ua = P.meta[c].ua;
-      uint32_t ce = c + 1;
-      uint32_t ub = P.meta[c].u_end;
-      while (ce < c_end && ce - c + kGather - 1 < P.list_cap) {
-        const uint32_t ue = P.meta[ce].u_end;
-        if (ue - ua > f_cap) break;
-        ub = ue;
-        ++ce;
+  // pass A: the simple classes (runs of consecutive ones).  A batch takes
+  // whole runs, or pieces of a long run, while their uniques fit in LDS and
+  // their classes in the list; each piece is folded at a running offset, the
+  // valid source rows of the batch are listed (in class order) and gathered
+  // kGather at a time, so the row loads overlap.  This pass runs before the
+  // move cache below exists, leaving registers for the loads in flight.
+  {
+    uint32_t r = 0;
+    uint32_t c = P.n_runs ? P.runs[0] : 0u;
+    while (r < P.n_runs) {
+      __syncthreads();  // the previous batch's list and folds are consumed
+      uint32_t n_list = 0, fo = 0;
+      while (r < P.n_runs) {
+        const uint32_t c_end = P.runs[2 * r + 1];
+        const uint32_t ua = P.meta[c].ua;
+        // the rest of the run if it fits what is left, else its longest piece that does
+        uint32_t ce = c_end;
+        if (fo + (P.meta[c_end - 1].u_end - ua) > f_cap || n_list + (c_end - c) + kGather - 1 > P.list_cap) {
+          ce = c;
+          while (ce < c_end && fo + (P.meta[ce].u_end - ua) <= f_cap &&
+                 n_list + (ce - c + 1) + kGather - 1 <= P.list_cap)
+            ++ce;
+        }
+        if (ce == c) break;  // nothing fits: close the batch
+        const uint32_t ub = P.meta[ce - 1].u_end;
+        fold_uniques<REALC>(P, ua, ub, ta, s_F + fo, s_Fz + fo);
+        n_list = append_valid_rows<R16>(P, c, ce, ua - fo, ta, s_rank, s_list, s_wcnt, n_list);
+        fo += ub - ua;
+        c = ce;
+        if (c == c_end && ++r < P.n_runs) c = P.runs[2 * r];
       }
+      // pad to a multiple of kGather with entries that read row 0 against a zero slot
+      const uint32_t padded = (n_list + kGather - 1u) / kGather * kGather;
+      if (threadIdx.x < padded - n_list) s_list[n_list + threadIdx.x] = make_uint2(0u, f_cap | (1u << 16));
       __syncthreads();
-      fold_uniques<REALC>(P, ua, ub, ta, s_F, s_Fz);
-      const uint32_t n_list = list_valid_rows<R16>(P, c, ce, ua, ta, s_rank, s_list, s_wcnt);
-      for (uint32_t e0 = 0; e0 < n_list; e0 += kGather) {
+      for (uint32_t e0 = 0; e0 < padded; e0 += kGather) {
         uint32_t rk[kGather], w[kGather];
         double a_r[kGather], a_i[kGather];
 #pragma unroll
@@ -446,7 +456,6 @@ __device__ __forceinline__ void sector_body(const SectorArgs& P, const T* __rest
           C::mac(f, a_r[i], a_i[i], ar4[i & 3], ai4[i & 3]);
         }
       }
-      c = ce;
     }
   }
 
