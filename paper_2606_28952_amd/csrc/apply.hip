@@ -121,6 +121,8 @@ Launch plan_sector(const pbs_grouped& h, const pbs_space& sp, size_t elem_bytes,
   a.pmap = h.pmap.get();
   a.qmap = h.qmap.get();
   a.quad_cnt = h.quad_cnt;
+  a.pair_sign = h.pair_sign ? 1u : 0u;
+  a.zpair = h.zpair.get();
   a.n_runs = h.n_runs;
   a.n_ns = h.n_ns;
   a.runs = h.runs.get();
@@ -142,7 +144,8 @@ Launch plan_sector(const pbs_grouped& h, const pbs_space& sp, size_t elem_bytes,
                h.n_pairs < 65536)
                   ? 1u
                   : 0u;
-  const uint32_t pu_bytes = a.enum_ok ? align16((h.n_pairs + 1) * 4) : 0u;
+  const uint32_t pu_bytes = kMiscBytes + kPuBytes;  // fixed: scratch and pair map (n_pairs + 1 <= 512 words)
+  PBS_REQUIRE(h.n_pairs + 1 <= kPuBytes / 4, PBS_ERR_RANGE, "too many orbital pairs for the pair map");
   const uint64_t n_ep = host_binom(sp.n_orb - sp.n_beta, 2), n_op = host_binom(sp.n_beta, 2);
   a.qenum_ok = (*r16 && a.enum_ok && h.n_qmap > 0 && h.n_quads > 0 && n_op * n_ep > 0) ? 1u : 0u;
   a.n_quads = h.n_quads;
@@ -167,17 +170,16 @@ Launch plan_sector(const pbs_grouped& h, const pbs_space& sp, size_t elem_bytes,
   const uint32_t fixed = base_fixed + qu_bytes;
   const uint32_t budget = fixed + f_min <= half ? half : limit;
   a.f_cap = std::min(kFCapMax, (budget - fixed - 64u) / per_unique - kZeroSlots);
-  uint32_t off = 0;
+  // layout: scratch [0, kMiscBytes), pair map at kPuOff, row or row list at
+  // kRowOff, then the rank tables, the folded uniques, their Z-masks and the
+  // quad map
+  uint32_t off = kRowOff + row_region;
   a.off_rank = off;
   off += rank_bytes;
-  a.off_row = off;
-  off += row_region;
   a.off_f = off;
   off += align16((a.f_cap + kZeroSlots) * (per_unique - 4u));
   a.off_fz = off;
   off += align16((a.f_cap + kZeroSlots) * 4u);
-  a.off_pu = off;
-  off += pu_bytes;
   a.off_qu = off;
   off += qu_bytes;
   *a_out = a;

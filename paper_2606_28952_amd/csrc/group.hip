@@ -387,6 +387,36 @@ static void build_sector_tables(pbs_grouped& g, const uint64_t* x, hipStream_t s
       }
     }
   }
+  // beta Z-masks of the single-unique pair groups, per orbital pair
+  {
+    std::vector<uint32_t> xb(g.n_pgroup), zb(g.n_unique);
+    PBS_HIP(hipMemcpy(xb.data(), g.pg_xb.get(), xb.size() * 4, hipMemcpyDeviceToHost));
+    PBS_HIP(hipMemcpy(zb.data(), g.u_zb.get(), zb.size() * 4, hipMemcpyDeviceToHost));
+    std::vector<uint32_t> zp(g.n_pairs + 1, 0u);
+    std::vector<char> seen(g.n_pairs + 1, 0);
+    bool uniform = true;
+    for (uint32_t c = 0; c < g.n_class && uniform; ++c) {
+      const ClassMeta& m = meta[c];
+      if (!(m.flags & kClassPairsSingle) || m.pm < 0) continue;
+      const uint32_t gz_end = m.zg >= 0 ? m.g0 + 1 : m.g0;
+      for (uint32_t q = gz_end; q < m.p1; ++q) {
+        const uint32_t x = xb[q];
+        const uint32_t lo = static_cast<uint32_t>(__builtin_ctz(x)), hi = 31u - static_cast<uint32_t>(__builtin_clz(x));
+        const uint32_t pid = hi * (hi - 1) / 2 + lo;
+        const uint32_t z = zb[u0[q]];
+        if (!seen[pid]) {
+          seen[pid] = 1;
+          zp[pid] = z;
+        } else if (zp[pid] != z) {
+          uniform = false;
+          break;
+        }
+      }
+    }
+    g.pair_sign = uniform && g.n_pairs > 0;
+    g.zpair.alloc(zp.size());
+    PBS_HIP(hipMemcpy(g.zpair.get(), zp.data(), zp.size() * 4, hipMemcpyHostToDevice));
+  }
   g.n_runs = static_cast<uint32_t>(runs.size() / 2);
   g.n_ns = static_cast<uint32_t>(ns.size());
   g.quad_cnt = qcnt > 0 ? static_cast<uint32_t>(qcnt) : 0u;

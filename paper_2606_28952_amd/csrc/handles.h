@@ -89,6 +89,12 @@ struct pbs_grouped {
   uint32_t n_runs = 0, n_ns = 0;
   pbs::DevBuf<uint32_t> runs, ns_list;
   uint32_t quad_cnt = 0;  // uniques of every mapped quad group when all are equal, else 0
+  // When every pair group of every kClassPairsSingle class has the beta
+  // Z-mask zpair[pair(p, q)] (a function of its two orbitals only, as for
+  // Jordan-Wigner strings), the kernel evaluates each move's beta parity
+  // once per target instead of once per class.
+  bool pair_sign = false;
+  pbs::DevBuf<uint32_t> zpair;
   pbs::DevBuf<uint32_t> pg_xb, pg_u0;
   pbs::DevBuf<uint32_t> u_zb, u_t0;
   pbs::DevBuf<uint32_t> pt_za;

@@ -86,9 +86,10 @@ __device__ inline ClassMeta ld_meta(const ClassMeta* p) {
   return m;
 }
 
+// Workgroup sums of (a, b, c) written by thread 0 to dst; red holds 3 B/64
+// doubles of LDS.
 template <int B>
-__device__ inline void block_reduce3_store(double a, double b, double c, double* dst) {
-  __shared__ double red[3][B / 64];
+__device__ inline void block_reduce3_store(double a, double b, double c, double* dst, double (*red)[B / 64]) {
   for (int d = 32; d > 0; d >>= 1) {
     a += __shfl_xor(a, d, 64);
     b += __shfl_xor(b, d, 64);
@@ -112,6 +113,12 @@ __device__ inline void block_reduce3_store(double a, double b, double c, double*
     dst[1] = s1;
     dst[2] = s2;
   }
+}
+
+template <int B>
+__device__ inline void block_reduce3_store(double a, double b, double c, double* dst) {
+  __shared__ double red[3][B / 64];
+  block_reduce3_store<B>(a, b, c, dst, red);
 }
 
 // ---------------------------------------------------------------- coefficients
@@ -158,6 +165,14 @@ constexpr uint32_t kListMinBytes = 4096u;  // simple-class row list when no row 
 // below it, then chunk 1 for 0..8 ones below it (zeros when n_orb <= 8)
 constexpr uint32_t kRank16Lds = 10u * 256u;
 constexpr int kGather = 16;  // simple-class row loads in flight per lane
+// Fixed LDS placement (the kernel declares no static LDS, so these are
+// absolute addresses): workgroup scratch at byte 0, the pair map at kPuOff
+// (one word per orbital pair, at most C(32, 2) + 1 entries) and the staged
+// row at kRowOff, so per-move addresses need no base register.
+constexpr uint32_t kMiscBytes = 256;  // ballot counts and the energy reduction
+constexpr uint32_t kPuOff = kMiscBytes;
+constexpr uint32_t kPuBytes = 2048;
+constexpr uint32_t kRowOff = kPuOff + kPuBytes;
 constexpr uint32_t kZeroSlots = 4;  // zero entries after the folded uniques (absent groups, padding)
 
 struct SectorArgs {
@@ -169,10 +184,12 @@ struct SectorArgs {
   uint32_t f_cap;     // folded uniques held in LDS at once; kZeroSlots zeros follow
   uint32_t qenum_ok, n_quads, n_qmoves;  // double-move enumeration (n_orb <= 16)
   uint32_t quad_cnt;                     // uniques of every quad group when all are equal, else 0
+  uint32_t pair_sign;                    // beta parities of pair moves cached per target (zpair)
+  const uint32_t* zpair;
   uint32_t n_runs, n_ns;                 // class schedule: simple-class runs, other classes
   const uint32_t* runs;                  // (first, end) per run
   const uint32_t* ns_list;
-  uint32_t off_rank, off_row, off_f, off_fz, off_pu, off_qu;  // LDS byte offsets
+  uint32_t off_rank, off_f, off_fz, off_qu;  // LDS byte offsets (the pair map and row are fixed)
   const uint32_t* str_a;
   const uint32_t* str_b;
   const uint16_t* rank16;  // n_orb <= 16
@@ -266,6 +283,16 @@ __device__ __forceinline__ void scan_group(const SectorArgs& P, uint32_t g, uint
 // One double move of this lane's target: X_beta = X (two occupied and two
 // empty orbitals).  The quad map slot gives the folded uniques of X's group
 // (absent groups point at the zero slot).
+// Source amplitude of a cached pair move: from the staged row at its LDS
+// byte offset, or from the global row.
+template <class T, bool ROWLDS>
+__device__ __forceinline__ void move_amp(const unsigned char* smem, const T* rowg, uint32_t e, double& r, double& m) {
+  if (ROWLDS)
+    Amp<T>::load(reinterpret_cast<const T*>(smem + kRowOff + (e & 0xffffu)), 0, r, m);
+  else
+    Amp<T>::load(rowg, e & 0xffffu, r, m);
+}
+
 // QC > 0: every quad group has QC uniques (absent groups point at QC zero
 // slots), so the phase sum is straight-line; QC = 0: counts from the map.
 template <int QC, bool R16, bool REALC, class T>
@@ -374,13 +401,14 @@ __device__ __forceinline__ void sector_body(const SectorArgs& P, const T* __rest
   using V = typename C::V;
   extern __shared__ __align__(16) unsigned char smem[];
   uint16_t* s_rank = reinterpret_cast<uint16_t*>(smem + P.off_rank);
-  T* s_row = reinterpret_cast<T*>(smem + P.off_row);
+  T* s_row = reinterpret_cast<T*>(smem + kRowOff);
   V* s_F = reinterpret_cast<V*>(smem + P.off_f);
   uint32_t* s_Fz = reinterpret_cast<uint32_t*>(smem + P.off_fz);
-  uint32_t* s_pu = reinterpret_cast<uint32_t*>(smem + P.off_pu);
+  uint32_t* s_pu = reinterpret_cast<uint32_t*>(smem + kPuOff);
   uint32_t* s_qu = reinterpret_cast<uint32_t*>(smem + P.off_qu);
-  uint2* s_list = reinterpret_cast<uint2*>(smem + P.off_row);  // shares the staged row's space
-  __shared__ uint32_t s_wcnt[kSB / 64];
+  uint2* s_list = reinterpret_cast<uint2*>(smem + kRowOff);  // shares the staged row's space
+  uint32_t* s_wcnt = reinterpret_cast<uint32_t*>(smem);      // kSB / 64 words
+  auto* s_red = reinterpret_cast<double(*)[kSB / 64]>(smem + 64);  // 3 x kSB / 64 doubles
   const uint32_t f_cap = P.f_cap;
 
   if (R16) {
@@ -459,11 +487,13 @@ __device__ __forceinline__ void sector_body(const SectorArgs& P, const T* __rest
     }
   }
 
-  // Pair moves of this lane's target (occupied p -> empty q), packed as
-  // source rank | pair index << 16, occupied-major.
+  // Pair moves of this lane's target (occupied p -> empty q), occupied-major,
+  // packed as: bits 0-15 the source column (its LDS byte offset in the staged
+  // row when rows are staged), bits 16-26 the pair-map byte offset 4 pair(p, q),
+  // bit 31 the move's beta parity popcount(zpair & t_b) when cached.
   uint32_t mv[kMaxMoves];
-  // padding moves point at pair index n_pairs (the zero slot) and column 0
-  const uint32_t pad_move = P.n_pairs << 16;
+  // padding moves point at map entry n_pairs (a zero slot) and column 0
+  const uint32_t pad_move = (4u * P.n_pairs) << 16;
   if (P.enum_ok) {
     const uint32_t full = (n_orb == 32) ? 0xffffffffu : ((1u << n_orb) - 1u);
     const uint32_t emp = ~tb & full;
@@ -478,7 +508,9 @@ __device__ __forceinline__ void sector_body(const SectorArgs& P, const T* __rest
         pm_emp &= pm_emp - 1;
         const uint32_t lo = p < q ? p : q, hi = p < q ? q : p;
         const uint32_t pair = hi * (hi - 1) / 2 + lo;
-        mv[k] = rank_of<R16>(tb ^ (1u << p) ^ (1u << q), P, s_rank) | (pair << 16);
+        const uint32_t src = rank_of<R16>(tb ^ (1u << p) ^ (1u << q), P, s_rank);
+        const uint32_t par = P.pair_sign ? (static_cast<uint32_t>(__popc(P.zpair[pair] & tb)) & 1u) : 0u;
+        mv[k] = (ROWLDS ? src * static_cast<uint32_t>(sizeof(T)) : src) | ((4u * pair) << 16) | (par << 31);
         if (++j == ne) {
           j = 0;
           pm_emp = emp;
@@ -498,7 +530,8 @@ __device__ __forceinline__ void sector_body(const SectorArgs& P, const T* __rest
     const uint32_t gz_end = M.zg >= 0 ? M.g0 + 1 : M.g0;
     // enumerate pair moves when the class's pair groups are dense enough
     const bool penum = P.enum_ok && M.pm >= 0 && (M.u_p - M.ua) <= f_cap && 2 * (M.p1 - gz_end) >= P.n_moves;
-    const bool single = penum && (M.flags & kClassPairsSingle);
+    // single-unique pair groups whose beta parities are cached per move
+    const bool single = penum && (M.flags & kClassPairsSingle) && P.pair_sign;
     const uint32_t ub_a = penum ? M.u_p : M.u_z;
     const bool fold_a = ub_a > M.ua && ub_a - M.ua <= f_cap;
     const bool stage = P.row_lds && gz_end < M.g1;
@@ -515,8 +548,8 @@ __device__ __forceinline__ void sector_body(const SectorArgs& P, const T* __rest
         for (uint32_t q = threadIdx.x; q <= P.n_pairs; q += kSB) {
           const int32_t g = q < P.n_pairs ? pm[q] : -1;  // entry n_pairs serves the padding moves
           uint32_t v;
-          if (single)
-            v = g >= 0 ? P.pg_u0[g] - M.ua : f_cap;
+          if (single)  // LDS byte address of the group's folded unique
+            v = P.off_f + (g >= 0 ? P.pg_u0[g] - M.ua : f_cap) * static_cast<uint32_t>(sizeof(V));
           else
             v = g >= 0 ? ((P.pg_u0[g] - M.ua) | ((P.pg_u0[g + 1] - P.pg_u0[g]) << 16)) : 0u;
           s_pu[q] = v;
@@ -547,23 +580,22 @@ __device__ __forceinline__ void sector_body(const SectorArgs& P, const T* __rest
 #pragma unroll
         for (int k0 = 0; k0 < kMaxMoves; k0 += 4) {
           if (static_cast<uint32_t>(k0) < n_moves) {
-            uint32_t e[4], sl[4], z[4];
+            uint32_t fa[4], e[4];
             V f[4];
             double a_r[4], a_i[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
               e[i] = mv[k0 + i];
               asm volatile("" : "+v"(e[i]));  // keep per-move address arithmetic inside the class loop
-              sl[i] = s_pu[e[i] >> 16];
+              fa[i] = *reinterpret_cast<const uint32_t*>(smem + kPuOff + ((e[i] >> 16) & 0x7ffu));
             }
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-              f[i] = s_F[sl[i]];
-              z[i] = s_Fz[sl[i]];
-              ld_amp<T>(rowp, e[i] & 0xffffu, a_r[i], a_i[i]);
+              f[i] = *reinterpret_cast<const V*>(smem + fa[i]);
+              move_amp<T, ROWLDS>(smem, rowg, e[i], a_r[i], a_i[i]);
             }
 #pragma unroll
-            for (int i = 0; i < 4; ++i) C::mac(C::sign(f[i], __popc(z[i] & tb)), a_r[i], a_i[i], ar4[i], ai4[i]);
+            for (int i = 0; i < 4; ++i) C::mac(C::sign(f[i], e[i] >> 31), a_r[i], a_i[i], ar4[i], ai4[i]);
           }
         }
       } else {
@@ -572,11 +604,11 @@ __device__ __forceinline__ void sector_body(const SectorArgs& P, const T* __rest
           if (static_cast<uint32_t>(k) < n_moves) {
             uint32_t e = mv[k];
             asm volatile("" : "+v"(e));
-            const uint32_t w = s_pu[e >> 16];
+            const uint32_t w = *reinterpret_cast<const uint32_t*>(smem + kPuOff + ((e >> 16) & 0x7ffu));
             V f = C::zero();
             phase_sum_lds<REALC>(s_F, s_Fz, w & 0xffffu, w >> 16, tb, f);
             double a_r, a_i;
-            ld_amp<T>(rowp, e & 0xffffu, a_r, a_i);
+            move_amp<T, ROWLDS>(smem, rowg, e, a_r, a_i);
             C::mac(f, a_r, a_i, ar4[k & 3], ai4[k & 3]);
           }
         }
@@ -652,7 +684,7 @@ __device__ __forceinline__ void sector_body(const SectorArgs& P, const T* __rest
       Amp<T>::store(out, t, acc_r, acc_i);
     }
   }
-  if (EXPVAL) block_reduce3_store<kSB>(e_re, e_im, nrm, slot);
+  if (EXPVAL) block_reduce3_store<kSB>(e_re, e_im, nrm, slot, s_red);
 }
 
 // Workgroup b takes row b mod dim_alpha and column chunk b / dim_alpha, so
