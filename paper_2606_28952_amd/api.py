@@ -119,7 +119,7 @@ class PauliSum:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value and _abi._LIB is not None:
+        if h is not None and h.value and _abi is not None and _abi._LIB is not None:
             _abi._LIB.pbs_sum_destroy(h)
             self._h = None
 
@@ -161,7 +161,7 @@ class Grouped:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value and _abi._LIB is not None:
+        if h is not None and h.value and _abi is not None and _abi._LIB is not None:
             _abi._LIB.pbs_grouped_destroy(h)
             self._h = None
 
@@ -213,7 +213,7 @@ class Space:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value and _abi._LIB is not None:
+        if h is not None and h.value and _abi is not None and _abi._LIB is not None:
             _abi._LIB.pbs_space_destroy(h)
             self._h = None
 
@@ -309,6 +309,6 @@ class Batch:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value and _abi._LIB is not None:
+        if h is not None and h.value and _abi is not None and _abi._LIB is not None:
             _abi._LIB.pbs_batch_destroy(h)
             self._h = None

@@ -261,6 +261,22 @@ __device__ inline void ld_amp(const T* p, uint64_t i, double& r, double& m) {
   Amp<T>::load(p, i, r, m);
 }
 
+// Validity, source column and phase sum of one scanned group (the phase sum
+// is zeroed for invalid targets, whose column is 0).
+template <bool R16, bool REALC>
+__device__ __forceinline__ void scan_prepare(const SectorArgs& P, uint32_t g, uint32_t us, uint32_t tb,
+                                             const uint16_t* s_rank, const typename Coef<REALC>::V* s_F,
+                                             const uint32_t* s_Fz, uint32_t& jb, typename Coef<REALC>::V& f) {
+  using C = Coef<REALC>;
+  const uint32_t xb = ldc(P.pg_xb + g);
+  const uint32_t u0 = ldc(P.pg_u0 + g), u1 = ldc(P.pg_u0 + g + 1);
+  const bool valid = 2u * __popc(tb & xb) == static_cast<uint32_t>(__popc(xb));
+  jb = valid ? rank_of<R16>(tb ^ xb, P, s_rank) : 0u;
+  typename C::V h = C::zero();
+  phase_sum_lds<REALC>(s_F, s_Fz, u0 - us, u1 - u0, tb, h);
+  f = C::zeroed_unless(h, valid);
+}
+
 // One group of a scanned chunk: validity of X_beta for this lane's target,
 // source column rank, phase sum from the folded uniques; invalid targets are
 // predicated off (column 0 is read, the coefficient is zeroed).
@@ -659,11 +675,18 @@ __device__ __forceinline__ void sector_body(const SectorArgs& P, const T* __rest
       fold_uniques<REALC>(P, us, P.pg_u0[ge], ta, s_F, s_Fz);
       __syncthreads();
       uint32_t g = gs;
-      for (; g + 1 < ge; g += 2) {
-        scan_group<R16, REALC>(P, g, us, tb, s_rank, s_F, s_Fz, rowp, ar4[2], ai4[2]);
-        scan_group<R16, REALC>(P, g + 1, us, tb, s_rank, s_F, s_Fz, rowp, ar4[3], ai4[3]);
+      for (; g + 3 < ge; g += 4) {  // four source loads in flight
+        uint32_t jb[4];
+        V f[4];
+        double a_r[4], a_i[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) scan_prepare<R16, REALC>(P, g + i, us, tb, s_rank, s_F, s_Fz, jb[i], f[i]);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) ld_amp<T>(rowp, jb[i], a_r[i], a_i[i]);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) C::mac(f[i], a_r[i], a_i[i], ar4[i], ai4[i]);
       }
-      if (g < ge) scan_group<R16, REALC>(P, g, us, tb, s_rank, s_F, s_Fz, rowp, ar4[2], ai4[2]);
+      for (; g < ge; ++g) scan_group<R16, REALC>(P, g, us, tb, s_rank, s_F, s_Fz, rowp, ar4[2], ai4[2]);
       gs = ge;
     }
   }
@@ -687,13 +710,32 @@ __device__ __forceinline__ void sector_body(const SectorArgs& P, const T* __rest
   if (EXPVAL) block_reduce3_store<kSB>(e_re, e_im, nrm, slot, s_red);
 }
 
-// Workgroup b takes row b mod dim_alpha and column chunk b / dim_alpha, so
-// the workgroups in flight at any time share one column chunk across many
-// rows.  (Keeping a row's chunks together on one XCD, or giving each XCD a
-// contiguous row range, measured 3-4% slower on the 28-qubit sector.)
-__device__ inline void row_chunk_of(uint32_t b, uint32_t rows, uint32_t& row, uint32_t& chunk) {
-  row = b % rows;
-  chunk = b / rows;
+// Order of the workgroups.  With source rows staged in LDS, workgroup b
+// takes row b mod dim_alpha and column chunk b / dim_alpha, so the
+// workgroups in flight share one column chunk across many rows (measured
+// best on the 28-qubit sector).  Without staging, pair-move gathers read
+// the source row through L2, so the chunks of one row run back to back on
+// one XCD (workgroup b runs on XCD b mod 8): rows are dealt to the XCDs in
+// groups of eight, and rows past the last full group take row-major order.
+constexpr uint32_t kXcds = 8;
+__device__ inline void row_chunk_of(uint32_t b, uint32_t rows, uint32_t chunks, bool row_fast, uint32_t& row,
+                                    uint32_t& chunk) {
+  if (row_fast) {
+    row = b % rows;
+    chunk = b / rows;
+    return;
+  }
+  const uint32_t grouped = rows / kXcds * kXcds;
+  const uint32_t full = grouped * chunks;
+  if (b < full) {
+    const uint32_t x = b % kXcds, j = b / kXcds;
+    row = j / chunks * kXcds + x;
+    chunk = j % chunks;
+  } else {
+    const uint32_t r = b - full;
+    row = grouped + r / chunks;
+    chunk = r % chunks;
+  }
 }
 
 // One-dimensional grid of dim_alpha * chunks workgroups.
@@ -702,7 +744,7 @@ __global__ __launch_bounds__(kSB) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     SectorArgs P, const T* __restrict__ psi, T* __restrict__ out, double* __restrict__ partial) {
   const uint32_t chunks = (P.dim_beta + kSB - 1) / kSB;
   uint32_t row, chunk;
-  row_chunk_of(blockIdx.x, gridDim.x / chunks, row, chunk);
+  row_chunk_of(blockIdx.x, gridDim.x / chunks, chunks, P.row_lds != 0, row, chunk);
   sector_body<T, EXPVAL, R16, ROWLDS, REALC>(P, psi, out, partial + 3ull * blockIdx.x, row, chunk);
 }
 
