@@ -94,12 +94,13 @@ def test_twelve_qubit_molecular_full_and_sector(dev):
 
 
 @pytest.mark.parametrize("n_o,na,nb", [(1, 0, 1), (1, 1, 1), (3, 1, 2), (4, 0, 4), (5, 2, 3), (9, 4, 5),
-                                       (11, 5, 5), (12, 6, 6), (13, 6, 6)])
+                                       (11, 5, 5), (12, 6, 6), (13, 6, 6), (15, 1, 7), (16, 1, 8)])
 def test_sector_projection_random_operator(dev, n_o, na, nb):
     """Non-conserving random operators: the sector result is P H P psi.  The
     operators carry many strings with even X popcounts per spin so that the
-    sector sees nonzero coupling; beta dimensions span 1 to 1716 columns
-    (several lanes per thread, ragged tails)."""
+    sector sees nonzero coupling; beta dimensions span 1 to 12,870 columns
+    (several lanes per thread, ragged tails; rows of 6,435 and 12,870
+    columns exceed LDS and are staged in tiles)."""
     api = _api()
     n = 2 * n_o
     rng = np.random.default_rng(n_o * 31 + na)
