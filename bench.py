@@ -45,8 +45,12 @@ def _source_hash():
     csrc = os.path.join(ROOT, "paper_2606_28952_amd", "csrc")
     for f in sorted(os.listdir(csrc)):
         if f.endswith((".hip", ".h")):
-            with open(os.path.join(csrc, f), "rb") as fh:
-                h.update(fh.read())
+            with open(os.path.join(csrc, f), encoding="utf-8") as fh:
+                # code only: comment and blank-line edits do not change the kernels
+                for line in fh:
+                    code = line.split("//", 1)[0].rstrip()
+                    if code:
+                        h.update(code.encode() + b"\n")
     return h.hexdigest()[:16]
 
 

@@ -19,17 +19,19 @@
 // the source row s_a = t_a ^ X_alpha, its validity and its rank are uniform
 // across the workgroup, and so are the alpha parities of every term: the
 // coefficients of each unique beta Z-mask are folded over their terms' alpha
-// parities cooperatively into LDS once per class.  Per class:
-//  * the group with X_beta = 0 gathers from the lane's own column;
-//  * groups whose X_beta flips two orbitals are visited by enumerating the
-//    lane's valid pair moves (occupied -> empty, the same count for every
-//    target of a sector), cached in registers with their source ranks, and a
-//    per-class pair map; invalid moves are never visited;
-//  * other groups are scanned with a per-lane validity test;
-//  * consecutive classes holding only an X_beta = 0 group share one fold,
-//    and their valid source rows are listed in LDS and gathered four at a
-//    time;
-//  * the source row is staged in LDS when it fits.
+// parities cooperatively into LDS once per class.
+//  * Simple classes (a single X_beta = 0 group) come first: runs of them are
+//    batched into one fold, their valid source rows are listed in LDS and
+//    gathered kGather at a time.
+//  * In every other class the source row is staged in LDS when it fits; the
+//    group with X_beta = 0 gathers from the lane's own column; groups whose
+//    X_beta flips two orbitals are visited by enumerating the lane's valid
+//    pair moves (occupied -> empty, the same count for every target of a
+//    sector), cached in registers with their source columns and beta
+//    parities, through a per-class pair map; groups whose X_beta flips four
+//    orbitals by enumerating the valid double moves through a quad map;
+//    invalid moves are never visited.  Other groups are scanned with a
+//    per-lane validity test.
 // Parities are evaluated against the target strings each lane holds; the
 // constant (-1)^popcount(z & X) factors were moved into the coefficients
 // when the tables were built.
