@@ -1,6 +1,7 @@
 // Pauli-string products, Pauli sums, canonical reduction and the direct
 // Jordan-Wigner construction (Sections 2.2-2.3, Algorithm 1).
 #include <cmath>
+#include <mutex>
 
 #include "exact_sum.h"
 #include "pbs_internal.h"
@@ -372,6 +373,70 @@ void check_sum(const pbs_sum* s) { PBS_REQUIRE(s != nullptr, PBS_ERR_ARG, "null 
 }  // namespace
 
 void set_last_error(const std::string& msg) { g_last_error = msg; }
+
+// ---------------------------------------------------------------- scratch arena
+struct Scratch::Arena {
+  std::mutex mu;
+  void* base = nullptr;
+  size_t cap = 0;
+};
+
+namespace {
+thread_local Scratch* tl_scratch = nullptr;
+
+Scratch::Arena* device_arena() {
+  static std::mutex mu;
+  static Scratch::Arena* arenas[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(mu);
+  if (!arenas[dev]) arenas[dev] = new Scratch::Arena();  // lives until the process ends
+  return arenas[dev];
+}
+}  // namespace
+
+Scratch::Scratch(hipStream_t s) : arena_(device_arena()), stream_(s), outer_(tl_scratch) {
+  if (outer_) {  // nested scope: share the outer scope's arena and cursor
+    arena_ = nullptr;
+  } else if (arena_) {
+    arena_->mu.lock();
+  }
+  tl_scratch = this;
+}
+
+Scratch::~Scratch() {
+  tl_scratch = outer_;
+  if (!arena_) return;
+  // temporaries may still be in use by queued work on the stream
+  (void)hipStreamSynchronize(stream_);
+  if (wanted_ > arena_->cap) {
+    if (arena_->base) (void)hipFree(arena_->base);
+    arena_->base = nullptr;
+    arena_->cap = 0;
+    const size_t grown = wanted_ + wanted_ / 4;
+    if (hipMalloc(&arena_->base, grown) == hipSuccess)
+      arena_->cap = grown;
+    else
+      arena_->base = nullptr;
+  }
+  (void)hipGetLastError();
+  arena_->mu.unlock();
+}
+
+void* Scratch::take(size_t bytes) {
+  if (outer_) return outer_->take(bytes);
+  const size_t need = (bytes + 255) & ~static_cast<size_t>(255);
+  const size_t at = top_;
+  top_ += need;
+  wanted_ = top_ > wanted_ ? top_ : wanted_;
+  if (!arena_ || !arena_->base || top_ > arena_->cap) return nullptr;
+  return static_cast<char*>(arena_->base) + at;
+}
+
+Scratch* Scratch::current() { return tl_scratch; }
 void clear_last_error() { g_last_error.clear(); }
 
 void canonicalize_soa(uint32_t n_qubits, int W, uint64_t m, DevBuf<uint64_t>& keys, DevBuf<double>& re,
@@ -388,15 +453,15 @@ void canonicalize_soa(uint32_t n_qubits, int W, uint64_t m, DevBuf<uint64_t>& ke
     return;
   }
   const int nw = 2 * W;
-  DevBuf<uint32_t> order(m);
+  DevBuf<uint32_t> order(m, s);
   iota_u32(order.get(), m, s);
   radix_sort_keys(keys.get(), order.get(), m, nw, s);
-  DevBuf<uint32_t> heads(m), segid(m), cnt(2);
+  DevBuf<uint32_t> heads(m, s), segid(m, s), cnt(2, s);
   mark_heads(keys.get(), m, nw, heads.get(), s);
   exclusive_scan_u32(heads.get(), segid.get(), m, cnt.get(), s);
   const uint32_t nseg = read_scalar(cnt.get(), s);
-  DevBuf<uint32_t> start(nseg), keep(nseg), pos(nseg), flags(2), slow(nseg);
-  DevBuf<double> sre(nseg), sim(nseg);
+  DevBuf<uint32_t> start(nseg, s), keep(nseg, s), pos(nseg, s), flags(2, s), slow(nseg, s);
+  DevBuf<double> sre(nseg, s), sim(nseg, s);
   uint32_t* overflow = flags.get();
   uint32_t* n_slow = flags.get() + 1;
   PBS_HIP(hipMemsetAsync(flags.get(), 0, 2 * sizeof(uint32_t), s));
@@ -458,6 +523,7 @@ pbs_status pbs_sum_create(uint32_t n_qubits, uint64_t n_terms, const uint64_t* x
     PBS_REQUIRE(n_terms < (1ull << 32), PBS_ERR_RANGE, "n_terms must be below 2^32");
     PBS_REQUIRE(n_terms == 0 || (x && z && coeff), PBS_ERR_ARG, "null array");
     hipStream_t s = as_stream(stream);
+    Scratch scratch(s);  // temporaries of this call
     auto* sum = new pbs_sum();
     try {
       sum->n_qubits = n_qubits;
@@ -472,7 +538,7 @@ pbs_status pbs_sum_create(uint32_t n_qubits, uint64_t n_terms, const uint64_t* x
         PBS_HIP(hipMemcpyAsync(sum->x.get(), x, nw * 8, hipMemcpyDefault, s));
         PBS_HIP(hipMemcpyAsync(sum->z.get(), z, nw * 8, hipMemcpyDefault, s));
         PBS_HIP(hipMemcpyAsync(sum->coeff.get(), coeff, 2 * n_terms * 8, hipMemcpyDefault, s));
-        DevBuf<unsigned long long> stray(1);
+        DevBuf<unsigned long long> stray(1, s);
         PBS_HIP(hipMemsetAsync(stray.get(), 0, sizeof(unsigned long long), s));
         hipLaunchKernelGGL(k_stray_bits, dim3(grid_for(n_terms, 256, 4096)), dim3(256), 0, s, sum->x.get(),
                            sum->z.get(), n_terms, sum->words, n_qubits, stray.get());
@@ -518,10 +584,11 @@ pbs_status pbs_pauli_canonicalize(pbs_sum* sum, double eps_drop, void* stream) {
     check_sum(sum);
     PBS_REQUIRE(!std::isnan(eps_drop), PBS_ERR_ARG, "eps_drop is NaN");
     hipStream_t s = as_stream(stream);
+    Scratch scratch(s);  // temporaries of this call
     const uint64_t m = sum->n_terms;
     const int W = sum->words;
-    DevBuf<uint64_t> keys(m * 2 * W);
-    DevBuf<double> re(m), im(m);
+    DevBuf<uint64_t> keys(m * 2 * W, s);
+    DevBuf<double> re(m, s), im(m, s);
     if (m) {
       hipLaunchKernelGGL(k_to_soa, dim3(grid_for(m, 256, 65536)), dim3(256), 0, s, m, W, sum->x.get(), sum->z.get(),
                          sum->coeff.get(), keys.get(), re.get(), im.get());
@@ -549,10 +616,11 @@ pbs_status pbs_pauli_sum_mul(const pbs_sum* a, const pbs_sum* b, double eps_drop
     PBS_REQUIRE(a->n_terms < (1ull << 30) && b->n_terms < (1ull << 30) && np < (1ull << 30), PBS_ERR_RANGE,
                 "product has 2^30 or more term pairs");
     hipStream_t s = as_stream(stream);
+    Scratch scratch(s);  // temporaries of this call
     const int W = a->words;
     const uint64_t m = 4 * np;
-    DevBuf<uint64_t> keys(m * 2 * W);
-    DevBuf<double> re(m), im(m);
+    DevBuf<uint64_t> keys(m * 2 * W, s);
+    DevBuf<double> re(m, s), im(m, s);
     if (np) {
       hipLaunchKernelGGL(k_sum_mul, dim3(grid_for(np, 256, 65536)), dim3(256), 0, s, a->n_terms, b->n_terms, W,
                          a->x.get(), a->z.get(), a->coeff.get(), b->x.get(), b->z.get(), b->coeff.get(), keys.get(),
@@ -579,14 +647,15 @@ pbs_status pbs_jw_transform(uint32_t n_spin_orb, const double* h1, const double*
     PBS_REQUIRE(h1 != nullptr, PBS_ERR_ARG, "null h1");
     PBS_REQUIRE(!std::isnan(eps) && !std::isnan(eps_drop), PBS_ERR_ARG, "threshold is NaN");
     hipStream_t s = as_stream(stream);
+    Scratch scratch(s);  // temporaries of this call
     const uint32_t n = n_spin_orb;
     const int W = words_for(n);
     const uint64_t n2 = static_cast<uint64_t>(n) * n;
     const uint64_t n4 = h2 ? n2 * n2 : 0;
-    DevBuf<uint32_t> flag1(n2), off1(n2), cnt(2);
+    DevBuf<uint32_t> flag1(n2, s), off1(n2, s), cnt(2, s);
     hipLaunchKernelGGL(k_flag_abs_gt, dim3(grid_for(n2, 256, 65536)), dim3(256), 0, s, h1, n2, eps, flag1.get());
     exclusive_scan_u32(flag1.get(), off1.get(), n2, cnt.get(), s);
-    DevBuf<uint32_t> flag2(n4), off2(n4);
+    DevBuf<uint32_t> flag2(n4, s), off2(n4, s);
     uint64_t k2 = 0;
     if (n4) {
       hipLaunchKernelGGL(k_flag_abs_gt, dim3(grid_for(n4, 256, 65536)), dim3(256), 0, s, h2, n4, eps, flag2.get());
@@ -596,8 +665,8 @@ pbs_status pbs_jw_transform(uint32_t n_spin_orb, const double* h1, const double*
     const uint64_t k1 = read_scalar(cnt.get(), s);
     const uint64_t m = 1 + 4 * k1 + 16 * k2;
     PBS_REQUIRE(m < (1ull << 32), PBS_ERR_RANGE, "more than 2^32 - 1 Pauli contributions");
-    DevBuf<uint64_t> keys(m * 2 * W);
-    DevBuf<double> re(m), im(m);
+    DevBuf<uint64_t> keys(m * 2 * W, s);
+    DevBuf<double> re(m, s), im(m, s);
     hipLaunchKernelGGL(k_jw_identity, dim3(1), dim3(1), 0, s, W, m, e0, keys.get(), re.get(), im.get());
     if (k1)
       hipLaunchKernelGGL(k_jw_one_body, dim3(grid_for(n2, 256, 65536)), dim3(256), 0, s, n, W, h1, flag1.get(),

@@ -248,9 +248,9 @@ static void build_sector_tables(pbs_grouped& g, const uint64_t* x, hipStream_t s
   const uint32_t h = g.n_qubits / 2;
   g.half = h;
   g.n_pairs = h * (h - 1) / 2;
-  DevBuf<uint32_t> alive(m), apos(m), cnt(4);
-  DevBuf<uint64_t> k2(m), k1(m), k0(m);
-  DevBuf<double> cre(m), cim(m);
+  DevBuf<uint32_t> alive(m, s), apos(m, s), cnt(4, s);
+  DevBuf<uint64_t> k2(m, s), k1(m, s), k0(m, s);
+  DevBuf<double> cre(m, s), cim(m, s);
   if (m) {
     hipLaunchKernelGGL(k_sector_terms, dim3(grid_for(m, 256, 65536)), dim3(256), 0, s, x, g.zk.get(), g.ck.get(), m,
                        h, alive.get(), k2.get(), k1.get(), k0.get(), cre.get(), cim.get());
@@ -273,8 +273,8 @@ static void build_sector_tables(pbs_grouped& g, const uint64_t* x, hipStream_t s
     PBS_HIP(hipStreamSynchronize(s));
     return;
   }
-  DevBuf<uint64_t> keys(3 * ma);
-  DevBuf<uint32_t> src(ma), order(ma);
+  DevBuf<uint64_t> keys(3 * ma, s);
+  DevBuf<uint32_t> src(ma, s), order(ma, s);
   hipLaunchKernelGGL(k_compact_alive, dim3(grid_for(m, 256, 65536)), dim3(256), 0, s, alive.get(), apos.get(), m,
                      k2.get(), k1.get(), k0.get(), keys.get(), ma);
   hipLaunchKernelGGL(k_alive_index, dim3(grid_for(m, 256, 65536)), dim3(256), 0, s, alive.get(), apos.get(), m,
@@ -282,7 +282,7 @@ static void build_sector_tables(pbs_grouped& g, const uint64_t* x, hipStream_t s
   PBS_HIP(hipGetLastError());
   iota_u32(order.get(), ma, s);
   radix_sort_keys(keys.get(), order.get(), ma, 3, s);
-  DevBuf<uint32_t> hc(ma), hg(ma), hu(ma), cid(ma), gid(ma), uid(ma);
+  DevBuf<uint32_t> hc(ma, s), hg(ma, s), hu(ma, s), cid(ma, s), gid(ma, s), uid(ma, s);
   hipLaunchKernelGGL(k_plan_heads, dim3(grid_for(ma, 256, 65536)), dim3(256), 0, s, keys.get(), ma, hc.get(),
                      hg.get(), hu.get());
   exclusive_scan_u32(hc.get(), cid.get(), ma, cnt.get() + 1, s);
@@ -324,7 +324,7 @@ static void build_sector_tables(pbs_grouped& g, const uint64_t* x, hipStream_t s
   g.cls_qm.alloc(g.n_class);
   const uint64_t n_quads = host_binom(h, 4);
   g.n_quads = n_quads <= kMaxQuads ? static_cast<uint32_t>(n_quads) : 0u;
-  DevBuf<uint32_t> has_pairs(g.n_class), has_quads(g.n_class), slot(g.n_class);
+  DevBuf<uint32_t> has_pairs(g.n_class, s), has_quads(g.n_class, s), slot(g.n_class, s);
   hipLaunchKernelGGL(k_class_meta, dim3(grid_for(g.n_class, 256, 65536)), dim3(256), 0, s, g.n_class,
                      g.cls_g0.get(), g.pg_pc.get(), g.n_quads > 0, g.cls_zg.get(), g.cls_p0.get(), g.cls_p1.get(),
                      g.cls_q1.get(), has_pairs.get(), has_quads.get());
@@ -440,12 +440,13 @@ pbs_status pbs_group_by_xmask(const pbs_sum* hs, void* stream, pbs_grouped** out
     PBS_REQUIRE(hs->canonical, PBS_ERR_ARG, "group_by_xmask needs a canonical sum");
     PBS_REQUIRE(hs->n_qubits <= 64, PBS_ERR_RANGE, "grouping supports at most 64 qubits");
     hipStream_t s = as_stream(stream);
+    Scratch scratch(s);  // temporaries of this call
     auto* g = new pbs_grouped();
     try {
       const uint64_t m = hs->n_terms;
       g->n_qubits = hs->n_qubits;
       g->n_terms = m;
-      DevBuf<uint32_t> heads(m), gid(m), cnt(1);
+      DevBuf<uint32_t> heads(m, s), gid(m, s), cnt(1, s);
       uint64_t G = 0;
       if (m) {
         hipLaunchKernelGGL(k_x_heads, dim3(grid_for(m, 256, 65536)), dim3(256), 0, s, hs->x.get(), m, heads.get());

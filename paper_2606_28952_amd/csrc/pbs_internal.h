@@ -56,18 +56,58 @@ pbs_status guarded(F&& body) {
 }
 
 // ---------------------------------------------------------------- device memory
+// Scratch arena for the temporaries of one handle-building call.  Each
+// device keeps one device buffer; a call opens a Scratch scope (which holds
+// the device's arena for the call's duration), bump-allocates its
+// temporaries from it, and at scope end synchronizes the call's stream and
+// releases everything at once.  A request that does not fit falls back to
+// hipMalloc and makes the scope grow the arena for the next call.  This
+// replaces dozens of hipMalloc/hipFree pairs per call (each hipFree waits for
+// the device).
+class Scratch {
+ public:
+  explicit Scratch(hipStream_t s);
+  ~Scratch();
+  Scratch(const Scratch&) = delete;
+  Scratch& operator=(const Scratch&) = delete;
+  // 256-byte aligned bytes from the arena, or nullptr when they do not fit
+  void* take(size_t bytes);
+  static Scratch* current();  // innermost open scope of this thread, or nullptr
+  struct Arena;                // one per device (defined with the implementation)
+
+ private:
+  Arena* arena_;
+  hipStream_t stream_;
+  size_t top_ = 0, wanted_ = 0;
+  Scratch* outer_;
+};
+
 // Owning device buffer.  Allocation happens only in handle-building calls.
+// Buffers owned by a handle use hipMalloc; temporaries pass the call's
+// stream and come from the thread's open Scratch scope when there is one.
 template <class T>
 struct DevBuf {
   T* ptr = nullptr;
   size_t n = 0;
+  bool borrowed = false;  // from a Scratch arena: not freed here
   DevBuf() = default;
   explicit DevBuf(size_t count) { alloc(count); }
+  DevBuf(size_t count, hipStream_t) { alloc_temp(count); }
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
-  DevBuf(DevBuf&& o) noexcept : ptr(o.ptr), n(o.n) { o.ptr = nullptr; o.n = 0; }
+  DevBuf(DevBuf&& o) noexcept : ptr(o.ptr), n(o.n), borrowed(o.borrowed) {
+    o.ptr = nullptr;
+    o.n = 0;
+  }
   DevBuf& operator=(DevBuf&& o) noexcept {
-    if (this != &o) { release(); ptr = o.ptr; n = o.n; o.ptr = nullptr; o.n = 0; }
+    if (this != &o) {
+      release();
+      ptr = o.ptr;
+      n = o.n;
+      borrowed = o.borrowed;
+      o.ptr = nullptr;
+      o.n = 0;
+    }
     return *this;
   }
   ~DevBuf() { release(); }
@@ -76,19 +116,36 @@ struct DevBuf {
     n = count;
     if (count == 0) return;
     hipError_t e = hipMalloc(reinterpret_cast<void**>(&ptr), count * sizeof(T));
-    if (e != hipSuccess) {
-      ptr = nullptr;
-      n = 0;
-      (void)hipGetLastError();
-      fail(PBS_ERR_ALLOC, "device allocation of " + std::to_string(count * sizeof(T)) + " bytes failed");
+    if (e != hipSuccess) failed(count);
+  }
+  void alloc_temp(size_t count) {
+    release();
+    n = count;
+    if (count == 0) return;
+    if (Scratch* sc = Scratch::current()) {
+      if (void* p = sc->take(count * sizeof(T))) {
+        ptr = static_cast<T*>(p);
+        borrowed = true;
+        return;
+      }
     }
+    alloc(count);
   }
   void release() {
-    if (ptr) (void)hipFree(ptr);
+    if (ptr && !borrowed) (void)hipFree(ptr);
     ptr = nullptr;
     n = 0;
+    borrowed = false;
   }
   T* get() const { return ptr; }
+
+ private:
+  void failed(size_t count) {
+    ptr = nullptr;
+    n = 0;
+    (void)hipGetLastError();
+    fail(PBS_ERR_ALLOC, "device allocation of " + std::to_string(count * sizeof(T)) + " bytes failed");
+  }
 };
 
 inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }

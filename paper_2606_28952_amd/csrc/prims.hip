@@ -209,7 +209,7 @@ void exclusive_scan_u32(const uint32_t* in, uint32_t* out, uint64_t n, uint32_t*
     return;
   }
   const uint64_t nb = (n + kScanTile - 1) / kScanTile;
-  DevBuf<uint32_t> partial(nb);
+  DevBuf<uint32_t> partial(nb, s);
   hipLaunchKernelGGL(k_scan_partials, dim3(static_cast<unsigned>(nb)), dim3(kScanBlock), 0, s, in, n, partial.get());
   hipLaunchKernelGGL(k_scan_partials_scan, dim3(1), dim3(kScanBlock), 0, s, partial.get(), nb, total);
   hipLaunchKernelGGL(k_scan_apply, dim3(static_cast<unsigned>(nb)), dim3(kScanBlock), 0, s, in, out, n, partial.get());
@@ -226,7 +226,7 @@ void mark_heads(const uint64_t* keys, uint64_t m, int nw, uint32_t* heads, hipSt
 void radix_sort_keys(uint64_t* keys, uint32_t* vals, uint64_t m, int nw, hipStream_t s) {
   PBS_REQUIRE(m < (1ull << 32), PBS_ERR_RANGE, "sort length exceeds 2^32");
   if (m <= 1) return;
-  DevBuf<unsigned long long> vary(nw);
+  DevBuf<unsigned long long> vary(nw, s);
   PBS_HIP(hipMemsetAsync(vary.get(), 0, nw * sizeof(unsigned long long), s));
   hipLaunchKernelGGL(k_varying_bits, dim3(grid_for(m, 256, 1024)), dim3(256), 0, s, keys, m, nw, vary.get());
   PBS_HIP(hipGetLastError());
@@ -235,9 +235,9 @@ void radix_sort_keys(uint64_t* keys, uint32_t* vals, uint64_t m, int nw, hipStre
   PBS_HIP(hipStreamSynchronize(s));
 
   const uint32_t nblk = static_cast<uint32_t>((m + kSortTile - 1) / kSortTile);
-  DevBuf<uint64_t> ktmp(m * nw);
-  DevBuf<uint32_t> vtmp(m);
-  DevBuf<uint32_t> counts(static_cast<uint64_t>(nblk) * 256);
+  DevBuf<uint64_t> ktmp(m * nw, s);
+  DevBuf<uint32_t> vtmp(m, s);
+  DevBuf<uint32_t> counts(static_cast<uint64_t>(nblk) * 256, s);
   uint64_t* kcur = keys;
   uint32_t* vcur = vals;
   uint64_t* kalt = ktmp.get();
