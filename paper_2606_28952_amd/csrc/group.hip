@@ -144,13 +144,20 @@ __global__ void k_class_meta(uint32_t n_class, const uint32_t* cls_g0, const uin
                              uint32_t* has_quads) {
   for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < n_class; c += gridDim.x * blockDim.x) {
     const uint32_t g0 = cls_g0[c], g1 = cls_g0[c + 1];
-    uint32_t g = g0;
-    int32_t z = -1;
-    if (g < g1 && pg_pc[g] == 0) z = static_cast<int32_t>(g++);
-    const uint32_t a = g;
-    while (g < g1 && pg_pc[g] == 2) ++g;
-    const uint32_t b = g;
-    while (g < g1 && pg_pc[g] == 4) ++g;
+    // popcounts are ascending within a class: first group with popcount >= v
+    auto first_at_least = [&](uint32_t v) {
+      uint32_t lo = g0, hi = g1;
+      while (lo < hi) {
+        const uint32_t mid = (lo + hi) / 2;
+        if (pg_pc[mid] < v)
+          lo = mid + 1;
+        else
+          hi = mid;
+      }
+      return lo;
+    };
+    const uint32_t a = first_at_least(1), b = first_at_least(3), g = first_at_least(5);
+    const int32_t z = a > g0 ? static_cast<int32_t>(g0) : -1;
     zg[c] = z;
     p0[c] = static_cast<int32_t>(a);
     p1[c] = static_cast<int32_t>(b);
@@ -169,11 +176,12 @@ __device__ inline uint32_t small_binom(uint32_t n, uint32_t r) {
 
 // Quad map: the group of each popcount-4 X_beta in its class, at the
 // colexicographic rank of X_beta.
+// One workgroup per class, its threads over the class's quad groups.
 __global__ void k_quad_map(uint32_t n_class, const int32_t* p1, const int32_t* q1, const int32_t* qm,
                            const uint32_t* pg_xb, uint32_t n_quads, int32_t* qmap) {
-  for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < n_class; c += gridDim.x * blockDim.x) {
+  for (uint32_t c = blockIdx.x; c < n_class; c += gridDim.x) {
     if (qm[c] < 0) continue;
-    for (int32_t g = p1[c]; g < q1[c]; ++g) {
+    for (int32_t g = p1[c] + static_cast<int32_t>(threadIdx.x); g < q1[c]; g += static_cast<int32_t>(blockDim.x)) {
       uint32_t xb = pg_xb[g], id = 0;
       for (uint32_t j = 1; j <= 4; ++j) {
         const uint32_t b = __ffs(xb) - 1;
@@ -349,7 +357,7 @@ static void build_sector_tables(pbs_grouped& g, const uint64_t* x, hipStream_t s
   if (qm_entries) {
     hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(qm_entries, 256, 65536)), dim3(256), 0, s, g.qmap.get(), qm_entries,
                        -1);
-    hipLaunchKernelGGL(k_quad_map, dim3(grid_for(g.n_class, 256, 65536)), dim3(256), 0, s, g.n_class,
+    hipLaunchKernelGGL(k_quad_map, dim3(std::min<uint32_t>(g.n_class, 65536u)), dim3(256), 0, s, g.n_class,
                        g.cls_p1.get(), g.cls_q1.get(), g.cls_qm.get(), g.pg_xb.get(), g.n_quads, g.qmap.get());
   }
   g.cls_meta.alloc(g.n_class);
