@@ -409,6 +409,21 @@ __device__ uint32_t append_valid_rows(const SectorArgs& P, uint32_t c0, uint32_t
   return base;
 }
 
+// Copies the db-element source row into LDS, with 16-byte accesses when the
+// row is 16-byte aligned (complex64 pairs; complex128 is 16 bytes anyway).
+template <class T>
+__device__ __forceinline__ void stage_row(T* s_row, const T* rowg, uint32_t db) {
+  if (sizeof(T) == 8 && (reinterpret_cast<uintptr_t>(rowg) & 15u) == 0) {
+    const uint32_t n2 = db / 2;
+    const uint4* src = reinterpret_cast<const uint4*>(rowg);
+    uint4* dst = reinterpret_cast<uint4*>(s_row);  // the staged row is 16-byte aligned
+    for (uint32_t j = threadIdx.x; j < n2; j += kSB) dst[j] = src[j];
+    if ((db & 1u) && threadIdx.x == 0) s_row[db - 1] = rowg[db - 1];
+  } else {
+    for (uint32_t j = threadIdx.x; j < db; j += kSB) s_row[j] = rowg[j];
+  }
+}
+
 // One workgroup: target alpha string ia (one row of the state), beta columns
 // chunk*kSB .. chunk*kSB + kSB - 1, one target per lane.  See the file header
 // for the scheme.  `slot` receives the workgroup's energy partials.
@@ -559,7 +574,7 @@ __device__ __forceinline__ void sector_body(const SectorArgs& P, const T* __rest
     if (stage || fold_a) {
       __syncthreads();
       if (stage)
-        for (uint32_t j = threadIdx.x; j < db; j += kSB) s_row[j] = rowg[j];
+        stage_row<T>(s_row, rowg, db);
       if (fold_a) fold_uniques<REALC>(P, M.ua, ub_a, ta, s_F, s_Fz);
       if (penum) {
         const int32_t* pm = P.pmap + static_cast<uint64_t>(M.pm) * P.n_pairs;
