@@ -227,9 +227,10 @@ __device__ inline uint32_t rank_of(uint32_t s, const SectorArgs& P, const uint16
 // F[u - ua] = sum over the unique's terms of C_t (-1)^popcount(za_t & ta).
 template <bool REALC>
 __device__ inline void fold_uniques(const SectorArgs& P, uint32_t ua, uint32_t ub, uint32_t ta,
-                                    typename Coef<REALC>::V* F, uint32_t* Fz) {
+                                    typename Coef<REALC>::V* F, uint32_t* Fz, uint32_t lane0 = threadIdx.x,
+                                    uint32_t stride = kSB) {
   using C = Coef<REALC>;
-  for (uint32_t u = ua + threadIdx.x; u < ub; u += kSB) {
+  for (uint32_t u = ua + lane0; u < ub; u += stride) {
     typename C::V f = C::zero();
     const uint32_t t1 = P.u_t0[u + 1];
     for (uint32_t t = P.u_t0[u]; t < t1; ++t) C::add_signed(f, C::term(P.pt_c, t), __popc(P.pt_za[t] & ta));
@@ -412,15 +413,15 @@ __device__ uint32_t append_valid_rows(const SectorArgs& P, uint32_t c0, uint32_t
 // Copies the db-element source row into LDS, with 16-byte accesses when the
 // row is 16-byte aligned (complex64 pairs; complex128 is 16 bytes anyway).
 template <class T>
-__device__ __forceinline__ void stage_row(T* s_row, const T* rowg, uint32_t db) {
+__device__ __forceinline__ void stage_row(T* s_row, const T* rowg, uint32_t db, uint32_t lane0, uint32_t stride) {
   if (sizeof(T) == 8 && (reinterpret_cast<uintptr_t>(rowg) & 15u) == 0) {
     const uint32_t n2 = db / 2;
     const uint4* src = reinterpret_cast<const uint4*>(rowg);
     uint4* dst = reinterpret_cast<uint4*>(s_row);  // the staged row is 16-byte aligned
-    for (uint32_t j = threadIdx.x; j < n2; j += kSB) dst[j] = src[j];
-    if ((db & 1u) && threadIdx.x == 0) s_row[db - 1] = rowg[db - 1];
+    for (uint32_t j = lane0; j < n2; j += stride) dst[j] = src[j];
+    if ((db & 1u) && lane0 == 0) s_row[db - 1] = rowg[db - 1];
   } else {
-    for (uint32_t j = threadIdx.x; j < db; j += kSB) s_row[j] = rowg[j];
+    for (uint32_t j = lane0; j < db; j += stride) s_row[j] = rowg[j];
   }
 }
 
@@ -573,12 +574,18 @@ __device__ __forceinline__ void sector_body(const SectorArgs& P, const T* __rest
     // phase A: X_beta = 0 group and, when enumerated, the pair groups
     if (stage || fold_a) {
       __syncthreads();
-      if (stage)
-        stage_row<T>(s_row, rowg, db);
-      if (fold_a) fold_uniques<REALC>(P, M.ua, ub_a, ta, s_F, s_Fz);
-      if (penum) {
+      // with a row to stage, half of the workgroup stages it while the other
+      // half folds the coefficients and fills the pair map (their global
+      // loads overlap); the split is by wave, so no wave diverges
+      const bool split = stage && (fold_a || penum);
+      const bool stager = !split || threadIdx.x < kSB / 2;
+      const uint32_t lane0 = split ? threadIdx.x % (kSB / 2) : threadIdx.x;
+      const uint32_t stride = split ? kSB / 2 : kSB;
+      if (stage && stager) stage_row<T>(s_row, rowg, db, lane0, stride);
+      if (fold_a && (!split || !stager)) fold_uniques<REALC>(P, M.ua, ub_a, ta, s_F, s_Fz, lane0, stride);
+      if (penum && (!split || !stager)) {
         const int32_t* pm = P.pmap + static_cast<uint64_t>(M.pm) * P.n_pairs;
-        for (uint32_t q = threadIdx.x; q <= P.n_pairs; q += kSB) {
+        for (uint32_t q = lane0; q <= P.n_pairs; q += stride) {
           const int32_t g = q < P.n_pairs ? pm[q] : -1;  // entry n_pairs serves the padding moves
           uint32_t v;
           if (single)  // LDS byte address of the group's folded unique
