@@ -79,6 +79,7 @@ typedef struct pbs_sum pbs_sum;         /* Pauli sum: strings + letter-form coef
 typedef struct pbs_grouped pbs_grouped; /* sum grouped by X-mask, kernel tables */
 typedef struct pbs_space pbs_space;     /* configuration space (full or spin sector) */
 typedef struct pbs_batch pbs_batch;     /* prepared launch of many operator-state products */
+typedef struct pbs_vqe pbs_vqe;         /* Pauli-rotation ansatz with energy and gradient */
 
 /* Message describing the calling thread's last failure ("" after success). */
 const char* pbs_last_error(void);
@@ -266,6 +267,39 @@ pbs_status pbs_krylov_workspace_bytes(const pbs_space* sp, pbs_dtype dt, uint32_
  * Synchronizes the stream (the tridiagonal matrix is read back). */
 pbs_status pbs_krylov_step(const pbs_grouped* h, const pbs_space* sp, pbs_dtype dt, void* psi, double dt_step,
                            uint32_t m, void* work, uint64_t work_bytes, double* info, void* stream);
+
+/* ------------------------------------------------------------------ variational layer */
+
+/* Ansatz psi(theta) = R_{n-1} ... R_0 |ref>, R_k = exp(i theta_k P_k) =
+ * cos(theta_k) + i sin(theta_k) P_k, over the full 2^(2 n_orb) space, with
+ * its energy <psi|H|psi> (Section 2.1, Eq. vqe_energy).  H must conserve
+ * N_alpha and N_beta (a JW Hamiltonian of spin-orbital integrals): the
+ * product H|psi> runs through the batched sector kernel over all
+ * (N_alpha, N_beta) blocks of the full space.
+ *  h      grouped operator on 2 n_orb qubits (1 <= n_orb <= 14), with sector
+ *         tables; it must outlive the handle.
+ *  x, z   host, n_rot words: the Hermitian letter-form strings P_k (phase 0).
+ *  ref    basis index of the reference state (bit k = qubit k).
+ *  dt     storage of the state vectors; energies, overlaps and gradients are
+ *         float64.
+ * Allocates four full-space vectors and the sector tables; synchronizes the
+ * stream. */
+pbs_status pbs_vqe_create(const pbs_grouped* h, uint32_t n_orb, uint32_t n_rot, const uint64_t* x, const uint64_t* z,
+                          uint64_t ref, pbs_dtype dt, void* stream, pbs_vqe** out);
+
+/* energy = <psi(theta)|H|psi(theta)>; when grad is not NULL, also
+ * grad[k] = dE/dtheta_k = -2 Im <lambda_k|P_k|psi_k> by the adjoint method
+ * (psi_k after rotation k, lambda_k = R_{k+1}^dag ... R_{n-1}^dag H psi).
+ * theta, energy, grad: host.  Synchronizes the stream.  Calls on one handle
+ * must not overlap. */
+pbs_status pbs_vqe_energy_grad(pbs_vqe* v, const double* theta, double* energy, double* grad, void* stream);
+
+/* Writes psi(theta) of the last pbs_vqe_energy_grad call (2^(2 n_orb)
+ * values of the handle's dtype, full-space order) to the device buffer
+ * psi_out.  PBS_ERR_ARG before the first evaluation. */
+pbs_status pbs_vqe_state(const pbs_vqe* v, void* psi_out, void* stream);
+
+void pbs_vqe_destroy(pbs_vqe* v);
 
 #ifdef __cplusplus
 }

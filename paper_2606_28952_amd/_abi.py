@@ -49,6 +49,10 @@ SIGNATURES = {
     "pbs_batch_destroy": (None, [_vp]),
     "pbs_krylov_workspace_bytes": (c_int32, [_vp, c_int32, c_uint32, POINTER(c_uint64)]),
     "pbs_krylov_step": (c_int32, [_vp, _vp, c_int32, _vp, c_double, c_uint32, _vp, c_uint64, _vp, _vp]),
+    "pbs_vqe_create": (c_int32, [_vp, c_uint32, c_uint32, _vp, _vp, c_uint64, c_int32, _vp, POINTER(_vp)]),
+    "pbs_vqe_energy_grad": (c_int32, [_vp, _vp, _vp, _vp, _vp]),
+    "pbs_vqe_state": (c_int32, [_vp, _vp, _vp]),
+    "pbs_vqe_destroy": (None, [_vp]),
 }
 
 _LIB = None

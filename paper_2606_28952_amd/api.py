@@ -17,7 +17,7 @@ from ._abi import PBS_C64, PBS_C128, call
 
 __all__ = [
     "PauliSum", "Grouped", "Space", "pauli_mul", "jw_transform", "apply_pauli_sum", "expval",
-    "words_for", "PBS_C64", "PBS_C128", "KrylovPropagator", "Batch",
+    "words_for", "PBS_C64", "PBS_C128", "KrylovPropagator", "Batch", "VQE",
 ]
 
 
@@ -311,4 +311,48 @@ class Batch:
         h = getattr(self, "_h", None)
         if h is not None and h.value and _abi is not None and _abi._LIB is not None:
             _abi._LIB.pbs_batch_destroy(h)
+            self._h = None
+
+
+class VQE:
+    """Pauli-rotation ansatz R_{n-1} ... R_0 |ref>, R_k = exp(i theta_k P_k),
+    on the full 2^(2 n_orb) space of a number-conserving grouped operator;
+    energy and adjoint gradient on the device (float64)."""
+
+    def __init__(self, grouped, n_orb, x, z, ref, dtype=torch.complex128):
+        x = np.ascontiguousarray(np.asarray(x, dtype=np.uint64).reshape(-1))
+        z = np.ascontiguousarray(np.asarray(z, dtype=np.uint64).reshape(-1))
+        if x.shape != z.shape:
+            raise ValueError("x and z must have one word per rotation")
+        self.n_rot = int(x.shape[0])
+        self.n_orb = int(n_orb)
+        self.dtype = dtype
+        self._grouped = grouped  # keeps the operator alive
+        code = PBS_C128 if dtype == torch.complex128 else PBS_C64
+        out = c_void_p()
+        call("pbs_vqe_create", grouped._h, self.n_orb, self.n_rot, _ptr(x), _ptr(z), int(ref), code, _stream(),
+             byref(out))
+        self._h = out
+
+    def energy(self, theta):
+        return self.energy_grad(theta, grad=False)[0]
+
+    def energy_grad(self, theta, grad=True):
+        th = np.ascontiguousarray(np.asarray(theta, dtype=np.float64).reshape(-1))
+        if th.shape[0] != self.n_rot:
+            raise ValueError(f"expected {self.n_rot} parameters")
+        e = ctypes.c_double()
+        g = np.zeros(self.n_rot, np.float64) if grad else None
+        call("pbs_vqe_energy_grad", self._h, _ptr(th), byref(e), _ptr(g), _stream())
+        return e.value, g
+
+    def state(self):
+        psi = torch.empty(1 << (2 * self.n_orb), dtype=self.dtype, device="cuda")
+        call("pbs_vqe_state", self._h, _ptr(psi), _stream())
+        return psi
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _abi is not None and _abi._LIB is not None:
+            _abi._LIB.pbs_vqe_destroy(h)
             self._h = None

@@ -1,0 +1,355 @@
+// Variational layer on top of the operator-state product: an ansatz of
+// Pauli rotations exp(i theta_k P_k) acting on a reference basis state in the
+// full 2^n space, its energy <psi(theta)|H|psi(theta)> (Section 2.1, Eq.
+// vqe_energy) and the gradient of that energy by the adjoint method.
+//
+// A number- and S_z-conserving H acts on each (N_alpha, N_beta) sector of the
+// full space separately, so the full-space product H|psi> is computed by
+// permuting psi into sector blocks (each block alpha-major, the layout of a
+// sector space), running the batched sector kernel over all blocks in one
+// launch, and permuting back.  Rotations and overlaps are bandwidth-bound
+// passes over the full-space vectors.
+#include <vector>
+
+#include "sector.h"
+
+namespace pbs {
+namespace {
+
+// XZ form of a Hermitian letter-form string: P|s> = omega (-1)^popcount(z & s) |s ^ x>
+// with omega = i^popcount(x & z) (Section 2.3).
+struct Rot {
+  uint64_t x, z;
+  uint32_t omega;  // power of i, 0..3
+};
+
+// i^k * (r, m)
+__device__ inline void times_i_pow(uint32_t k, double& r, double& m) {
+  const double a = r, b = m;
+  switch (k & 3u) {
+    case 0: break;
+    case 1: r = -b; m = a; break;
+    case 2: r = -a; m = -b; break;
+    default: r = b; m = -a; break;
+  }
+}
+
+// psi <- (cos theta + i sin theta P) psi over pairs (t, t ^ x), t with the
+// highest bit of x clear; x = 0 is a diagonal phase.
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_rotate(T* __restrict__ psi, uint64_t dim, uint64_t x, uint64_t z,
+                                                    uint32_t omega, double c, double s) {
+  if (x == 0) {
+    for (uint64_t t = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; t < dim;
+         t += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+      double pr, pi;
+      Amp<T>::load(psi, t, pr, pi);
+      double fr = 0.0, fi = signed_by(s, __popcll(z & t));  // i s (-1)^(z.t) omega
+      times_i_pow(omega, fr, fi);
+      const double gr = c + fr, gi = fi;
+      Amp<T>::store(psi, t, pr * gr - pi * gi, pr * gi + pi * gr);
+    }
+    return;
+  }
+  const uint32_t h = 63u - static_cast<uint32_t>(__clzll(static_cast<long long>(x)));
+  const uint64_t low = (1ull << h) - 1ull;
+  for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < dim / 2;
+       i += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+    const uint64_t t = ((i & ~low) << 1) | (i & low);  // bit h clear
+    const uint64_t u = t ^ x;
+    double ar, ai, br, bi;
+    Amp<T>::load(psi, t, ar, ai);
+    Amp<T>::load(psi, u, br, bi);
+    // (P psi)[t] = omega (-1)^(z.u) psi[u], (P psi)[u] = omega (-1)^(z.t) psi[t]
+    double pr = signed_by(br, __popcll(z & u)), pi = signed_by(bi, __popcll(z & u));
+    double qr = signed_by(ar, __popcll(z & t)), qi = signed_by(ai, __popcll(z & t));
+    times_i_pow(omega + 1u, pr, pi);  // i * omega
+    times_i_pow(omega + 1u, qr, qi);
+    Amp<T>::store(psi, t, c * ar + s * pr, c * ai + s * pi);
+    Amp<T>::store(psi, u, c * br + s * qr, c * bi + s * qi);
+  }
+}
+
+// Workgroup partials of <lam|P|psi> = sum_t conj(lam[t]) omega (-1)^(z.(t^x)) psi[t ^ x].
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_overlap(const T* __restrict__ lam, const T* __restrict__ psi,
+                                                     uint64_t dim, uint64_t x, uint64_t z, uint32_t omega,
+                                                     double* __restrict__ partial) {
+  double sr = 0.0, si = 0.0;
+  for (uint64_t t = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; t < dim;
+       t += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+    const uint64_t u = t ^ x;
+    double lr, li, pr, pi;
+    Amp<T>::load(lam, t, lr, li);
+    Amp<T>::load(psi, u, pr, pi);
+    const uint32_t par = __popcll(z & u);
+    pr = signed_by(pr, par);
+    pi = signed_by(pi, par);
+    times_i_pow(omega, pr, pi);
+    sr = fma(lr, pr, fma(li, pi, sr));
+    si = fma(lr, pi, fma(-li, pr, si));
+  }
+  block_reduce3_store<kBlock>(sr, si, 0.0, partial + 3ull * blockIdx.x);
+}
+
+// out[k] = (sum of the partials of overlap k, real and imaginary parts), fixed order.
+__global__ __launch_bounds__(kBlock) void k_sum_overlaps(const double* partial, uint32_t nparts, double* out) {
+  const double* p = partial + 3ull * nparts * blockIdx.x;
+  double a = 0.0, b = 0.0;
+  for (uint32_t i = threadIdx.x; i < nparts; i += kBlock) {
+    a += p[3ull * i];
+    b += p[3ull * i + 1];
+  }
+  double r[3];
+  block_reduce3_store<kBlock>(a, b, 0.0, r);
+  if (threadIdx.x == 0) {
+    out[2 * blockIdx.x] = r[0];
+    out[2 * blockIdx.x + 1] = r[1];
+  }
+}
+
+__global__ void k_basis_state(double2* psi64, float2* psi32, uint64_t dim, uint64_t ref) {
+  for (uint64_t t = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; t < dim;
+       t += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+    const double v = t == ref ? 1.0 : 0.0;
+    if (psi64) psi64[t] = make_double2(v, 0.0);
+    if (psi32) psi32[t] = make_float2(static_cast<float>(v), 0.0f);
+  }
+}
+
+// Colexicographic rank of a spin string from T[c][k][byte] tables.
+__device__ inline uint32_t colex_rank(uint32_t s, uint32_t n_orb, uint32_t n_chunks, const uint32_t* tab) {
+  uint32_t r = 0, below = 0;
+  for (uint32_t c = 0; c < n_chunks; ++c) {
+    const uint32_t byte = (s >> (8 * c)) & 255u;
+    r += tab[(c * (n_orb + 1) + below) * 256 + byte];
+    below += __popc(byte);
+  }
+  return r;
+}
+
+// Full-space index s = alpha | beta << n_orb  <->  sector-block index
+// off[N_alpha][N_beta] + rank(alpha) C(n_orb, N_beta) + rank(beta).
+template <class T, bool TO_BLOCKS>
+__global__ __launch_bounds__(kBlock) void k_fock_permute(const T* __restrict__ in, T* __restrict__ out, uint64_t dim,
+                                                          uint32_t n_orb, uint32_t n_chunks,
+                                                          const uint32_t* __restrict__ tab,
+                                                          const uint64_t* __restrict__ off,
+                                                          const uint32_t* __restrict__ binom_n) {
+  const uint32_t mask = (1u << n_orb) - 1u;
+  for (uint64_t s = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; s < dim;
+       s += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+    const uint32_t a = static_cast<uint32_t>(s) & mask, b = static_cast<uint32_t>(s >> n_orb);
+    const uint32_t pa = __popc(a), pb = __popc(b);
+    const uint64_t j = off[pa * (n_orb + 1) + pb] +
+                       static_cast<uint64_t>(colex_rank(a, n_orb, n_chunks, tab)) * binom_n[pb] +
+                       colex_rank(b, n_orb, n_chunks, tab);
+    if (TO_BLOCKS)
+      out[j] = in[s];
+    else
+      out[s] = in[j];
+  }
+}
+
+Rot rot_of(uint64_t x, uint64_t z) { return Rot{x, z, static_cast<uint32_t>(__builtin_popcountll(x & z) & 3)}; }
+
+}  // namespace
+}  // namespace pbs
+
+using namespace pbs;
+
+struct pbs_vqe {
+  uint32_t n_orb = 0, n_qubits = 0, n_rot = 0;
+  pbs_dtype dt = PBS_C128;
+  uint64_t dim = 0, ref = 0;
+  std::vector<Rot> rots;
+  std::vector<pbs_space*> spaces;  // one per nonempty (N_alpha, N_beta) block, alpha-major order
+  pbs_batch* batch = nullptr;
+  uint32_t n_jobs = 0;
+  DevBuf<uint32_t> rank_tab, binom_n;
+  DevBuf<uint64_t> off;
+  DevBuf<char> psi, lam, blk_in, blk_out;
+  DevBuf<double> energies, partial, overlaps;
+  uint32_t nparts = 0;
+  bool evaluated = false;  // blk_in holds psi(theta) of the last evaluation
+  ~pbs_vqe() {
+    if (batch) pbs_batch_destroy(batch);
+    for (pbs_space* sp : spaces) pbs_space_destroy(sp);
+  }
+};
+
+namespace pbs {
+namespace {
+constexpr unsigned kVqeGrid = 4096;
+
+template <class T>
+void rotate_all(pbs_vqe& v, T* psi, const double* theta, bool inverse, uint32_t k, hipStream_t s) {
+  const Rot& r = v.rots[k];
+  const double th = inverse ? -theta[k] : theta[k];
+  hipLaunchKernelGGL((k_rotate<T>), dim3(grid_for(v.dim, kBlock, kVqeGrid)), dim3(kBlock), 0, s, psi, v.dim, r.x,
+                     r.z, r.omega, cos(th), sin(th));
+}
+
+template <class T>
+void energy_grad(pbs_vqe& v, const double* theta, double* energy, double* grad, hipStream_t s) {
+  T* psi = reinterpret_cast<T*>(v.psi.get());
+  T* lam = reinterpret_cast<T*>(v.lam.get());
+  T* bin = reinterpret_cast<T*>(v.blk_in.get());
+  T* bout = reinterpret_cast<T*>(v.blk_out.get());
+  const dim3 grid(grid_for(v.dim, kBlock, kVqeGrid));
+  hipLaunchKernelGGL(k_basis_state, grid, dim3(kBlock), 0, s, sizeof(T) == 16 ? reinterpret_cast<double2*>(psi) : nullptr,
+                     sizeof(T) == 8 ? reinterpret_cast<float2*>(psi) : nullptr, v.dim, v.ref);
+  for (uint32_t k = 0; k < v.n_rot; ++k) rotate_all<T>(v, psi, theta, false, k, s);
+  // H psi through the sector blocks, with each block's energy
+  const pbs_space& sp0 = *v.spaces[0];
+  hipLaunchKernelGGL((k_fock_permute<T, true>), grid, dim3(kBlock), 0, s, psi, bin, v.dim, v.n_orb, sp0.n_chunks,
+                     v.rank_tab.get(), v.off.get(), v.binom_n.get());
+  PBS_HIP(hipGetLastError());
+  const pbs_status st = pbs_batch_run(v.batch, v.energies.get(), s);
+  PBS_REQUIRE(st == PBS_OK, st, std::string("batched sector apply failed: ") + pbs_last_error());
+  std::vector<double> e(3ull * v.n_jobs);
+  PBS_HIP(hipMemcpyAsync(e.data(), v.energies.get(), e.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  if (grad && v.n_rot > 0) {
+    hipLaunchKernelGGL((k_fock_permute<T, false>), grid, dim3(kBlock), 0, s, bout, lam, v.dim, v.n_orb,
+                       sp0.n_chunks, v.rank_tab.get(), v.off.get(), v.binom_n.get());
+    // adjoint sweep: g_k = -2 Im <lam_k|P_k|psi_k>, then undo rotation k on both vectors
+    for (uint32_t k = v.n_rot; k-- > 0;) {
+      const Rot& r = v.rots[k];
+      hipLaunchKernelGGL((k_overlap<T>), dim3(v.nparts), dim3(kBlock), 0, s, lam, psi, v.dim, r.x, r.z, r.omega,
+                         v.partial.get() + 3ull * v.nparts * k);
+      rotate_all<T>(v, psi, theta, true, k, s);
+      rotate_all<T>(v, lam, theta, true, k, s);
+    }
+    hipLaunchKernelGGL(k_sum_overlaps, dim3(v.n_rot), dim3(kBlock), 0, s, v.partial.get(), v.nparts,
+                       v.overlaps.get());
+    PBS_HIP(hipGetLastError());
+    std::vector<double> ov(2ull * v.n_rot);
+    PBS_HIP(hipMemcpyAsync(ov.data(), v.overlaps.get(), ov.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    PBS_HIP(hipStreamSynchronize(s));
+    for (uint32_t k = 0; k < v.n_rot; ++k) grad[k] = -2.0 * ov[2 * k + 1];
+  }
+  PBS_HIP(hipGetLastError());
+  PBS_HIP(hipStreamSynchronize(s));
+  double acc = 0.0;
+  for (uint32_t j = 0; j < v.n_jobs; ++j) acc += e[3 * j];
+  *energy = acc;
+  v.evaluated = true;
+}
+
+template <class T>
+void state_out(const pbs_vqe& v, T* psi_out, hipStream_t s) {
+  const pbs_space& sp0 = *v.spaces[0];
+  hipLaunchKernelGGL((k_fock_permute<T, false>), dim3(grid_for(v.dim, kBlock, kVqeGrid)), dim3(kBlock), 0, s,
+                     reinterpret_cast<const T*>(v.blk_in.get()), psi_out, v.dim, v.n_orb, sp0.n_chunks,
+                     v.rank_tab.get(), v.off.get(), v.binom_n.get());
+  PBS_HIP(hipGetLastError());
+}
+}  // namespace
+}  // namespace pbs
+
+extern "C" {
+
+pbs_status pbs_vqe_create(const pbs_grouped* h, uint32_t n_orb, uint32_t n_rot, const uint64_t* x, const uint64_t* z,
+                          uint64_t ref, pbs_dtype dt, void* stream, pbs_vqe** out) {
+  return guarded([&] {
+    PBS_REQUIRE(out != nullptr, PBS_ERR_ARG, "null output handle");
+    *out = nullptr;
+    PBS_REQUIRE(h != nullptr, PBS_ERR_ARG, "null pbs_grouped");
+    PBS_REQUIRE(dt == PBS_C128 || dt == PBS_C64, PBS_ERR_ARG, "unknown dtype");
+    PBS_REQUIRE(n_orb >= 1 && n_orb <= 14, PBS_ERR_RANGE, "the full space needs 1 <= n_orb <= 14");
+    PBS_REQUIRE(h->n_qubits == 2 * n_orb && h->has_sector && h->half == n_orb, PBS_ERR_ARG,
+                "operator must act on 2 n_orb qubits with sector tables");
+    PBS_REQUIRE(n_rot == 0 || (x != nullptr && z != nullptr), PBS_ERR_ARG, "null rotation strings");
+    const uint64_t dim = 1ull << (2 * n_orb);
+    PBS_REQUIRE(ref < dim, PBS_ERR_ARG, "reference state outside the space");
+    for (uint32_t k = 0; k < n_rot; ++k)
+      PBS_REQUIRE(((x[k] | z[k]) >> (2 * n_orb)) == 0, PBS_ERR_ARG,
+                  "rotation " + std::to_string(k) + " acts beyond the qubits");
+    hipStream_t s = as_stream(stream);
+    auto* v = new pbs_vqe();
+    try {
+      v->n_orb = n_orb;
+      v->n_qubits = 2 * n_orb;
+      v->n_rot = n_rot;
+      v->dt = dt;
+      v->dim = dim;
+      v->ref = ref;
+      for (uint32_t k = 0; k < n_rot; ++k) v->rots.push_back(rot_of(x[k], z[k]));
+      const size_t esz = dt == PBS_C128 ? 16 : 8;
+      v->psi.alloc(dim * esz);
+      v->lam.alloc(dim * esz);
+      v->blk_in.alloc(dim * esz);
+      v->blk_out.alloc(dim * esz);
+      // sector blocks, alpha-major over (N_alpha, N_beta)
+      std::vector<uint64_t> off((n_orb + 1) * (n_orb + 1), 0);
+      std::vector<uint32_t> bn(n_orb + 1);
+      for (uint32_t k = 0; k <= n_orb; ++k) bn[k] = static_cast<uint32_t>(host_binom(n_orb, k));
+      std::vector<const pbs_grouped*> hs;
+      std::vector<const pbs_space*> sps;
+      std::vector<const void*> ins;
+      std::vector<void*> outs;
+      uint64_t acc = 0;
+      for (uint32_t na = 0; na <= n_orb; ++na) {
+        for (uint32_t nb = 0; nb <= n_orb; ++nb) {
+          off[na * (n_orb + 1) + nb] = acc;
+          pbs_space* sp = nullptr;
+          const pbs_status st = pbs_space_sector(n_orb, na, nb, stream, &sp);
+          PBS_REQUIRE(st == PBS_OK, st, std::string("sector space: ") + pbs_last_error());
+          v->spaces.push_back(sp);
+          hs.push_back(h);
+          sps.push_back(sp);
+          ins.push_back(v->blk_in.get() + acc * esz);
+          outs.push_back(v->blk_out.get() + acc * esz);
+          acc += sp->dim;
+        }
+      }
+      PBS_REQUIRE(acc == dim, PBS_ERR_DEVICE, "sector blocks do not tile the full space");
+      v->n_jobs = static_cast<uint32_t>(sps.size());
+      const pbs_status st = pbs_batch_create(v->n_jobs, hs.data(), sps.data(), dt, ins.data(), outs.data(), &v->batch);
+      PBS_REQUIRE(st == PBS_OK, st, std::string("batch: ") + pbs_last_error());
+      const pbs_space& sp0 = *v->spaces[0];
+      v->rank_tab.alloc(sp0.rank_tab.n);
+      PBS_HIP(hipMemcpyAsync(v->rank_tab.get(), sp0.rank_tab.get(), sp0.rank_tab.n * 4, hipMemcpyDeviceToDevice, s));
+      v->off.alloc(off.size());
+      v->binom_n.alloc(bn.size());
+      PBS_HIP(hipMemcpyAsync(v->off.get(), off.data(), off.size() * 8, hipMemcpyHostToDevice, s));
+      PBS_HIP(hipMemcpyAsync(v->binom_n.get(), bn.data(), bn.size() * 4, hipMemcpyHostToDevice, s));
+      v->energies.alloc(3ull * v->n_jobs);
+      v->nparts = grid_for(dim, kBlock, 1024);
+      v->partial.alloc(3ull * v->nparts * (n_rot ? n_rot : 1));
+      v->overlaps.alloc(2ull * (n_rot ? n_rot : 1));
+      PBS_HIP(hipStreamSynchronize(s));
+    } catch (...) {
+      delete v;
+      throw;
+    }
+    *out = v;
+  });
+}
+
+pbs_status pbs_vqe_energy_grad(pbs_vqe* v, const double* theta, double* energy, double* grad, void* stream) {
+  return guarded([&] {
+    PBS_REQUIRE(v != nullptr && energy != nullptr, PBS_ERR_ARG, "null argument");
+    PBS_REQUIRE(v->n_rot == 0 || theta != nullptr, PBS_ERR_ARG, "null parameters");
+    hipStream_t s = as_stream(stream);
+    if (v->dt == PBS_C128)
+      energy_grad<double2>(*v, theta, energy, grad, s);
+    else
+      energy_grad<float2>(*v, theta, energy, grad, s);
+  });
+}
+
+pbs_status pbs_vqe_state(const pbs_vqe* v, void* psi_out, void* stream) {
+  return guarded([&] {
+    PBS_REQUIRE(v != nullptr && psi_out != nullptr, PBS_ERR_ARG, "null argument");
+    PBS_REQUIRE(v->evaluated, PBS_ERR_ARG, "no state before the first evaluation");
+    if (v->dt == PBS_C128)
+      state_out(*v, static_cast<double2*>(psi_out), as_stream(stream));
+    else
+      state_out(*v, static_cast<float2*>(psi_out), as_stream(stream));
+  });
+}
+
+void pbs_vqe_destroy(pbs_vqe* v) { delete v; }
+
+}  // extern "C"

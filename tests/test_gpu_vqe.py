@@ -1,0 +1,91 @@
+"""GPU parity of the Pauli-rotation ansatz (pbs_vqe_*): state, energy and
+adjoint gradient against the oracle's dense rotations, scatter energy and
+parameter-shift gradient."""
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import apply as oapply
+from oracle import jw as ojw
+from oracle import pauli as opauli
+from oracle import vqe as ovqe
+
+pytestmark = pytest.mark.gpu
+
+
+def _api():
+    from paper_2606_28952_amd import api
+
+    return api
+
+
+def _problem(dev, n_orb, n_rot, seed):
+    api = _api()
+    h1, h2 = synth.molecular_spin_integrals(n_orb, seed=seed)
+    G = api.jw_transform(torch.from_numpy(h1).to(dev), torch.from_numpy(h2).to(dev)).group()
+    op = ojw.jw_sum(h1, h2)
+    n = 2 * n_orb
+    rng = np.random.default_rng(seed)
+    rots = [rng.integers(0, 4, n).astype(np.uint8) for _ in range(n_rot)]
+    if n_rot >= 3:
+        rots[1] = np.zeros(n, np.uint8)  # identity: a global phase
+        rots[2] = np.where(rng.random(n) < 0.5, 3, 0).astype(np.uint8)  # diagonal
+    xz = [opauli.letters_to_xz(r) for r in rots]
+    x = np.array([int(np.asarray(a).reshape(-1)[0]) for a, _ in xz], np.uint64)
+    z = np.array([int(np.asarray(b).reshape(-1)[0]) for _, b in xz], np.uint64)
+    na = n_orb // 2
+    nb = (n_orb + 1) // 2
+    ref = ((1 << na) - 1) | (((1 << nb) - 1) << n_orb)
+    theta = rng.normal(size=n_rot) * 0.5
+    return G, op, rots, x, z, ref, theta
+
+
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+@pytest.mark.parametrize("n_orb,n_rot", [(1, 4), (2, 9), (3, 12), (5, 10)])
+def test_vqe_matches_oracle(dev, dtype, n_orb, n_rot):
+    api = _api()
+    G, op, rots, x, z, ref, theta = _problem(dev, n_orb, n_rot, seed=40 + n_orb)
+    v = api.VQE(G, n_orb, x, z, ref, dtype=dtype)
+    e, g = v.energy_grad(theta)
+    psi = v.state().cpu().numpy()
+    want_psi = ovqe.ansatz_state(rots, theta, ref, 2 * n_orb)
+    want_e = ovqe.energy(op, rots, theta, ref)
+    want_g = ovqe.gradient(op, rots, theta, ref)
+    scale = max(1.0, float(np.abs(op.coeff).sum()))
+    if dtype == torch.complex128:
+        tol_psi, tol_e, tol_g = 1e-12, 1e-12 * scale, 1e-11 * scale
+    else:
+        tol_psi, tol_e, tol_g = 2e-6, 2e-6 * scale, 4e-6 * scale
+    assert np.abs(psi - want_psi).max() < tol_psi
+    assert abs(e - want_e) < tol_e
+    assert np.abs(g - want_g).max() < tol_g
+    # the identity rotation only changes a global phase
+    assert abs(g[1]) < tol_g
+    e2, _ = v.energy_grad(theta, grad=False)
+    assert e2 == e
+
+
+def test_vqe_without_rotations_is_reference_energy(dev):
+    api = _api()
+    G, op, _, _, _, ref, _ = _problem(dev, 3, 0, seed=7)
+    v = api.VQE(G, 3, np.zeros(0, np.uint64), np.zeros(0, np.uint64), ref)
+    e, g = v.energy_grad(np.zeros(0))
+    H = oapply.dense_matrix(op)
+    assert abs(e - H[ref, ref].real) < 1e-12 * max(1.0, abs(H[ref, ref]))
+    assert g.shape == (0,)
+
+
+def test_vqe_argument_errors(dev):
+    api = _api()
+    G, _, _, x, z, ref, _ = _problem(dev, 2, 3, seed=1)
+    with pytest.raises(Exception, match="reference"):
+        api.VQE(G, 2, x, z, 1 << 4)
+    with pytest.raises(Exception, match="beyond"):
+        api.VQE(G, 2, np.array([1 << 5], np.uint64), np.array([0], np.uint64), ref)
+    with pytest.raises(Exception, match="2 n_orb"):
+        api.VQE(G, 3, x, z, ref)
+    v = api.VQE(G, 2, x, z, ref)
+    with pytest.raises(ValueError):
+        v.energy_grad(np.zeros(5))
