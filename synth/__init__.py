@@ -32,6 +32,9 @@ __all__ = [
     "random_state",
     "random_pauli_strings",
     "neel_occupations",
+    "pes_integrals",
+    "excitation_generators",
+    "mlp_init",
 ]
 
 
@@ -195,3 +198,69 @@ def random_symplectic(n_strings, n_qubits, seed, pool=None):
         x, z = x[pick], z[pick]
     phase = rng.integers(0, 4, size=n_strings, dtype=np.uint8)
     return np.ascontiguousarray(x), np.ascontiguousarray(z), phase
+
+
+def pes_integrals(n_orb, r, seed=5001):
+    """Spatial integrals along a synthetic potential-energy scan:
+    h(R) = h0 + R h1 + R^2 h2 and g(R) = g0 + R g1 + R^2 g2, where (h_k, g_k)
+    is ``molecular_integrals(n_orb, seed + k)``.  Returns spin-orbital
+    (h1, h2) arrays of ``spin_orbital_integrals``."""
+    h = np.zeros((n_orb, n_orb))
+    g = np.zeros((n_orb,) * 4)
+    for k in range(3):
+        hk, gk = molecular_integrals(n_orb, seed + k)
+        h = h + r ** k * hk
+        g = g + r ** k * gk
+    return spin_orbital_integrals(h, g)
+
+
+def excitation_generators(n_orb, n_alpha, n_beta, count, seed=7):
+    """Letter strings (uint8 rows over 2 n_orb qubits, 0=I 1=X 2=Y 3=Z) that
+    generate the rotations of a synthetic excitation ansatz on the reference
+    with the lowest n_alpha alpha and n_beta beta spin-orbitals occupied.
+
+    Every spin-conserving single (i -> a) and double (i j -> a b) excitation
+    from occupied to empty spin-orbitals gives one string: Y on its lowest
+    qubit, X on its other qubits, and Z on the qubits strictly inside each
+    consecutive pair of its sorted qubits (first-second, third-fourth).  The
+    list holds all singles, then the doubles in a seeded random order, cut
+    to ``count`` strings."""
+    n = 2 * n_orb
+    occ = [p for p in range(n_alpha)] + [n_orb + p for p in range(n_beta)]
+    vir = [p for p in range(n_alpha, n_orb)] + [n_orb + p for p in range(n_beta, n_orb)]
+    spin = lambda q: q // n_orb
+
+    def string(qubits):
+        qs = sorted(qubits)
+        s = np.zeros(n, np.uint8)
+        for a, b in zip(qs[0::2], qs[1::2]):
+            s[a + 1:b] = 3
+        s[qs] = 1
+        s[qs[0]] = 2
+        return s
+
+    singles = [string((i, a)) for i in occ for a in vir if spin(i) == spin(a)]
+    doubles = []
+    for ii, i in enumerate(occ):
+        for j in occ[ii + 1:]:
+            for aa, a in enumerate(vir):
+                for b in vir[aa + 1:]:
+                    if sorted((spin(i), spin(j))) == sorted((spin(a), spin(b))):
+                        doubles.append(string((i, j, a, b)))
+    rng = np.random.default_rng(seed)
+    doubles = [doubles[k] for k in rng.permutation(len(doubles))]
+    rows = (singles + doubles)[:count]
+    return np.array(rows, dtype=np.uint8).reshape(len(rows), n)
+
+
+def mlp_init(hidden, n_out, seed):
+    """Initial parameters of the warm-start network, float32, packed as
+    [W1 (H), b1 (H), W2 (H*H), b2 (H), W3 (n_out*H), b3 (n_out)]:
+    W1 ~ U(-4, 4), b1 ~ U(-2, 2), W2 ~ U(+-sqrt(3/H)), b2 = 0,
+    W3 ~ U(+-0.1 sqrt(3/H)), b3 = 0."""
+    rng = np.random.default_rng(seed)
+    H, O = hidden, n_out
+    a = np.sqrt(3.0 / H)
+    parts = [rng.uniform(-4, 4, H), rng.uniform(-2, 2, H), rng.uniform(-a, a, H * H), np.zeros(H),
+             rng.uniform(-0.1 * a, 0.1 * a, O * H), np.zeros(O)]
+    return np.concatenate(parts).astype(np.float32)
