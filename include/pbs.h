@@ -80,6 +80,7 @@ typedef struct pbs_grouped pbs_grouped; /* sum grouped by X-mask, kernel tables 
 typedef struct pbs_space pbs_space;     /* configuration space (full or spin sector) */
 typedef struct pbs_batch pbs_batch;     /* prepared launch of many operator-state products */
 typedef struct pbs_vqe pbs_vqe;         /* Pauli-rotation ansatz with energy and gradient */
+typedef struct pbs_mlp pbs_mlp;         /* warm-start network: parameters, optimizer state, buffers */
 
 /* Message describing the calling thread's last failure ("" after success). */
 const char* pbs_last_error(void);
@@ -299,7 +300,83 @@ pbs_status pbs_vqe_energy_grad(pbs_vqe* v, const double* theta, double* energy, 
  * psi_out.  PBS_ERR_ARG before the first evaluation. */
 pbs_status pbs_vqe_state(const pbs_vqe* v, void* psi_out, void* stream);
 
+/* Minimises the energy over theta (host, n_rot doubles, in/out: start point
+ * in, minimiser out) with pbs_lbfgs_minimize, each evaluation being one
+ * pbs_vqe_energy_grad call on the stream; the decrease test tolerates
+ * 1e-13 (complex128) or 1e-6 (complex64) relative noise in E.  Outputs as in pbs_lbfgs_minimize
+ * (energy = final E).  Synchronizes. */
+pbs_status pbs_vqe_minimize(pbs_vqe* v, double* theta, uint32_t max_iter, double g_tol, double f_tol, void* stream,
+                            double* energy, uint32_t* iters, uint32_t* evals, int32_t* reason);
+
 void pbs_vqe_destroy(pbs_vqe* v);
+
+/* ------------------------------------------------------------------ optimizer */
+
+/* Objective for pbs_lbfgs_minimize: writes f(x) and its gradient g (n
+ * doubles, host) and returns 0, or nonzero to abort the minimisation. */
+typedef int32_t (*pbs_objective)(void* user, uint32_t n, const double* x, double* f, double* g);
+
+/* Limited-memory BFGS (host code) with a strong-Wolfe line search
+ * (c1 = 1e-4, c2 = 0.9), the optimiser of the paper's VQE runs (Section 3.2);
+ * the decrease test tolerates 1e-13 max(|f|, 1) of rounding noise in f.
+ * x: host, n doubles, start point in, final point out.  history: curvature
+ * pairs kept (1..64).  Stops with *reason = 0 when max |g_i| <= g_tol, 1 when
+ * (f_tol > 0) an accepted step lowers f by at most
+ * f_tol * max(|f_old|, |f_new|, 1), 2 at
+ * max_iter iterations, 3 when the line search finds no acceptable step.
+ * f_out, iters, evals (objective calls), reason may be NULL.  An objective
+ * failure returns PBS_ERR_ARG. */
+pbs_status pbs_lbfgs_minimize(uint32_t n, double* x, pbs_objective fn, void* user, uint32_t max_iter,
+                              uint32_t history, double g_tol, double f_tol, double* f_out, uint32_t* iters,
+                              uint32_t* evals, int32_t* reason);
+
+/* ------------------------------------------------------------------ warm-start network */
+
+/* A 1 -> H -> H -> O perceptron that maps a geometry coordinate R of a
+ * potential-energy scan to ansatz parameters theta(R), trained on converged
+ * parameters of earlier geometries (an extension beyond the paper, which
+ * optimises each geometry from scratch, Section 3.2):
+ *   h1 = tanh(W1 R + b1), h2 = tanh(W2 h1 + b2), y = W3 h2 + b3,
+ * loss = mean over rows and outputs of (y - t)^2, full-batch Adam
+ * (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected).
+ * Every product rounds its operands to bfloat16 (nearest-even) and
+ * accumulates in float32 on the matrix cores; parameters, Adam moments,
+ * activations and bias gradients are float32.
+ * Parameters are one float32 array packed as
+ *   [W1 (H), b1 (H), W2 (H*H, row j = unit j), b2 (H), W3 (O*H), b3 (O)];
+ * gradients use the same layout. */
+
+/* Number of packed parameters for hidden width H and output width O. */
+pbs_status pbs_mlp_param_count(uint32_t hidden, uint32_t n_out, uint64_t* count);
+
+/* hidden: multiple of 32 in 32..1024; n_out 1..1024; max_batch 1..4096 rows.
+ * params: host or device, packed initial parameters (copied).  Adam state
+ * starts at zero.  Allocates every buffer the other calls use.  Synchronizes. */
+pbs_status pbs_mlp_create(uint32_t hidden, uint32_t n_out, uint32_t max_batch, const float* params, void* stream,
+                          pbs_mlp** out);
+
+/* Replaces the parameters (host or device source) and resets Adam.  Synchronizes. */
+pbs_status pbs_mlp_set_params(pbs_mlp* m, const float* params, void* stream);
+
+/* Copies the parameters to a host or device array.  Synchronizes. */
+pbs_status pbs_mlp_get_params(const pbs_mlp* m, float* params, void* stream);
+
+/* Inference: y[n][O] (device, row-major) for inputs x[n] (device), 1 <= n <= max_batch.
+ * Asynchronous.  Calls on one handle must not overlap (shared activations). */
+pbs_status pbs_mlp_forward(pbs_mlp* m, uint32_t n, const float* x, float* y, void* stream);
+
+/* Loss and gradient without an update: targets t[n][O] (device), loss (device
+ * float, may be NULL), grad (device, packed layout).  Asynchronous. */
+pbs_status pbs_mlp_loss_grad(pbs_mlp* m, uint32_t n, const float* x, const float* t, float* loss, float* grad,
+                             void* stream);
+
+/* n_steps full-batch Adam steps with learning rate lr on (x, t), continuing
+ * the handle's step count; losses (device, n_steps floats, may be NULL)
+ * receives the loss before each step.  Asynchronous. */
+pbs_status pbs_mlp_train(pbs_mlp* m, uint32_t n, const float* x, const float* t, uint32_t n_steps, float lr,
+                         float* losses, void* stream);
+
+void pbs_mlp_destroy(pbs_mlp* m);
 
 #ifdef __cplusplus
 }

@@ -7,7 +7,7 @@ fallback.
 
 import ctypes
 import os
-from ctypes import POINTER, c_char_p, c_double, c_int32, c_uint8, c_uint32, c_uint64, c_void_p
+from ctypes import POINTER, c_char_p, c_double, c_float, c_int32, c_uint8, c_uint32, c_uint64, c_void_p
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libpbs.so")
 
@@ -52,7 +52,19 @@ SIGNATURES = {
     "pbs_vqe_create": (c_int32, [_vp, c_uint32, c_uint32, _vp, _vp, c_uint64, c_int32, _vp, POINTER(_vp)]),
     "pbs_vqe_energy_grad": (c_int32, [_vp, _vp, _vp, _vp, _vp]),
     "pbs_vqe_state": (c_int32, [_vp, _vp, _vp]),
+    "pbs_vqe_minimize": (c_int32, [_vp, _vp, c_uint32, c_double, c_double, _vp, POINTER(c_double),
+                                   POINTER(c_uint32), POINTER(c_uint32), POINTER(c_int32)]),
     "pbs_vqe_destroy": (None, [_vp]),
+    "pbs_lbfgs_minimize": (c_int32, [c_uint32, _vp, _vp, _vp, c_uint32, c_uint32, c_double, c_double,
+                                     POINTER(c_double), POINTER(c_uint32), POINTER(c_uint32), POINTER(c_int32)]),
+    "pbs_mlp_param_count": (c_int32, [c_uint32, c_uint32, POINTER(c_uint64)]),
+    "pbs_mlp_create": (c_int32, [c_uint32, c_uint32, c_uint32, _vp, _vp, POINTER(_vp)]),
+    "pbs_mlp_set_params": (c_int32, [_vp, _vp, _vp]),
+    "pbs_mlp_get_params": (c_int32, [_vp, _vp, _vp]),
+    "pbs_mlp_forward": (c_int32, [_vp, c_uint32, _vp, _vp, _vp]),
+    "pbs_mlp_loss_grad": (c_int32, [_vp, c_uint32, _vp, _vp, _vp, _vp, _vp]),
+    "pbs_mlp_train": (c_int32, [_vp, c_uint32, _vp, _vp, c_uint32, c_float, _vp, _vp]),
+    "pbs_mlp_destroy": (None, [_vp]),
 }
 
 _LIB = None

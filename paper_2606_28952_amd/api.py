@@ -17,8 +17,11 @@ from ._abi import PBS_C64, PBS_C128, call
 
 __all__ = [
     "PauliSum", "Grouped", "Space", "pauli_mul", "jw_transform", "apply_pauli_sum", "expval",
-    "words_for", "PBS_C64", "PBS_C128", "KrylovPropagator", "Batch", "VQE",
+    "words_for", "PBS_C64", "PBS_C128", "KrylovPropagator", "Batch", "VQE", "MLP", "lbfgs_minimize",
+    "STOP_REASONS",
 ]
+
+STOP_REASONS = {0: "gradient", 1: "decrease", 2: "iterations", 3: "line search"}
 
 
 def words_for(n_qubits):
@@ -346,6 +349,16 @@ class VQE:
         call("pbs_vqe_energy_grad", self._h, _ptr(th), byref(e), _ptr(g), _stream())
         return e.value, g
 
+    def minimize(self, theta0, max_iter=500, g_tol=1e-6, f_tol=1e-12):
+        """L-BFGS from theta0; returns (theta, energy, iterations, evaluations, reason)."""
+        th = np.ascontiguousarray(np.asarray(theta0, dtype=np.float64).reshape(-1)).copy()
+        if th.shape[0] != self.n_rot:
+            raise ValueError(f"expected {self.n_rot} parameters")
+        e, it, ev, why = ctypes.c_double(), c_uint32(), c_uint32(), c_int32()
+        call("pbs_vqe_minimize", self._h, _ptr(th), int(max_iter), float(g_tol), float(f_tol), _stream(),
+             byref(e), byref(it), byref(ev), byref(why))
+        return th, e.value, it.value, ev.value, STOP_REASONS[why.value]
+
     def state(self):
         psi = torch.empty(1 << (2 * self.n_orb), dtype=self.dtype, device="cuda")
         call("pbs_vqe_state", self._h, _ptr(psi), _stream())
@@ -355,4 +368,99 @@ class VQE:
         h = getattr(self, "_h", None)
         if h is not None and h.value and _abi is not None and _abi._LIB is not None:
             _abi._LIB.pbs_vqe_destroy(h)
+            self._h = None
+
+
+_OBJECTIVE = ctypes.CFUNCTYPE(c_int32, c_void_p, c_uint32, ctypes.POINTER(ctypes.c_double),
+                              ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double))
+
+
+def lbfgs_minimize(fg, x0, max_iter=500, history=10, g_tol=1e-6, f_tol=1e-12):
+    """L-BFGS of the library on a host objective fg(x) -> (f, g) over float64
+    arrays; returns (x, f, iterations, evaluations, reason)."""
+    x = np.ascontiguousarray(np.asarray(x0, dtype=np.float64).reshape(-1)).copy()
+    n = x.shape[0]
+    errors = []
+
+    def trampoline(_user, m, xp, fp, gp):
+        try:
+            xv = np.ctypeslib.as_array(xp, shape=(m,)).copy()
+            f, g = fg(xv)
+            fp[0] = float(f)
+            np.ctypeslib.as_array(gp, shape=(m,))[:] = np.asarray(g, dtype=np.float64).reshape(-1)
+            return 0
+        except Exception as exc:  # reported after the call returns
+            errors.append(exc)
+            return 1
+
+    cb = _OBJECTIVE(trampoline)
+    f, it, ev, why = ctypes.c_double(), c_uint32(), c_uint32(), c_int32()
+    try:
+        call("pbs_lbfgs_minimize", n, _ptr(x), ctypes.cast(cb, c_void_p), None, int(max_iter), int(history),
+             float(g_tol), float(f_tol), byref(f), byref(it), byref(ev), byref(why))
+    except _abi.PbsError:
+        if errors:
+            raise errors[0]
+        raise
+    return x, f.value, it.value, ev.value, STOP_REASONS[why.value]
+
+
+class MLP:
+    """Warm-start network 1 -> hidden -> hidden -> n_out (bf16 products, float32
+    accumulation, Adam), parameters packed as in include/pbs.h."""
+
+    def __init__(self, hidden, n_out, max_batch, params):
+        self.hidden, self.n_out, self.max_batch = int(hidden), int(n_out), int(max_batch)
+        p = np.ascontiguousarray(np.asarray(params, dtype=np.float32).reshape(-1))
+        if p.shape[0] != self.param_count(hidden, n_out):
+            raise ValueError(f"expected {self.param_count(hidden, n_out)} parameters, got {p.shape[0]}")
+        out = c_void_p()
+        call("pbs_mlp_create", self.hidden, self.n_out, self.max_batch, _ptr(p), _stream(), byref(out))
+        self._h = out
+
+    @staticmethod
+    def param_count(hidden, n_out):
+        c = c_uint64()
+        call("pbs_mlp_param_count", int(hidden), int(n_out), byref(c))
+        return c.value
+
+    def _rows(self, x):
+        x = torch.as_tensor(x, dtype=torch.float32, device="cuda").reshape(-1).contiguous()
+        return x, x.shape[0]
+
+    def set_params(self, params):
+        p = np.ascontiguousarray(np.asarray(params, dtype=np.float32).reshape(-1))
+        call("pbs_mlp_set_params", self._h, _ptr(p), _stream())
+
+    def params(self):
+        p = np.zeros(self.param_count(self.hidden, self.n_out), np.float32)
+        call("pbs_mlp_get_params", self._h, _ptr(p), _stream())
+        return p
+
+    def forward(self, x):
+        x, n = self._rows(x)
+        y = torch.empty((n, self.n_out), dtype=torch.float32, device="cuda")
+        call("pbs_mlp_forward", self._h, n, _ptr(x), _ptr(y), _stream())
+        return y
+
+    def loss_grad(self, x, t):
+        x, n = self._rows(x)
+        t = torch.as_tensor(t, dtype=torch.float32, device="cuda").reshape(n, self.n_out).contiguous()
+        loss = torch.empty(1, dtype=torch.float32, device="cuda")
+        g = torch.empty(self.param_count(self.hidden, self.n_out), dtype=torch.float32, device="cuda")
+        call("pbs_mlp_loss_grad", self._h, n, _ptr(x), _ptr(t), _ptr(loss), _ptr(g), _stream())
+        return loss, g
+
+    def train(self, x, t, n_steps, lr):
+        x, n = self._rows(x)
+        t = torch.as_tensor(t, dtype=torch.float32, device="cuda").reshape(n, self.n_out).contiguous()
+        losses = torch.empty(max(1, int(n_steps)), dtype=torch.float32, device="cuda")
+        call("pbs_mlp_train", self._h, n, _ptr(x), _ptr(t), int(n_steps), ctypes.c_float(lr), _ptr(losses),
+             _stream())
+        return losses[:n_steps]
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _abi is not None and _abi._LIB is not None:
+            _abi._LIB.pbs_mlp_destroy(h)
             self._h = None

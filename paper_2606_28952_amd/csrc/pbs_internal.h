@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <algorithm>
+#include <functional>
 #include <cstring>
 #include <stdexcept>
 #include <string>
@@ -210,4 +211,19 @@ namespace pbs {
 // arrays; fills `out` (allocates its arrays).
 void canonicalize_soa(uint32_t n_qubits, int W, uint64_t m, DevBuf<uint64_t>& keys, DevBuf<double>& re,
                       DevBuf<double>& im, double eps_drop, pbs_sum& out, hipStream_t s);
+}  // namespace pbs
+
+namespace pbs {
+// ---------------------------------------------------------------- L-BFGS (optim.hip)
+using Objective = std::function<void(const double* x, double* f, double* g)>;
+enum : int32_t { kStopGradient = 0, kStopDecrease = 1, kStopIterations = 2, kStopLineSearch = 3 };
+struct LbfgsResult {
+  double f = 0.0, g_inf = 0.0;
+  uint32_t iters = 0, evals = 0;
+  int32_t reason = kStopIterations;
+};
+// Minimises fg from x (updated in place); f_noise is the relative rounding
+// noise of f allowed in the sufficient-decrease test.  See optim.hip.
+LbfgsResult lbfgs_minimize(uint32_t n, double* x, const Objective& fg, uint32_t max_iter, uint32_t history,
+                           double g_tol, double f_tol, double f_noise);
 }  // namespace pbs

@@ -350,6 +350,28 @@ pbs_status pbs_vqe_state(const pbs_vqe* v, void* psi_out, void* stream) {
   });
 }
 
+pbs_status pbs_vqe_minimize(pbs_vqe* v, double* theta, uint32_t max_iter, double g_tol, double f_tol, void* stream,
+                            double* energy, uint32_t* iters, uint32_t* evals, int32_t* reason) {
+  return guarded([&] {
+    PBS_REQUIRE(v != nullptr && theta != nullptr, PBS_ERR_ARG, "null argument");
+    PBS_REQUIRE(v->n_rot >= 1, PBS_ERR_ARG, "nothing to optimise: the ansatz has no rotations");
+    hipStream_t s = as_stream(stream);
+    const Objective fg = [&](const double* th, double* f, double* g) {
+      if (v->dt == PBS_C128)
+        energy_grad<double2>(*v, th, f, g, s);
+      else
+        energy_grad<float2>(*v, th, f, g, s);
+    };
+    // energies of a complex64 state carry float32 rounding noise
+    const double noise = v->dt == PBS_C128 ? 1e-13 : 1e-6;
+    const LbfgsResult r = lbfgs_minimize(v->n_rot, theta, fg, max_iter, 10, g_tol, f_tol, noise);
+    if (energy) *energy = r.f;
+    if (iters) *iters = r.iters;
+    if (evals) *evals = r.evals;
+    if (reason) *reason = r.reason;
+  });
+}
+
 void pbs_vqe_destroy(pbs_vqe* v) { delete v; }
 
 }  // extern "C"
