@@ -200,17 +200,24 @@ def random_symplectic(n_strings, n_qubits, seed, pool=None):
     return np.ascontiguousarray(x), np.ascontiguousarray(z), phase
 
 
-def pes_integrals(n_orb, r, seed=5001):
-    """Spatial integrals along a synthetic potential-energy scan:
-    h(R) = h0 + R h1 + R^2 h2 and g(R) = g0 + R g1 + R^2 g2, where (h_k, g_k)
-    is ``molecular_integrals(n_orb, seed + k)``.  Returns spin-orbital
-    (h1, h2) arrays of ``spin_orbital_integrals``."""
+def pes_integrals(n_orb, r, seed=5001, r_scale=0.3):
+    """Spatial integrals along a synthetic potential-energy scan, returned as
+    spin-orbital (h1, h2) arrays of ``spin_orbital_integrals``.
+
+    h(R) = h0 + s (R h1 + R^2 h2) and g(R) = g0 + s (R g1 + R^2 g2) with
+    s = r_scale, where (h_k, g_k) is ``molecular_integrals(n_orb, seed + k)``
+    expressed in the eigenbasis of h0 (orbitals ordered by h0's eigenvalues).
+    In that basis the reference that fills the lowest orbitals is the
+    one-body ground state of h0, so the scan starts near a mean-field
+    solution, as a molecular scan in its Hartree-Fock orbitals does."""
+    hs, gs = zip(*(molecular_integrals(n_orb, seed + k) for k in range(3)))
+    _, u = np.linalg.eigh(hs[0])
     h = np.zeros((n_orb, n_orb))
     g = np.zeros((n_orb,) * 4)
     for k in range(3):
-        hk, gk = molecular_integrals(n_orb, seed + k)
-        h = h + r ** k * hk
-        g = g + r ** k * gk
+        f = 1.0 if k == 0 else r_scale * r ** k
+        h = h + f * (u.T @ hs[k] @ u)
+        g = g + f * np.einsum("pqrs,pi,qj,rk,sl->ijkl", gs[k], u, u, u, u, optimize=True)
     return spin_orbital_integrals(h, g)
 
 

@@ -7,9 +7,12 @@ Tolerances.  Both sides multiply the same bf16-rounded weights; the kernel
 accumulates in float32 (error <= K u32 sum|a b|, about 1.5e-5 relative for
 K = 256), and rounds its own float32 activations to bf16 where the oracle
 rounds float64 ones.  The two roundings differ by one bf16 ulp (2^-8
-relative) only for the few operands whose float32 and float64 values straddle
-a rounding boundary, so results agree to well under 2^-8 in the relative
-2-norm; that is the bound used for outputs, losses and gradient blocks."""
+relative) only for operands whose float32 and float64 values straddle a
+rounding boundary: a fraction of about K u32 / 2^-8 (~2e-3) of them, each
+moving a K-term sum by 2^-8 / sqrt(K) in the relative 2-norm, so the
+expected effect is ~1e-5 and BOUND = 2^-12 (2.4e-4) holds outputs, losses
+and gradient blocks with room to spare, while a wrong index, operand or
+rounding point shows up at 1e-2 or more."""
 
 import numpy as np
 import pytest
@@ -20,7 +23,7 @@ from oracle import mlp as omlp
 
 pytestmark = pytest.mark.gpu
 
-BOUND = 2.0 ** -8
+BOUND = 2.0 ** -12
 
 
 def _api():
@@ -83,11 +86,13 @@ def test_adam_trajectory_matches_oracle(dev):
     net = api.MLP(H, O, 64, p)
     losses = net.train(torch.from_numpy(x).to(dev), torch.from_numpy(t).to(dev), steps, lr).cpu().numpy()
     q, want_losses, _ = omlp.train(p.astype(np.float64), x, t, H, O, steps, lr)
-    assert np.all(np.abs(losses - want_losses) < BOUND * want_losses)
+    assert np.all(np.abs(losses - want_losses) < 16 * BOUND * want_losses)
     assert losses[-1] < 0.5 * losses[0]
     got = net.params().astype(np.float64)
-    # Adam moves each weight by at most about lr per step; compare the moves
-    assert _rel(got - p, q - p) < 4 * BOUND
+    # Adam divides by the root of the second moment, which amplifies the
+    # gradient differences of weights whose gradients are near zero; the
+    # moves still agree to a few percent of the bf16 step
+    assert _rel(got - p, q - p) < 64 * BOUND
 
 
 def test_training_generalises_between_samples(dev):
