@@ -232,13 +232,75 @@ def bench_krylov(args):
                       "final_state_rel_diff_c64_vs_c128": diff}))
 
 
+def bench_pes(args):
+    """Learned warm start on a potential-energy scan: 12 orbitals, (6, 6)
+    reference, 24 qubits (full 2^24 space), 200 excitation rotations,
+    R_j = j / (G - 1) for j < G geometries.  Every geometry runs the
+    variational minimisation from the reference (cold) and from the network's
+    prediction (warm, with the cold start as fallback); the network
+    1 -> 256 -> 256 -> 200 is retrained on the converged parameters.  Prints
+    one progress line per geometry on stderr and one JSON summary line."""
+    import torch
+
+    import synth
+    from paper_2606_28952_amd import api, pes
+
+    n_orb, na, nb, n_rot = 12, 6, 6, 200
+    dev = torch.device("cuda:0")
+    gens = synth.excitation_generators(n_orb, na, nb, n_rot)
+    ref = ((1 << na) - 1) | (((1 << nb) - 1) << n_orb)
+    radii = np.linspace(0.0, 1.0, args.geometries)
+    # cost of one energy + gradient evaluation at the middle of the scan
+    h1, h2 = synth.pes_integrals(n_orb, 0.5)
+    G = api.jw_transform(torch.from_numpy(h1).to(dev), torch.from_numpy(h2).to(dev)).group()
+    _, n_groups, n_terms = G.info()
+    x, z = pes.letters_to_masks(gens)
+    evals = {}
+    for name, dtype in (("c128", torch.complex128), ("c64", torch.complex64)):
+        v = api.VQE(G, n_orb, x, z, ref, dtype=dtype)
+        th = np.random.default_rng(0).normal(size=n_rot) * 0.05
+        v.energy_grad(th)
+        t0 = time.perf_counter()
+        for _ in range(3):
+            v.energy_grad(th)
+        t_eg = (time.perf_counter() - t0) / 3
+        t0 = time.perf_counter()
+        for _ in range(3):
+            v.energy(th)
+        evals[name] = {"energy_grad_ms": t_eg * 1e3, "energy_ms": (time.perf_counter() - t0) / 3 * 1e3}
+        del v
+    del G
+
+    def log(j, r):
+        print(f"[pes] {j + 1}/{len(radii)} R={r['R']:.4f} cold {r['E_cold']:.10f} ({r['iters_cold']} it) "
+              f"warm[{r['start']}] {r['E_warm']:.10f} ({r['iters_warm']} it) {r['sec_total']:.1f}s",
+              file=sys.stderr, flush=True)
+
+    t0 = time.perf_counter()
+    recs = pes.scan(lambda r: synth.pes_integrals(n_orb, r), radii, n_orb, gens, ref, dtype=torch.complex128,
+                    hidden=256, mlp_params=synth.mlp_init(256, n_rot, seed=2), train_steps=600, lr=1e-3,
+                    g_tol=1e-5, log=log)
+    wall = time.perf_counter() - t0
+    summ = pes.summary(recs)
+    out = {"workload": "pes-scan-24q", "n_qubits": 2 * n_orb, "dim": 1 << (2 * n_orb), "rotations": n_rot,
+           "geometries": len(radii), "pauli_strings_R0.5": n_terms, "groups_R0.5": n_groups,
+           "network": "1-256-256-200 bf16/fp32", "dtype": "c128 (fp64 energies)",
+           "g_tol": 1e-5, "wall_s": wall, "evaluation": evals, **summ,
+           "sec_cold": sum(r["sec_cold"] for r in recs), "sec_warm": sum(r["sec_warm"] for r in recs),
+           "sec_train": sum(r.get("sec_train", 0.0) for r in recs),
+           "per_geometry": [{k: r[k] for k in ("R", "E_ref", "E_cold", "iters_cold", "E_warm", "iters_warm",
+                                                "start")} for r in recs]}
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="molecular-28q-sector",
-                    choices=sorted(WORKLOADS) + ["batched-64", "hubbard-krylov"])
+                    choices=sorted(WORKLOADS) + ["batched-64", "hubbard-krylov", "pes-scan"])
+    ap.add_argument("--geometries", type=int, default=40, help="pes-scan: number of geometries")
     ap.add_argument("--krylov-steps", type=int, default=200)
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="counter calibration: one device-to-device copy of this many bytes, nothing else")
@@ -265,6 +327,8 @@ def main():
         return bench_batched(args)
     if args.workload == "hubbard-krylov":
         return bench_krylov(args)
+    if args.workload == "pes-scan":
+        return bench_pes(args)
 
     import torch
 

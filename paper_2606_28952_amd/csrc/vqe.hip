@@ -70,24 +70,63 @@ __global__ __launch_bounds__(kBlock) void k_rotate(T* __restrict__ psi, uint64_t
   }
 }
 
-// Workgroup partials of <lam|P|psi> = sum_t conj(lam[t]) omega (-1)^(z.(t^x)) psi[t ^ x].
+// One step of the adjoint sweep in a single pass: workgroup partials of
+// <lam|P|psi> = sum_t conj(lam[t]) (P psi)[t], then psi <- R^dagger psi and
+// lam <- R^dagger lam
+// with R^dagger = cos theta - i sin theta P, all from the same loads.  c, s
+// are cos(-theta), sin(-theta).
 template <class T>
-__global__ __launch_bounds__(kBlock) void k_overlap(const T* __restrict__ lam, const T* __restrict__ psi,
-                                                     uint64_t dim, uint64_t x, uint64_t z, uint32_t omega,
-                                                     double* __restrict__ partial) {
+__global__ __launch_bounds__(kBlock) void k_adjoint_step(T* __restrict__ psi, T* __restrict__ lam, uint64_t dim,
+                                                          uint64_t x, uint64_t z, uint32_t omega, double c, double s,
+                                                          double* __restrict__ partial) {
   double sr = 0.0, si = 0.0;
-  for (uint64_t t = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; t < dim;
-       t += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
-    const uint64_t u = t ^ x;
-    double lr, li, pr, pi;
-    Amp<T>::load(lam, t, lr, li);
-    Amp<T>::load(psi, u, pr, pi);
-    const uint32_t par = __popcll(z & u);
-    pr = signed_by(pr, par);
-    pi = signed_by(pi, par);
-    times_i_pow(omega, pr, pi);
-    sr = fma(lr, pr, fma(li, pi, sr));
-    si = fma(lr, pi, fma(-li, pr, si));
+  if (x == 0) {
+    for (uint64_t t = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; t < dim;
+         t += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+      double pr, pi, lr, li;
+      Amp<T>::load(psi, t, pr, pi);
+      Amp<T>::load(lam, t, lr, li);
+      double wr = signed_by(1.0, __popcll(z & t)), wi = 0.0;  // P|t> = w |t>
+      times_i_pow(omega, wr, wi);
+      const double qr = wr * pr - wi * pi, qi = wr * pi + wi * pr;  // (P psi)[t]
+      sr = fma(lr, qr, fma(li, qi, sr));
+      si = fma(lr, qi, fma(-li, qr, si));
+      const double gr = c - s * wi, gi = s * wr;  // c + i s w
+      Amp<T>::store(psi, t, pr * gr - pi * gi, pr * gi + pi * gr);
+      Amp<T>::store(lam, t, lr * gr - li * gi, lr * gi + li * gr);
+    }
+  } else {
+    const uint32_t h = 63u - static_cast<uint32_t>(__clzll(static_cast<long long>(x)));
+    const uint64_t low = (1ull << h) - 1ull;
+    for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < dim / 2;
+         i += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+      const uint64_t t = ((i & ~low) << 1) | (i & low);
+      const uint64_t u = t ^ x;
+      double atr, ati, aur, aui, btr, bti, bur, bui;  // psi[t], psi[u], lam[t], lam[u]
+      Amp<T>::load(psi, t, atr, ati);
+      Amp<T>::load(psi, u, aur, aui);
+      Amp<T>::load(lam, t, btr, bti);
+      Amp<T>::load(lam, u, bur, bui);
+      const uint32_t pu = __popcll(z & u), pt = __popcll(z & t);
+      // (P v)[t] = omega (-1)^(z.u) v[u], (P v)[u] = omega (-1)^(z.t) v[t]
+      double ptr = signed_by(aur, pu), pti = signed_by(aui, pu);
+      double pur = signed_by(atr, pt), pui = signed_by(ati, pt);
+      double qtr = signed_by(bur, pu), qti = signed_by(bui, pu);
+      double qur = signed_by(btr, pt), qui = signed_by(bti, pt);
+      times_i_pow(omega, ptr, pti);
+      times_i_pow(omega, pur, pui);
+      times_i_pow(omega, qtr, qti);
+      times_i_pow(omega, qur, qui);
+      sr = fma(btr, ptr, fma(bti, pti, sr));
+      si = fma(btr, pti, fma(-bti, ptr, si));
+      sr = fma(bur, pur, fma(bui, pui, sr));
+      si = fma(bur, pui, fma(-bui, pur, si));
+      // v <- c v + i s (P v)
+      Amp<T>::store(psi, t, c * atr - s * pti, c * ati + s * ptr);
+      Amp<T>::store(psi, u, c * aur - s * pui, c * aui + s * pur);
+      Amp<T>::store(lam, t, c * btr - s * qti, c * bti + s * qtr);
+      Amp<T>::store(lam, u, c * bur - s * qui, c * bui + s * qur);
+    }
   }
   block_reduce3_store<kBlock>(sr, si, 0.0, partial + 3ull * blockIdx.x);
 }
@@ -215,10 +254,8 @@ void energy_grad(pbs_vqe& v, const double* theta, double* energy, double* grad, 
     // adjoint sweep: g_k = -2 Im <lam_k|P_k|psi_k>, then undo rotation k on both vectors
     for (uint32_t k = v.n_rot; k-- > 0;) {
       const Rot& r = v.rots[k];
-      hipLaunchKernelGGL((k_overlap<T>), dim3(v.nparts), dim3(kBlock), 0, s, lam, psi, v.dim, r.x, r.z, r.omega,
-                         v.partial.get() + 3ull * v.nparts * k);
-      rotate_all<T>(v, psi, theta, true, k, s);
-      rotate_all<T>(v, lam, theta, true, k, s);
+      hipLaunchKernelGGL((k_adjoint_step<T>), dim3(v.nparts), dim3(kBlock), 0, s, psi, lam, v.dim, r.x, r.z,
+                         r.omega, cos(-theta[k]), sin(-theta[k]), v.partial.get() + 3ull * v.nparts * k);
     }
     hipLaunchKernelGGL(k_sum_overlaps, dim3(v.n_rot), dim3(kBlock), 0, s, v.partial.get(), v.nparts,
                        v.overlaps.get());
