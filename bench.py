@@ -40,17 +40,22 @@ WORKLOADS = {
 }
 
 
+# sources that decide what the sector apply kernel does per launch: its
+# device code, its launch planner and the tables grouping builds for it
+APPLY_SOURCES = ("apply.hip", "group.hip", "handles.h", "sector.h", "sector_c128_apply.hip",
+                 "sector_c128_expval.hip", "sector_c64_apply.hip", "sector_c64_expval.hip")
+
+
 def _source_hash():
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2606_28952_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".h")):
-            with open(os.path.join(csrc, f), encoding="utf-8") as fh:
-                # code only: comment and blank-line edits do not change the kernels
-                for line in fh:
-                    code = line.split("//", 1)[0].rstrip()
-                    if code:
-                        h.update(code.encode() + b"\n")
+    for f in APPLY_SOURCES:
+        with open(os.path.join(csrc, f), encoding="utf-8") as fh:
+            # code only: comment and blank-line edits do not change the kernels
+            for line in fh:
+                code = line.split("//", 1)[0].rstrip()
+                if code:
+                    h.update(code.encode() + b"\n")
     return h.hexdigest()[:16]
 
 
