@@ -352,7 +352,7 @@ pbs_status pbs_vqe_create(const pbs_grouped* h, uint32_t n_orb, uint32_t n_rot, 
       PBS_HIP(hipMemcpyAsync(v->off.get(), off.data(), off.size() * 8, hipMemcpyHostToDevice, s));
       PBS_HIP(hipMemcpyAsync(v->binom_n.get(), bn.data(), bn.size() * 4, hipMemcpyHostToDevice, s));
       v->energies.alloc(3ull * v->n_jobs);
-      v->nparts = grid_for(dim, kBlock, 1024);
+      v->nparts = grid_for(dim / 2, kBlock, 4096);  // one pair per thread and pass, up to 4096 workgroups
       v->partial.alloc(3ull * v->nparts * (n_rot ? n_rot : 1));
       v->overlaps.alloc(2ull * (n_rot ? n_rot : 1));
       PBS_HIP(hipStreamSynchronize(s));

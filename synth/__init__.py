@@ -38,6 +38,18 @@ __all__ = [
 ]
 
 
+def _orbit_representatives(n_orb):
+    """Index arrays (a, b, c, d) such that g[a, b, c, d] is the canonical
+    representative of the 8-fold permutation orbit of each (p, q, r, s):
+    ordered pairs, then the ordered pair of pairs."""
+    p, q, r, s = np.indices((n_orb,) * 4)
+    pq_hi, pq_lo = np.maximum(p, q), np.minimum(p, q)
+    rs_hi, rs_lo = np.maximum(r, s), np.minimum(r, s)
+    first_is_big = pq_hi * n_orb + pq_lo >= rs_hi * n_orb + rs_lo
+    return (np.where(first_is_big, pq_hi, rs_hi), np.where(first_is_big, pq_lo, rs_lo),
+            np.where(first_is_big, rs_hi, pq_hi), np.where(first_is_big, rs_lo, pq_lo))
+
+
 def molecular_integrals(n_orb, seed, h_scale=1.0, g_scale=0.1):
     """Random real spatial integrals (h, g).
 
@@ -49,18 +61,7 @@ def molecular_integrals(n_orb, seed, h_scale=1.0, g_scale=0.1):
     a = rng.standard_normal((n_orb, n_orb)) * h_scale
     h = np.triu(a) + np.triu(a, 1).T
     raw = rng.standard_normal((n_orb,) * 4) * g_scale
-    p, q, r, s = np.indices((n_orb,) * 4)
-    # canonical representative of each orbit: ordered pairs, then ordered pair-of-pairs
-    pq_hi, pq_lo = np.maximum(p, q), np.minimum(p, q)
-    rs_hi, rs_lo = np.maximum(r, s), np.minimum(r, s)
-    pq = pq_hi * n_orb + pq_lo
-    rs = rs_hi * n_orb + rs_lo
-    first_is_big = pq >= rs
-    a_hi = np.where(first_is_big, pq_hi, rs_hi)
-    a_lo = np.where(first_is_big, pq_lo, rs_lo)
-    b_hi = np.where(first_is_big, rs_hi, pq_hi)
-    b_lo = np.where(first_is_big, rs_lo, pq_lo)
-    g = raw[a_hi, a_lo, b_hi, b_lo]
+    g = raw[_orbit_representatives(n_orb)]
     return h, g
 
 
@@ -218,6 +219,11 @@ def pes_integrals(n_orb, r, seed=5001, r_scale=0.3):
         f = 1.0 if k == 0 else r_scale * r ** k
         h = h + f * (u.T @ hs[k] @ u)
         g = g + f * np.einsum("pqrs,pi,qj,rk,sl->ijkl", gs[k], u, u, u, u, optimize=True)
+    # the rotation keeps the symmetries only up to rounding: give every
+    # symmetric pair of h and every 8-fold orbit of g one exact value, so that
+    # Pauli strings whose contributions cancel by symmetry cancel exactly
+    h = 0.5 * (h + h.T)
+    g = g[_orbit_representatives(n_orb)]
     return spin_orbital_integrals(h, g)
 
 
