@@ -131,6 +131,152 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_step(T* __restrict__ psi, T*
   block_reduce3_store<kBlock>(sr, si, 0.0, partial + 3ull * blockIdx.x);
 }
 
+// ---------------------------------------------------------------- two rotations per pass
+// Rotations a and b with independent nonzero X masks act together on the
+// orbits {t, t^xa, t^xb, t^xa^xb}.  Pivot bits: h1 = highest bit of xa and
+// h2 = highest bit of y, where y is xb or xb^xa, whichever has bit h1 clear.
+// Every orbit holds exactly one index with both pivot bits clear, which is
+// enumerated by inserting zero bits at the two pivots (lo < hi) into i.
+struct PairRot {
+  uint64_t x, z;
+  uint32_t omega;
+  double c, s;
+};
+
+struct Cx {
+  double r, i;
+};
+
+// (P v)[t] for the pair (t, u = t ^ x): omega (-1)^(z.u) v[u]
+__device__ inline Cx pauli_image(const Cx& vu, uint64_t z, uint64_t u, uint32_t omega) {
+  const uint32_t p = __popcll(z & u);
+  double r = signed_by(vu.r, p), m = signed_by(vu.i, p);
+  times_i_pow(omega, r, m);
+  return Cx{r, m};
+}
+
+// (vt, vu) <- (c vt + i s (P v)[t], c vu + i s (P v)[u])
+__device__ inline void rotate_pair(Cx& vt, Cx& vu, uint64_t t, uint64_t u, const PairRot& R) {
+  const Cx pt = pauli_image(vu, R.z, u, R.omega), pu = pauli_image(vt, R.z, t, R.omega);
+  vt = Cx{R.c * vt.r - R.s * pt.i, R.c * vt.i + R.s * pt.r};
+  vu = Cx{R.c * vu.r - R.s * pu.i, R.c * vu.i + R.s * pu.r};
+}
+
+// acc += conj(l[t]) (P a)[t] + conj(l[u]) (P a)[u]
+__device__ inline void overlap_pair(const Cx& at, const Cx& au, const Cx& lt, const Cx& lu, uint64_t t, uint64_t u,
+                                    const PairRot& R, double& sr, double& si) {
+  const Cx pt = pauli_image(au, R.z, u, R.omega), pu = pauli_image(at, R.z, t, R.omega);
+  sr = fma(lt.r, pt.r, fma(lt.i, pt.i, sr));
+  si = fma(lt.r, pt.i, fma(-lt.i, pt.r, si));
+  sr = fma(lu.r, pu.r, fma(lu.i, pu.i, sr));
+  si = fma(lu.r, pu.i, fma(-lu.i, pu.r, si));
+}
+
+__device__ inline uint64_t insert_zero(uint64_t v, uint32_t b) {
+  const uint64_t low = (1ull << b) - 1ull;
+  return ((v & ~low) << 1) | (v & low);
+}
+
+template <class T>
+__device__ inline Cx load_cx(const T* p, uint64_t i) {
+  Cx v;
+  Amp<T>::load(p, i, v.r, v.i);
+  return v;
+}
+
+template <class T>
+__device__ inline void store_cx(T* p, uint64_t i, const Cx& v) {
+  Amp<T>::store(p, i, v.r, v.i);
+}
+
+// psi <- R_b R_a psi
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_rotate2(T* __restrict__ psi, uint64_t dim, PairRot A, PairRot B,
+                                                     uint32_t lo, uint32_t hi) {
+  for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < dim / 4;
+       i += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+    const uint64_t t0 = insert_zero(insert_zero(i, lo), hi);
+    const uint64_t t1 = t0 ^ A.x, t2 = t0 ^ B.x, t3 = t1 ^ B.x;
+    Cx v0 = load_cx(psi, t0), v1 = load_cx(psi, t1), v2 = load_cx(psi, t2), v3 = load_cx(psi, t3);
+    rotate_pair(v0, v1, t0, t1, A);
+    rotate_pair(v2, v3, t2, t3, A);
+    rotate_pair(v0, v2, t0, t2, B);
+    rotate_pair(v1, v3, t1, t3, B);
+    store_cx(psi, t0, v0);
+    store_cx(psi, t1, v1);
+    store_cx(psi, t2, v2);
+    store_cx(psi, t3, v3);
+  }
+}
+
+// Two adjoint steps in one pass: with psi = psi_b and lam = lam_b on entry,
+// partials of <lam|P_b|psi>, then R_b^dagger on both vectors, partials of
+// <lam|P_a|psi>, then R_a^dagger on both (A and B carry cos, sin of -theta).
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_adjoint_step2(T* __restrict__ psi, T* __restrict__ lam, uint64_t dim,
+                                                           PairRot A, PairRot B, uint32_t lo, uint32_t hi,
+                                                           double* __restrict__ partial_a,
+                                                           double* __restrict__ partial_b) {
+  double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0;
+  for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < dim / 4;
+       i += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+    const uint64_t t0 = insert_zero(insert_zero(i, lo), hi);
+    const uint64_t t1 = t0 ^ A.x, t2 = t0 ^ B.x, t3 = t1 ^ B.x;
+    Cx p0 = load_cx(psi, t0), p1 = load_cx(psi, t1), p2 = load_cx(psi, t2), p3 = load_cx(psi, t3);
+    Cx l0 = load_cx(lam, t0), l1 = load_cx(lam, t1), l2 = load_cx(lam, t2), l3 = load_cx(lam, t3);
+    overlap_pair(p0, p2, l0, l2, t0, t2, B, br, bi);
+    overlap_pair(p1, p3, l1, l3, t1, t3, B, br, bi);
+    rotate_pair(p0, p2, t0, t2, B);
+    rotate_pair(p1, p3, t1, t3, B);
+    rotate_pair(l0, l2, t0, t2, B);
+    rotate_pair(l1, l3, t1, t3, B);
+    overlap_pair(p0, p1, l0, l1, t0, t1, A, ar, ai);
+    overlap_pair(p2, p3, l2, l3, t2, t3, A, ar, ai);
+    rotate_pair(p0, p1, t0, t1, A);
+    rotate_pair(p2, p3, t2, t3, A);
+    rotate_pair(l0, l1, t0, t1, A);
+    rotate_pair(l2, l3, t2, t3, A);
+    store_cx(psi, t0, p0);
+    store_cx(psi, t1, p1);
+    store_cx(psi, t2, p2);
+    store_cx(psi, t3, p3);
+    store_cx(lam, t0, l0);
+    store_cx(lam, t1, l1);
+    store_cx(lam, t2, l2);
+    store_cx(lam, t3, l3);
+  }
+  __shared__ double red[4][kBlock / 64];
+  for (int d = 32; d > 0; d >>= 1) {
+    ar += __shfl_xor(ar, d, 64);
+    ai += __shfl_xor(ai, d, 64);
+    br += __shfl_xor(br, d, 64);
+    bi += __shfl_xor(bi, d, 64);
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+    red[0][wave] = ar;
+    red[1][wave] = ai;
+    red[2][wave] = br;
+    red[3][wave] = bi;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    for (int w = 0; w < kBlock / 64; ++w) {
+      s0 += red[0][w];
+      s1 += red[1][w];
+      s2 += red[2][w];
+      s3 += red[3][w];
+    }
+    partial_a[3ull * blockIdx.x] = s0;
+    partial_a[3ull * blockIdx.x + 1] = s1;
+    partial_a[3ull * blockIdx.x + 2] = 0.0;
+    partial_b[3ull * blockIdx.x] = s2;
+    partial_b[3ull * blockIdx.x + 1] = s3;
+    partial_b[3ull * blockIdx.x + 2] = 0.0;
+  }
+}
+
 // out[k] = (sum of the partials of overlap k, real and imaginary parts), fixed order.
 __global__ __launch_bounds__(kBlock) void k_sum_overlaps(const double* partial, uint32_t nparts, double* out) {
   const double* p = partial + 3ull * nparts * blockIdx.x;
@@ -221,6 +367,20 @@ namespace pbs {
 namespace {
 constexpr unsigned kVqeGrid = 4096;
 
+// Pivot bits (lo < hi) for rotations a, b fused in one pass, or false when
+// their X masks are zero or equal (then they run one at a time).
+bool pair_pivots(const Rot& a, const Rot& b, uint32_t& lo, uint32_t& hi) {
+  if (a.x == 0 || b.x == 0 || a.x == b.x) return false;
+  const uint32_t h1 = 63u - static_cast<uint32_t>(__builtin_clzll(a.x));
+  const uint64_t y = ((b.x >> h1) & 1ull) ? (b.x ^ a.x) : b.x;
+  const uint32_t h2 = 63u - static_cast<uint32_t>(__builtin_clzll(y));
+  lo = h1 < h2 ? h1 : h2;
+  hi = h1 < h2 ? h2 : h1;
+  return true;
+}
+
+PairRot pair_rot(const Rot& r, double angle) { return PairRot{r.x, r.z, r.omega, cos(angle), sin(angle)}; }
+
 template <class T>
 void rotate_all(pbs_vqe& v, T* psi, const double* theta, bool inverse, uint32_t k, hipStream_t s) {
   const Rot& r = v.rots[k];
@@ -238,7 +398,17 @@ void energy_grad(pbs_vqe& v, const double* theta, double* energy, double* grad, 
   const dim3 grid(grid_for(v.dim, kBlock, kVqeGrid));
   hipLaunchKernelGGL(k_basis_state, grid, dim3(kBlock), 0, s, sizeof(T) == 16 ? reinterpret_cast<double2*>(psi) : nullptr,
                      sizeof(T) == 8 ? reinterpret_cast<float2*>(psi) : nullptr, v.dim, v.ref);
-  for (uint32_t k = 0; k < v.n_rot; ++k) rotate_all<T>(v, psi, theta, false, k, s);
+  for (uint32_t k = 0; k < v.n_rot;) {
+    uint32_t lo, hi;
+    if (k + 1 < v.n_rot && pair_pivots(v.rots[k], v.rots[k + 1], lo, hi)) {
+      hipLaunchKernelGGL((k_rotate2<T>), dim3(grid_for(v.dim / 4, kBlock, kVqeGrid)), dim3(kBlock), 0, s, psi, v.dim,
+                         pair_rot(v.rots[k], theta[k]), pair_rot(v.rots[k + 1], theta[k + 1]), lo, hi);
+      k += 2;
+    } else {
+      rotate_all<T>(v, psi, theta, false, k, s);
+      k += 1;
+    }
+  }
   // H psi through the sector blocks, with each block's energy
   const pbs_space& sp0 = *v.spaces[0];
   hipLaunchKernelGGL((k_fock_permute<T, true>), grid, dim3(kBlock), 0, s, psi, bin, v.dim, v.n_orb, sp0.n_chunks,
@@ -252,10 +422,19 @@ void energy_grad(pbs_vqe& v, const double* theta, double* energy, double* grad, 
     hipLaunchKernelGGL((k_fock_permute<T, false>), grid, dim3(kBlock), 0, s, bout, lam, v.dim, v.n_orb,
                        sp0.n_chunks, v.rank_tab.get(), v.off.get(), v.binom_n.get());
     // adjoint sweep: g_k = -2 Im <lam_k|P_k|psi_k>, then undo rotation k on both vectors
-    for (uint32_t k = v.n_rot; k-- > 0;) {
-      const Rot& r = v.rots[k];
-      hipLaunchKernelGGL((k_adjoint_step<T>), dim3(v.nparts), dim3(kBlock), 0, s, psi, lam, v.dim, r.x, r.z,
-                         r.omega, cos(-theta[k]), sin(-theta[k]), v.partial.get() + 3ull * v.nparts * k);
+    for (uint32_t k = v.n_rot; k > 0;) {
+      uint32_t lo, hi;
+      if (k >= 2 && pair_pivots(v.rots[k - 2], v.rots[k - 1], lo, hi)) {
+        hipLaunchKernelGGL((k_adjoint_step2<T>), dim3(v.nparts), dim3(kBlock), 0, s, psi, lam, v.dim,
+                           pair_rot(v.rots[k - 2], -theta[k - 2]), pair_rot(v.rots[k - 1], -theta[k - 1]), lo, hi,
+                           v.partial.get() + 3ull * v.nparts * (k - 2), v.partial.get() + 3ull * v.nparts * (k - 1));
+        k -= 2;
+      } else {
+        --k;
+        const Rot& r = v.rots[k];
+        hipLaunchKernelGGL((k_adjoint_step<T>), dim3(v.nparts), dim3(kBlock), 0, s, psi, lam, v.dim, r.x, r.z,
+                           r.omega, cos(-theta[k]), sin(-theta[k]), v.partial.get() + 3ull * v.nparts * k);
+      }
     }
     hipLaunchKernelGGL(k_sum_overlaps, dim3(v.n_rot), dim3(kBlock), 0, s, v.partial.get(), v.nparts,
                        v.overlaps.get());

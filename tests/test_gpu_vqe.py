@@ -32,6 +32,10 @@ def _problem(dev, n_orb, n_rot, seed):
     if n_rot >= 3:
         rots[1] = np.zeros(n, np.uint8)  # identity: a global phase
         rots[2] = np.where(rng.random(n) < 0.5, 3, 0).astype(np.uint8)  # diagonal
+    if n_rot >= 6:
+        # same X mask as its predecessor, different Z mask (X <-> Y swapped)
+        swap = np.array([0, 2, 1, 3], np.uint8)
+        rots[5] = swap[rots[4]]
     xz = [opauli.letters_to_xz(r) for r in rots]
     x = np.array([int(np.asarray(a).reshape(-1)[0]) for a, _ in xz], np.uint64)
     z = np.array([int(np.asarray(b).reshape(-1)[0]) for _, b in xz], np.uint64)
