@@ -63,7 +63,10 @@ def _connected_groups(x_groups, n_orb, n_alpha, n_beta):
     """Average number of groups whose source lies in the sector, per target:
     a group with masks (X_alpha, X_beta) connects a target iff each half flips
     as many occupied as empty orbitals; counted exactly by combinatorics."""
-    from math import comb
+    from math import comb as _comb
+
+    def comb(n, k):
+        return _comb(n, k) if 0 <= k <= n else 0
 
     mask = (1 << n_orb) - 1
     total = 0
@@ -259,6 +262,13 @@ def bench_pes(args):
     h1, h2 = synth.pes_integrals(n_orb, 0.5)
     G = api.jw_transform(torch.from_numpy(h1).to(dev), torch.from_numpy(h2).to(dev)).group()
     _, n_groups, n_terms = G.info()
+    # algorithmic gather bytes of one batched apply over all sector blocks:
+    # sum over blocks of D_block * (1 + connected groups per target) amplitudes
+    xg = G.read()[0]
+    from math import comb
+
+    gathers = sum(comb(n_orb, a) * comb(n_orb, b) * (1.0 + _connected_groups(xg, n_orb, a, b))
+                  for a in range(n_orb + 1) for b in range(n_orb + 1))
     x, z = pes.letters_to_masks(gens)
     evals = {}
     for name, dtype in (("c128", torch.complex128), ("c64", torch.complex64)):
@@ -289,6 +299,7 @@ def bench_pes(args):
     summ = pes.summary(recs)
     out = {"workload": "pes-scan-24q", "n_qubits": 2 * n_orb, "dim": 1 << (2 * n_orb), "rotations": n_rot,
            "geometries": len(radii), "pauli_strings_R0.5": n_terms, "groups_R0.5": n_groups,
+           "apply_gather_amplitudes_R0.5": gathers,
            "network": "1-256-256-200 bf16/fp32", "dtype": "c128 (fp64 energies)",
            "g_tol": 1e-5, "wall_s": wall, "evaluation": evals, **summ,
            "sec_cold": sum(r["sec_cold"] for r in recs), "sec_warm": sum(r["sec_warm"] for r in recs),

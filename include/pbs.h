@@ -308,6 +308,13 @@ pbs_status pbs_vqe_state(const pbs_vqe* v, void* psi_out, void* stream);
 pbs_status pbs_vqe_minimize(pbs_vqe* v, double* theta, uint32_t max_iter, double g_tol, double f_tol, void* stream,
                             double* energy, uint32_t* iters, uint32_t* evals, int32_t* reason);
 
+/* Number of (N_alpha, N_beta) blocks of the handle, and how many of them are
+ * stored and applied as sector (N_beta, N_alpha): blocks with fewer beta than
+ * alpha strings and fewer than 512 beta strings, when the operator maps onto
+ * itself term by term under exchanging the two qubit halves (spin-free
+ * integrals).  Either output may be NULL. */
+pbs_status pbs_vqe_info(const pbs_vqe* v, uint32_t* n_blocks, uint32_t* n_transposed);
+
 void pbs_vqe_destroy(pbs_vqe* v);
 
 /* ------------------------------------------------------------------ optimizer */

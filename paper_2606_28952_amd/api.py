@@ -359,6 +359,12 @@ class VQE:
              byref(e), byref(it), byref(ev), byref(why))
         return th, e.value, it.value, ev.value, STOP_REASONS[why.value]
 
+    def blocks(self):
+        """(sector blocks, blocks stored as sector (N_beta, N_alpha))."""
+        nb, nt = c_uint32(), c_uint32()
+        call("pbs_vqe_info", self._h, byref(nb), byref(nt))
+        return nb.value, nt.value
+
     def state(self):
         psi = torch.empty(1 << (2 * self.n_orb), dtype=self.dtype, device="cuda")
         call("pbs_vqe_state", self._h, _ptr(psi), _stream())

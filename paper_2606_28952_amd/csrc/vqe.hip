@@ -9,6 +9,8 @@
 // sector space), running the batched sector kernel over all blocks in one
 // launch, and permuting back.  Rotations and overlaps are bandwidth-bound
 // passes over the full-space vectors.
+#include <algorithm>
+#include <cstring>
 #include <vector>
 
 #include "sector.h"
@@ -302,6 +304,8 @@ __global__ void k_basis_state(double2* psi64, float2* psi32, uint64_t dim, uint6
   }
 }
 
+constexpr uint64_t kTransposed = 1ull << 63;  // block offset flag: stored as sector (N_beta, N_alpha)
+
 // Colexicographic rank of a spin string from T[c][k][byte] tables.
 __device__ inline uint32_t colex_rank(uint32_t s, uint32_t n_orb, uint32_t n_chunks, const uint32_t* tab) {
   uint32_t r = 0, below = 0;
@@ -314,7 +318,9 @@ __device__ inline uint32_t colex_rank(uint32_t s, uint32_t n_orb, uint32_t n_chu
 }
 
 // Full-space index s = alpha | beta << n_orb  <->  sector-block index
-// off[N_alpha][N_beta] + rank(alpha) C(n_orb, N_beta) + rank(beta).
+// off[N_alpha][N_beta] + rank(alpha) C(n_orb, N_beta) + rank(beta), or, for a
+// block flagged transposed (top bit of its offset), + rank(beta) C(n_orb,
+// N_alpha) + rank(alpha): the layout of sector (N_beta, N_alpha).
 template <class T, bool TO_BLOCKS>
 __global__ __launch_bounds__(kBlock) void k_fock_permute(const T* __restrict__ in, T* __restrict__ out, uint64_t dim,
                                                           uint32_t n_orb, uint32_t n_chunks,
@@ -326,9 +332,9 @@ __global__ __launch_bounds__(kBlock) void k_fock_permute(const T* __restrict__ i
        s += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
     const uint32_t a = static_cast<uint32_t>(s) & mask, b = static_cast<uint32_t>(s >> n_orb);
     const uint32_t pa = __popc(a), pb = __popc(b);
-    const uint64_t j = off[pa * (n_orb + 1) + pb] +
-                       static_cast<uint64_t>(colex_rank(a, n_orb, n_chunks, tab)) * binom_n[pb] +
-                       colex_rank(b, n_orb, n_chunks, tab);
+    const uint64_t o = off[pa * (n_orb + 1) + pb];
+    const uint64_t ra = colex_rank(a, n_orb, n_chunks, tab), rb = colex_rank(b, n_orb, n_chunks, tab);
+    const uint64_t j = (o & ~kTransposed) + ((o & kTransposed) ? rb * binom_n[pa] + ra : ra * binom_n[pb] + rb);
     if (TO_BLOCKS)
       out[j] = in[s];
     else
@@ -337,6 +343,47 @@ __global__ __launch_bounds__(kBlock) void k_fock_permute(const T* __restrict__ i
 }
 
 Rot rot_of(uint64_t x, uint64_t z) { return Rot{x, z, static_cast<uint32_t>(__builtin_popcountll(x & z) & 3)}; }
+
+// True when exchanging the two qubit halves maps the operator onto itself
+// term by term (bit-identical coefficients), as for the Jordan-Wigner
+// Hamiltonian of spin-free integrals.  Then H = S H S for the half-exchange
+// S, so block (N_alpha, N_beta) of H psi equals, element for element, block
+// (N_beta, N_alpha) of H (S psi).
+bool halves_symmetric(const pbs_grouped& h, hipStream_t s) {
+  const uint32_t n = h.half;
+  std::vector<uint64_t> xg(h.n_groups), zk(h.n_terms);
+  std::vector<uint32_t> off(h.n_groups + 1);
+  std::vector<double> ck(2 * h.n_terms);
+  PBS_HIP(hipMemcpyAsync(xg.data(), h.xg.get(), xg.size() * 8, hipMemcpyDeviceToHost, s));
+  PBS_HIP(hipMemcpyAsync(off.data(), h.off.get(), off.size() * 4, hipMemcpyDeviceToHost, s));
+  PBS_HIP(hipMemcpyAsync(zk.data(), h.zk.get(), zk.size() * 8, hipMemcpyDeviceToHost, s));
+  PBS_HIP(hipMemcpyAsync(ck.data(), h.ck.get(), ck.size() * 8, hipMemcpyDeviceToHost, s));
+  PBS_HIP(hipStreamSynchronize(s));
+  struct Term {
+    uint64_t x, z, cr, ci;
+    bool operator<(const Term& o) const {
+      return x != o.x ? x < o.x : z != o.z ? z < o.z : cr != o.cr ? cr < o.cr : ci < o.ci;
+    }
+    bool operator==(const Term& o) const { return x == o.x && z == o.z && cr == o.cr && ci == o.ci; }
+  };
+  const uint64_t mask = (1ull << n) - 1ull;
+  auto swap = [&](uint64_t v) { return (v >> n) | ((v & mask) << n); };
+  std::vector<Term> a, b;
+  a.reserve(h.n_terms);
+  b.reserve(h.n_terms);
+  for (uint64_t g = 0; g < h.n_groups; ++g) {
+    for (uint32_t k = off[g]; k < off[g + 1]; ++k) {
+      uint64_t cr, ci;
+      std::memcpy(&cr, &ck[2 * k], 8);
+      std::memcpy(&ci, &ck[2 * k + 1], 8);
+      a.push_back(Term{xg[g], zk[k], cr, ci});
+      b.push_back(Term{swap(xg[g]), swap(zk[k]), cr, ci});
+    }
+  }
+  std::sort(a.begin(), a.end());
+  std::sort(b.begin(), b.end());
+  return a == b;
+}
 
 }  // namespace
 }  // namespace pbs
@@ -357,6 +404,7 @@ struct pbs_vqe {
   DevBuf<double> energies, partial, overlaps;
   uint32_t nparts = 0;
   bool evaluated = false;  // blk_in holds psi(theta) of the last evaluation
+  uint32_t n_transposed = 0;  // blocks stored as sector (N_beta, N_alpha)
   ~pbs_vqe() {
     if (batch) pbs_batch_destroy(batch);
     for (pbs_space* sp : spaces) pbs_space_destroy(sp);
@@ -496,10 +544,14 @@ pbs_status pbs_vqe_create(const pbs_grouped* h, uint32_t n_orb, uint32_t n_rot, 
       v->lam.alloc(dim * esz);
       v->blk_in.alloc(dim * esz);
       v->blk_out.alloc(dim * esz);
-      // sector blocks, alpha-major over (N_alpha, N_beta)
+      // sector blocks, alpha-major over (N_alpha, N_beta).  A block with fewer
+      // beta strings than a workgroup has lanes (and than alpha strings) is
+      // stored and applied as sector (N_beta, N_alpha) when the operator is
+      // symmetric under exchanging the halves, so its rows are long.
       std::vector<uint64_t> off((n_orb + 1) * (n_orb + 1), 0);
       std::vector<uint32_t> bn(n_orb + 1);
       for (uint32_t k = 0; k <= n_orb; ++k) bn[k] = static_cast<uint32_t>(host_binom(n_orb, k));
+      const bool sym = halves_symmetric(*h, s);
       std::vector<const pbs_grouped*> hs;
       std::vector<const pbs_space*> sps;
       std::vector<const void*> ins;
@@ -507,9 +559,11 @@ pbs_status pbs_vqe_create(const pbs_grouped* h, uint32_t n_orb, uint32_t n_rot, 
       uint64_t acc = 0;
       for (uint32_t na = 0; na <= n_orb; ++na) {
         for (uint32_t nb = 0; nb <= n_orb; ++nb) {
-          off[na * (n_orb + 1) + nb] = acc;
+          const bool tr = sym && bn[nb] < static_cast<uint32_t>(kSB) && bn[nb] < bn[na];
+          off[na * (n_orb + 1) + nb] = acc | (tr ? kTransposed : 0ull);
+          v->n_transposed += tr ? 1u : 0u;
           pbs_space* sp = nullptr;
-          const pbs_status st = pbs_space_sector(n_orb, na, nb, stream, &sp);
+          const pbs_status st = pbs_space_sector(n_orb, tr ? nb : na, tr ? na : nb, stream, &sp);
           PBS_REQUIRE(st == PBS_OK, st, std::string("sector space: ") + pbs_last_error());
           v->spaces.push_back(sp);
           hs.push_back(h);
@@ -585,6 +639,14 @@ pbs_status pbs_vqe_minimize(pbs_vqe* v, double* theta, uint32_t max_iter, double
     if (iters) *iters = r.iters;
     if (evals) *evals = r.evals;
     if (reason) *reason = r.reason;
+  });
+}
+
+pbs_status pbs_vqe_info(const pbs_vqe* v, uint32_t* n_blocks, uint32_t* n_transposed) {
+  return guarded([&] {
+    PBS_REQUIRE(v != nullptr, PBS_ERR_ARG, "null pbs_vqe");
+    if (n_blocks) *n_blocks = v->n_jobs;
+    if (n_transposed) *n_transposed = v->n_transposed;
   });
 }
 

@@ -69,6 +69,39 @@ def test_vqe_matches_oracle(dev, dtype, n_orb, n_rot):
     assert abs(g[1]) < tol_g
     e2, _ = v.energy_grad(theta, grad=False)
     assert e2 == e
+    # spin-free integrals: every narrow block is applied transposed
+    from math import comb
+
+    n_blocks, n_tr = v.blocks()
+    assert n_blocks == (n_orb + 1) ** 2
+    assert n_tr == sum(comb(n_orb, b) < comb(n_orb, a) for a in range(n_orb + 1) for b in range(n_orb + 1))
+
+
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+def test_vqe_operator_without_half_exchange_symmetry(dev, dtype):
+    # a spin-dependent one-body shift conserves N_alpha and N_beta but breaks
+    # the alpha <-> beta symmetry, so no block may be transposed
+    api = _api()
+    n_orb, n_rot = 4, 10
+    h1, h2 = synth.molecular_spin_integrals(n_orb, seed=61)
+    h1 = h1.copy()
+    h1[n_orb:, n_orb:] += 0.3 * np.eye(n_orb)
+    G = api.jw_transform(torch.from_numpy(h1).to(dev), torch.from_numpy(h2).to(dev)).group()
+    op = ojw.jw_sum(h1, h2)
+    rng = np.random.default_rng(62)
+    rots = [rng.integers(0, 4, 2 * n_orb).astype(np.uint8) for _ in range(n_rot)]
+    xz = [opauli.letters_to_xz(r) for r in rots]
+    x = np.array([int(np.asarray(a).reshape(-1)[0]) for a, _ in xz], np.uint64)
+    z = np.array([int(np.asarray(b).reshape(-1)[0]) for _, b in xz], np.uint64)
+    ref = 0b0011 | (0b0001 << n_orb)
+    theta = rng.normal(size=n_rot) * 0.5
+    v = api.VQE(G, n_orb, x, z, ref, dtype=dtype)
+    assert v.blocks() == ((n_orb + 1) ** 2, 0)
+    e, g = v.energy_grad(theta)
+    scale = float(np.abs(op.coeff).sum())
+    tol_e, tol_g = (1e-12 * scale, 1e-11 * scale) if dtype == torch.complex128 else (2e-6 * scale, 4e-6 * scale)
+    assert abs(e - ovqe.energy(op, rots, theta, ref)) < tol_e
+    assert np.abs(g - ovqe.gradient(op, rots, theta, ref)).max() < tol_g
 
 
 def test_vqe_without_rotations_is_reference_energy(dev):
