@@ -221,10 +221,12 @@ def bench_krylov(args):
         energies, norms = [], []
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(args.krylov_steps):
+        for k in range(args.krylov_steps):
             info = prop.step(psi, 0.05)
             norms.append(info[0])
             energies.append(info[1])
+            if (k + 1) % 25 == 0:
+                print(f"[krylov {name}] {k + 1}/{args.krylov_steps} steps", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         dt_total = time.perf_counter() - t0
         res[name] = {"seconds": dt_total, "ms_per_step": dt_total * 1e3 / args.krylov_steps,
