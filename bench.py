@@ -159,14 +159,20 @@ def bench_batched(args):
         work += sp.dim * H.n_terms
     batch = api.Batch(jobs32)
     energies = torch.zeros(3 * len(jobs32), dtype=torch.float64, device=dev)
-    for _ in range(args.warmup):
-        batch.run(energies)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        batch.run(energies)
-    torch.cuda.synchronize()
-    t_batch = (time.perf_counter() - t0) / args.steps
+
+    def time_batch():
+        for _ in range(args.warmup):
+            batch.run(energies)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            batch.run(energies)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / args.steps
+
+    t_default = time_batch()
+    tuned_config, tuned_ms = batch.tune(reps=3)
+    t_batch = time_batch()
 
     def per_job():
         for G, sp, psi, out in jobs64:
@@ -192,6 +198,8 @@ def bench_batched(args):
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "batched-64", "jobs": len(jobs32), "amplitude_terms": work,
                    "dims": [j[1].dim for j in jobs32]},
+        "ms_default_schedule": t_default * 1e3, "tuned_schedule": tuned_config,
+        "tuner_ms_per_run": tuned_ms, "workgroups": batch.info()[2],
         "ms_per_job_fp64_launches": t_single * 1e3,
         "speedup_batched_c64_vs_per_job_fp64": t_single / t_batch,
         "max_rel_err_c64_vs_fp64_same_input": worst,

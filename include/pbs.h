@@ -244,6 +244,27 @@ pbs_status pbs_batch_create(uint32_t n, const pbs_grouped* const* h, const pbs_s
  * batch must not overlap in time (they share the partial-sum buffer). */
 pbs_status pbs_batch_run(const pbs_batch* b, double* energies, void* stream);
 
+/* Schedule of a batched launch: bits of `config` (0 = the default schedule).
+ * Every schedule computes the same products and energies. */
+#define PBS_BATCH_GIVEN_ORDER 1u       /* jobs in the caller's order (default: largest first) */
+#define PBS_BATCH_NO_ROW_STAGING 2u    /* gather source rows from HBM/L2 instead of staging them in LDS */
+#define PBS_BATCH_NO_DOUBLE_MOVES 4u   /* scan double-flip groups instead of enumerating double moves */
+#define PBS_BATCH_NO_SINGLE_MOVES 8u   /* scan pair groups instead of enumerating single moves */
+
+/* Rebuilds the batch's job table for schedule `config` (0..15).  Synchronizes. */
+pbs_status pbs_batch_set_config(pbs_batch* b, uint32_t config);
+
+/* Autotuner: times every distinct schedule (a warm-up run, then `reps` runs,
+ * 1..100, with HIP events on the stream), keeps the fastest, and returns it
+ * in *config and its time per run in *ms (either may be NULL).  Runs the
+ * batch, so the output buffers are overwritten.  Call it before capturing
+ * pbs_batch_run in a graph: it rebuilds the job table.  Synchronizes. */
+pbs_status pbs_batch_tune(pbs_batch* b, uint32_t reps, void* stream, uint32_t* config, double* ms);
+
+/* Schedule in use, its tuned time per run (-1 when not chosen by the tuner)
+ * and the number of workgroups of one launch.  Any output may be NULL. */
+pbs_status pbs_batch_info(const pbs_batch* b, uint32_t* config, double* tuned_ms, uint32_t* workgroups);
+
 void pbs_batch_destroy(pbs_batch* b);
 
 /* ------------------------------------------------------------------ propagation */

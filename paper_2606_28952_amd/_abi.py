@@ -46,6 +46,9 @@ SIGNATURES = {
     "pbs_expval": (c_int32, [_vp, _vp, c_int32, _vp, _vp, _vp, _vp, c_uint64, _vp]),
     "pbs_batch_create": (c_int32, [c_uint32, _vp, _vp, c_int32, _vp, _vp, POINTER(_vp)]),
     "pbs_batch_run": (c_int32, [_vp, _vp, _vp]),
+    "pbs_batch_set_config": (c_int32, [_vp, c_uint32]),
+    "pbs_batch_tune": (c_int32, [_vp, c_uint32, _vp, POINTER(c_uint32), POINTER(c_double)]),
+    "pbs_batch_info": (c_int32, [_vp, POINTER(c_uint32), POINTER(c_double), POINTER(c_uint32)]),
     "pbs_batch_destroy": (None, [_vp]),
     "pbs_krylov_workspace_bytes": (c_int32, [_vp, c_int32, c_uint32, POINTER(c_uint64)]),
     "pbs_krylov_step": (c_int32, [_vp, _vp, c_int32, _vp, c_double, c_uint32, _vp, c_uint64, _vp, _vp]),

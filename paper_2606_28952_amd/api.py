@@ -310,6 +310,23 @@ class Batch:
         call("pbs_batch_run", self._h, _ptr(energies), _stream())
         return energies
 
+    def set_config(self, config):
+        """Job table for schedule bits ``config`` (PBS_BATCH_* in include/pbs.h)."""
+        call("pbs_batch_set_config", self._h, int(config))
+
+    def tune(self, reps=3):
+        """Times every distinct schedule, keeps the fastest; returns (config, ms).
+        Overwrites the outputs."""
+        c, ms = c_uint32(), ctypes.c_double()
+        call("pbs_batch_tune", self._h, int(reps), _stream(), byref(c), byref(ms))
+        return c.value, ms.value
+
+    def info(self):
+        """(schedule bits in use, tuned ms per run or -1, workgroups per launch)."""
+        c, ms, wg = c_uint32(), ctypes.c_double(), c_uint32()
+        call("pbs_batch_info", self._h, byref(c), byref(ms), byref(wg))
+        return c.value, ms.value, wg.value
+
     def __del__(self):
         h = getattr(self, "_h", None)
         if h is not None and h.value and _abi is not None and _abi._LIB is not None:

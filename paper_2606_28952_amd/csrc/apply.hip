@@ -103,7 +103,7 @@ int device_lds_limit() {
 // uniques get what is left of half the device's LDS, so that two workgroups
 // share a compute unit, unless the fixed parts alone need more.
 Launch plan_sector(const pbs_grouped& h, const pbs_space& sp, size_t elem_bytes, bool allow_row, bool realc,
-                   SectorArgs* a_out, bool* r16) {
+                   SectorArgs* a_out, bool* r16, bool allow_enum = true, bool allow_qenum = true) {
   SectorArgs a{};
   a.n_orb = sp.n_orb;
   a.n_alpha = sp.n_alpha;
@@ -140,14 +140,14 @@ Launch plan_sector(const pbs_grouped& h, const pbs_space& sp, size_t elem_bytes,
   const uint32_t rank_bytes = *r16 ? align16(kRank16Lds * 2u) : 0u;
   const uint32_t per_unique = (realc ? 8u : 16u) + 4u;
   const uint32_t f_min = (kFCapMin + kZeroSlots) * per_unique + 64u;
-  a.enum_ok = (h.n_pmap > 0 && a.n_moves <= static_cast<uint32_t>(kMaxMoves) && sp.dim_beta < 65536 &&
+  a.enum_ok = (allow_enum && h.n_pmap > 0 && a.n_moves <= static_cast<uint32_t>(kMaxMoves) && sp.dim_beta < 65536 &&
                h.n_pairs < 65536)
                   ? 1u
                   : 0u;
   const uint32_t pu_bytes = kMiscBytes + kPuBytes;  // fixed: scratch and pair map (n_pairs + 1 <= 512 words)
   PBS_REQUIRE(h.n_pairs + 1 <= kPuBytes / 4, PBS_ERR_RANGE, "too many orbital pairs for the pair map");
   const uint64_t n_ep = host_binom(sp.n_orb - sp.n_beta, 2), n_op = host_binom(sp.n_beta, 2);
-  a.qenum_ok = (*r16 && a.enum_ok && h.n_qmap > 0 && h.n_quads > 0 && n_op * n_ep > 0) ? 1u : 0u;
+  a.qenum_ok = (allow_qenum && *r16 && a.enum_ok && h.n_qmap > 0 && h.n_quads > 0 && n_op * n_ep > 0) ? 1u : 0u;
   a.n_quads = h.n_quads;
   a.n_qmoves = static_cast<uint32_t>(n_op * n_ep);
   const uint64_t row_bytes = sp.dim_beta * elem_bytes;
@@ -308,9 +308,102 @@ struct pbs_batch {
   pbs_dtype dt = PBS_C64;
   bool r16 = false, row_lds = false, realc = false;
   size_t lds = 0;
+  uint32_t config = 0;     // schedule in use (PBS_BATCH_* bits)
+  double tuned_ms = -1.0;  // time of that schedule when chosen by pbs_batch_tune
+  std::vector<const pbs_grouped*> h;
+  std::vector<const pbs_space*> sp;
+  std::vector<const void*> psi;
+  std::vector<void*> out;
   pbs::DevBuf<pbs::BatchJob> jobs;
   pbs::DevBuf<double> partial;
 };
+
+namespace pbs {
+namespace {
+
+constexpr uint32_t kBatchConfigs = 16;  // every combination of the four PBS_BATCH_* bits
+
+// Builds and uploads the job table of batch B for schedule `config`:
+// PBS_BATCH_GIVEN_ORDER keeps the caller's job order (else largest first),
+// PBS_BATCH_NO_ROW_STAGING gathers source rows from HBM/L2 instead of staging
+// them in LDS, PBS_BATCH_NO_DOUBLE_MOVES scans double-flip groups instead of
+// enumerating each target's double moves, PBS_BATCH_NO_SINGLE_MOVES scans
+// pair groups instead of enumerating single moves.  Synchronizes (plain copy).
+void fill_batch(pbs_batch& B, uint32_t config) {
+  const uint32_t n = B.n_jobs;
+  const size_t esz = B.dt == PBS_C128 ? 16 : 8;
+  const bool given = config & PBS_BATCH_GIVEN_ORDER, allow_row = !(config & PBS_BATCH_NO_ROW_STAGING);
+  const bool qenum = !(config & PBS_BATCH_NO_DOUBLE_MOVES), penum = !(config & PBS_BATCH_NO_SINGLE_MOVES);
+  std::vector<BatchJob> jobs(n);
+  std::vector<double> cost(n);
+  std::vector<uint32_t> order(n);
+  // one launch shares one kernel variant: rows staged only if every job's
+  // row fits, LDS rank tables only if every job has n_orb <= 16
+  bool r16 = true, rowlds = allow_row, realc = true;
+  for (uint32_t i = 0; i < n; ++i) realc = realc && B.h[i]->real_coef;
+  for (uint32_t i = 0; i < n; ++i) {
+    bool job_r16 = false;
+    plan_sector(*B.h[i], *B.sp[i], esz, allow_row, realc, &jobs[i].args, &job_r16, penum, qenum);
+    r16 = r16 && job_r16;
+    rowlds = rowlds && jobs[i].args.row_lds;
+  }
+  size_t lds = 0;
+  for (uint32_t i = 0; i < n; ++i) {
+    bool job_r16 = false;
+    const Launch L = plan_sector(*B.h[i], *B.sp[i], esz, rowlds, realc, &jobs[i].args, &job_r16, penum, qenum);
+    if (!r16) jobs[i].args.rank16 = nullptr;
+    jobs[i].psi = B.psi[i];
+    jobs[i].out = B.out[i];
+    jobs[i].chunks = L.chunks;
+    jobs[i].block_base = 0;
+    jobs[i].pad = i;  // original position (energies are written there)
+    lds = std::max(lds, L.lds);
+    cost[i] = static_cast<double>(B.sp[i]->dim) * static_cast<double>(B.h[i]->n_pterm + 1);
+    order[i] = i;
+  }
+  // largest jobs first, so the launch does not end on a long straggler
+  if (!given) std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return cost[a] > cost[b]; });
+  std::vector<BatchJob> sorted(n);
+  uint64_t base = 0;
+  for (uint32_t k = 0; k < n; ++k) {
+    BatchJob J = jobs[order[k]];
+    J.block_base = static_cast<uint32_t>(base);
+    base += static_cast<uint64_t>(B.sp[order[k]]->dim_alpha) * J.chunks;
+    sorted[k] = J;
+  }
+  PBS_REQUIRE(base < (1ull << 31), PBS_ERR_RANGE, "batch needs more than 2^31 workgroups");
+  if (lds > 64 * 1024) {
+    for (bool ev : {false, true})
+      PBS_HIP(hipFuncSetAttribute(sector_kernel(B.dt, ev, true, r16, rowlds, realc),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
+  }
+  if (B.partial.n < 3ull * base) B.partial.alloc(3ull * base);
+  if (B.jobs.n < n) B.jobs.alloc(n);
+  PBS_HIP(hipMemcpy(B.jobs.get(), sorted.data(), n * sizeof(BatchJob), hipMemcpyHostToDevice));
+  B.total_blocks = static_cast<uint32_t>(base);
+  B.r16 = r16;
+  B.row_lds = rowlds;
+  B.realc = realc;
+  B.lds = lds;
+  B.config = config;
+}
+
+void launch_batch(const pbs_batch& b, double* energies, hipStream_t s) {
+  const bool ev = energies != nullptr;
+  void* kern = sector_kernel(b.dt, ev, true, b.r16, b.row_lds, b.realc);
+  const BatchJob* jobs = b.jobs.get();
+  uint32_t n = b.n_jobs;
+  double* partial = b.partial.get();
+  void* args[] = {&jobs, &n, &partial};
+  PBS_HIP(hipLaunchKernel(kern, dim3(b.total_blocks), dim3(kSB), args, b.lds, s));
+  if (ev) {
+    hipLaunchKernelGGL(k_batch_finish, dim3(n), dim3(kBlock), 0, s, jobs, n, b.total_blocks, partial, energies);
+    PBS_HIP(hipGetLastError());
+  }
+}
+
+}  // namespace
+}  // namespace pbs
 
 extern "C" {
 
@@ -321,9 +414,6 @@ pbs_status pbs_batch_create(uint32_t n, const pbs_grouped* const* h, const pbs_s
     *batch = nullptr;
     PBS_REQUIRE(n >= 1 && h && sp && psi && out, PBS_ERR_ARG, "empty batch or null array");
     const size_t esz = dt == PBS_C128 ? 16 : 8;
-    std::vector<BatchJob> jobs(n);
-    std::vector<double> cost(n);
-    std::vector<uint32_t> order(n);
     for (uint32_t i = 0; i < n; ++i) {
       validate(h[i], sp[i], dt);
       PBS_REQUIRE(sp[i]->sector, PBS_ERR_UNSUPPORTED, "batched apply runs on spin-sector spaces");
@@ -340,58 +430,15 @@ pbs_status pbs_batch_create(uint32_t n, const pbs_grouped* const* h, const pbs_s
         PBS_REQUIRE(x + bi <= y || y + bj <= x, PBS_ERR_ARG, "outputs of jobs overlap");
       }
     }
-    // one launch shares one kernel variant: rows staged only if every job's
-    // row fits, LDS rank tables only if every job has n_orb <= 16
-    bool r16 = true, rowlds = true, realc = true;
-    for (uint32_t i = 0; i < n; ++i) realc = realc && h[i]->real_coef;
-    for (uint32_t i = 0; i < n; ++i) {
-      bool job_r16 = false;
-      plan_sector(*h[i], *sp[i], esz, true, realc, &jobs[i].args, &job_r16);
-      r16 = r16 && job_r16;
-      rowlds = rowlds && jobs[i].args.row_lds;
-    }
-    size_t lds = 0;
-    for (uint32_t i = 0; i < n; ++i) {
-      bool job_r16 = false;
-      const Launch L = plan_sector(*h[i], *sp[i], esz, rowlds, realc, &jobs[i].args, &job_r16);
-      if (!r16) jobs[i].args.rank16 = nullptr;
-      jobs[i].psi = psi[i];
-      jobs[i].out = out[i];
-      jobs[i].chunks = L.chunks;
-      jobs[i].block_base = 0;
-      jobs[i].pad = i;  // original position (energies are written there)
-      lds = std::max(lds, L.lds);
-      cost[i] = static_cast<double>(sp[i]->dim) * static_cast<double>(h[i]->n_pterm + 1);
-      order[i] = i;
-    }
-    // largest jobs first, so the launch does not end on a long straggler
-    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return cost[a] > cost[b]; });
-    std::vector<BatchJob> sorted(n);
-    uint64_t base = 0;
-    for (uint32_t k = 0; k < n; ++k) {
-      BatchJob J = jobs[order[k]];
-      J.block_base = static_cast<uint32_t>(base);
-      base += static_cast<uint64_t>(sp[order[k]]->dim_alpha) * J.chunks;
-      sorted[k] = J;
-    }
-    PBS_REQUIRE(base < (1ull << 31), PBS_ERR_RANGE, "batch needs more than 2^31 workgroups");
     auto* B = new pbs_batch();
     try {
       B->n_jobs = n;
-      B->total_blocks = static_cast<uint32_t>(base);
       B->dt = dt;
-      B->r16 = r16;
-      B->row_lds = rowlds;
-      B->realc = realc;
-      B->lds = lds;
-      B->jobs.alloc(n);
-      B->partial.alloc(3ull * base);
-      PBS_HIP(hipMemcpy(B->jobs.get(), sorted.data(), n * sizeof(BatchJob), hipMemcpyHostToDevice));
-      if (lds > 64 * 1024) {
-        for (bool ev : {false, true})
-          PBS_HIP(hipFuncSetAttribute(sector_kernel(dt, ev, true, r16, rowlds, realc),
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
-      }
+      B->h.assign(h, h + n);
+      B->sp.assign(sp, sp + n);
+      B->psi.assign(psi, psi + n);
+      B->out.assign(out, out + n);
+      fill_batch(*B, 0u);
     } catch (...) {
       delete B;
       throw;
@@ -400,21 +447,77 @@ pbs_status pbs_batch_create(uint32_t n, const pbs_grouped* const* h, const pbs_s
   });
 }
 
+pbs_status pbs_batch_set_config(pbs_batch* b, uint32_t config) {
+  return guarded([&] {
+    PBS_REQUIRE(b != nullptr, PBS_ERR_ARG, "null pbs_batch");
+    PBS_REQUIRE(config < kBatchConfigs, PBS_ERR_ARG, "unknown schedule bits");
+    fill_batch(*b, config);
+    b->tuned_ms = -1.0;
+  });
+}
+
+pbs_status pbs_batch_tune(pbs_batch* b, uint32_t reps, void* stream, uint32_t* config, double* ms) {
+  return guarded([&] {
+    PBS_REQUIRE(b != nullptr, PBS_ERR_ARG, "null pbs_batch");
+    PBS_REQUIRE(reps >= 1 && reps <= 100, PBS_ERR_RANGE, "reps must be in 1..100");
+    hipStream_t s = as_stream(stream);
+    hipEvent_t e0, e1;
+    PBS_HIP(hipEventCreate(&e0));
+    PBS_HIP(hipEventCreate(&e1));
+    uint32_t best = 0;
+    double best_ms = 0.0;
+    std::vector<std::string> seen;  // schedules that produce the same job table are timed once
+    try {
+      for (uint32_t c = 0; c < kBatchConfigs; ++c) {
+        fill_batch(*b, c);
+        std::string key(reinterpret_cast<const char*>(&b->row_lds), 1);
+        {
+          std::vector<BatchJob> table(b->n_jobs);
+          PBS_HIP(hipMemcpy(table.data(), b->jobs.get(), b->n_jobs * sizeof(BatchJob), hipMemcpyDeviceToHost));
+          key.append(reinterpret_cast<const char*>(table.data()), table.size() * sizeof(BatchJob));
+        }
+        if (std::find(seen.begin(), seen.end(), key) != seen.end()) continue;
+        seen.push_back(std::move(key));
+        launch_batch(*b, nullptr, s);  // warm-up
+        PBS_HIP(hipEventRecord(e0, s));
+        for (uint32_t r = 0; r < reps; ++r) launch_batch(*b, nullptr, s);
+        PBS_HIP(hipEventRecord(e1, s));
+        PBS_HIP(hipEventSynchronize(e1));
+        float t = 0.f;
+        PBS_HIP(hipEventElapsedTime(&t, e0, e1));
+        const double per = static_cast<double>(t) / reps;
+        if (seen.size() == 1 || per < best_ms) {
+          best = c;
+          best_ms = per;
+        }
+      }
+      fill_batch(*b, best);
+      b->tuned_ms = best_ms;
+    } catch (...) {
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      throw;
+    }
+    PBS_HIP(hipEventDestroy(e0));
+    PBS_HIP(hipEventDestroy(e1));
+    if (config) *config = best;
+    if (ms) *ms = best_ms;
+  });
+}
+
+pbs_status pbs_batch_info(const pbs_batch* b, uint32_t* config, double* tuned_ms, uint32_t* workgroups) {
+  return guarded([&] {
+    PBS_REQUIRE(b != nullptr, PBS_ERR_ARG, "null pbs_batch");
+    if (config) *config = b->config;
+    if (tuned_ms) *tuned_ms = b->tuned_ms;
+    if (workgroups) *workgroups = b->total_blocks;
+  });
+}
+
 pbs_status pbs_batch_run(const pbs_batch* b, double* energies, void* stream) {
   return guarded([&] {
     PBS_REQUIRE(b != nullptr, PBS_ERR_ARG, "null pbs_batch");
-    hipStream_t s = as_stream(stream);
-    const bool ev = energies != nullptr;
-    void* kern = sector_kernel(b->dt, ev, true, b->r16, b->row_lds, b->realc);
-    const BatchJob* jobs = b->jobs.get();
-    uint32_t n = b->n_jobs;
-    double* partial = b->partial.get();
-    void* args[] = {&jobs, &n, &partial};
-    PBS_HIP(hipLaunchKernel(kern, dim3(b->total_blocks), dim3(kSB), args, b->lds, s));
-    if (ev) {
-      hipLaunchKernelGGL(k_batch_finish, dim3(n), dim3(kBlock), 0, s, jobs, n, b->total_blocks, partial, energies);
-      PBS_HIP(hipGetLastError());
-    }
+    launch_batch(*b, energies, as_stream(stream));
   });
 }
 

@@ -114,3 +114,51 @@ def test_batch_rejects_bad_jobs(dev):
         api.Batch([(Gf, api.Space.full(6), x, torch.zeros_like(x))])
     with pytest.raises(TypeError):
         api.Batch([(G, sp, psi, out), (G, sp, psi.to(torch.complex64), out.to(torch.complex64))])
+
+
+def _oracle_refs(refs):
+    out = []
+    for h1, h2, n_o, na, nb, psi_np in refs:
+        ref = oapply.apply_scatter(ojw.jw_sum(h1, h2), ospace.SectorSpace(n_o, na, nb), psi_np)
+        out.append((ref, np.vdot(psi_np, ref).real))
+    return out
+
+
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+def test_every_schedule_matches_oracle(dev, dtype):
+    api = _api()
+    jobs, refs = _build(dev, dtype)
+    want = _oracle_refs(refs)
+    batch = api.Batch(jobs)
+    tol = 1e-12 if dtype == torch.complex128 else 1e-6
+    energies = torch.zeros(3 * len(jobs), dtype=torch.float64, device=dev)
+    for config in range(16):
+        batch.set_config(config)
+        assert batch.info()[0] == config and batch.info()[1] == -1.0
+        for _, _, _, out in jobs:
+            out.zero_()
+        batch.run(energies)
+        torch.cuda.synchronize()
+        e = energies.cpu().numpy().reshape(-1, 3)
+        for k, ((_, _, _, out), (ref, e_ref)) in enumerate(zip(jobs, want)):
+            assert rel_err(out.cpu().numpy(), ref) < tol, (config, k)
+            assert abs(e[k, 0] - e_ref) < 1e-11 * max(1.0, abs(e_ref)), (config, k)
+
+
+def test_tuner_keeps_the_fastest_schedule(dev):
+    api = _api()
+    jobs, refs = _build(dev, torch.complex64)
+    want = _oracle_refs(refs)
+    batch = api.Batch(jobs)
+    wg0 = batch.info()[2]
+    config, ms = batch.tune(reps=2)
+    assert 0 <= config < 16 and ms > 0.0
+    assert batch.info() == (config, ms, wg0)  # the workgroup count does not depend on the schedule
+    for _, _, _, out in jobs:
+        out.zero_()
+    batch.run()
+    torch.cuda.synchronize()
+    for (_, _, _, out), (ref, _) in zip(jobs, want):
+        assert rel_err(out.cpu().numpy(), ref) < 1e-6
+    with pytest.raises(Exception, match="schedule"):
+        batch.set_config(16)
