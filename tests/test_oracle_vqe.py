@@ -72,3 +72,17 @@ def test_reference_energy_is_diagonal_element():
     psi = ovqe.ansatz_state(rots, theta, ref, op.n_qubits)
     assert abs(np.vdot(psi, psi).real - 1.0) < 1e-13
     assert abs(ovqe.energy(op, rots, theta, ref) - np.vdot(psi, H @ psi).real) < 1e-12
+
+
+def test_sparse_route_matches_dense_route():
+    op, rots, ref, theta = _small_problem(n_o=3, seed=8, n_rot=4)
+    dense = ovqe.ansatz_state(rots, theta, ref, op.n_qubits)
+    sparse = ovqe.sparse_state(rots, theta, ref)
+    assert len(sparse) <= 2 ** len(rots)
+    emb = np.zeros_like(dense)
+    for s, a in sparse.items():
+        emb[s] += a
+    np.testing.assert_allclose(emb, dense, atol=1e-14)
+    assert abs(ovqe.sparse_energy(op, rots, theta, ref) - ovqe.energy(op, rots, theta, ref)) < 1e-12
+    np.testing.assert_allclose(ovqe.sparse_gradient(op, rots, theta, ref), ovqe.gradient(op, rots, theta, ref),
+                               atol=1e-12)
