@@ -329,6 +329,13 @@ pbs_status pbs_vqe_state(const pbs_vqe* v, void* psi_out, void* stream);
 pbs_status pbs_vqe_minimize(pbs_vqe* v, double* theta, uint32_t max_iter, double g_tol, double f_tol, void* stream,
                             double* energy, uint32_t* iters, uint32_t* evals, int32_t* reason);
 
+/* Runs pbs_batch_tune on the handle's batched launch over the sector blocks
+ * (after at least one evaluation) and keeps the fastest schedule; *config and
+ * *ms as there.  pbs_vqe_set_config applies a known schedule (for example
+ * one tuned at another geometry of the same shape).  Both synchronize. */
+pbs_status pbs_vqe_tune(pbs_vqe* v, uint32_t reps, void* stream, uint32_t* config, double* ms);
+pbs_status pbs_vqe_set_config(pbs_vqe* v, uint32_t config);
+
 /* Number of (N_alpha, N_beta) blocks of the handle, and how many of them are
  * stored and applied as sector (N_beta, N_alpha): blocks with fewer beta than
  * alpha strings and fewer than 512 beta strings, when the operator maps onto

@@ -57,6 +57,8 @@ SIGNATURES = {
     "pbs_vqe_state": (c_int32, [_vp, _vp, _vp]),
     "pbs_vqe_minimize": (c_int32, [_vp, _vp, c_uint32, c_double, c_double, _vp, POINTER(c_double),
                                    POINTER(c_uint32), POINTER(c_uint32), POINTER(c_int32)]),
+    "pbs_vqe_tune": (c_int32, [_vp, c_uint32, _vp, POINTER(c_uint32), POINTER(c_double)]),
+    "pbs_vqe_set_config": (c_int32, [_vp, c_uint32]),
     "pbs_vqe_info": (c_int32, [_vp, POINTER(c_uint32), POINTER(c_uint32)]),
     "pbs_vqe_destroy": (None, [_vp]),
     "pbs_lbfgs_minimize": (c_int32, [c_uint32, _vp, _vp, _vp, c_uint32, c_uint32, c_double, c_double,

@@ -376,6 +376,15 @@ class VQE:
              byref(e), byref(it), byref(ev), byref(why))
         return th, e.value, it.value, ev.value, STOP_REASONS[why.value]
 
+    def tune(self, reps=3):
+        """Autotunes the batched sector launch (after an evaluation); (config, ms)."""
+        c, ms = c_uint32(), ctypes.c_double()
+        call("pbs_vqe_tune", self._h, int(reps), _stream(), byref(c), byref(ms))
+        return c.value, ms.value
+
+    def set_config(self, config):
+        call("pbs_vqe_set_config", self._h, int(config))
+
     def blocks(self):
         """(sector blocks, blocks stored as sector (N_beta, N_alpha))."""
         nb, nt = c_uint32(), c_uint32()

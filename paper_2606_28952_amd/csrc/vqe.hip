@@ -642,6 +642,23 @@ pbs_status pbs_vqe_minimize(pbs_vqe* v, double* theta, uint32_t max_iter, double
   });
 }
 
+pbs_status pbs_vqe_tune(pbs_vqe* v, uint32_t reps, void* stream, uint32_t* config, double* ms) {
+  return guarded([&] {
+    PBS_REQUIRE(v != nullptr, PBS_ERR_ARG, "null pbs_vqe");
+    PBS_REQUIRE(v->evaluated, PBS_ERR_ARG, "tune after the first evaluation (the blocks hold a state then)");
+    const pbs_status st = pbs_batch_tune(v->batch, reps, stream, config, ms);
+    PBS_REQUIRE(st == PBS_OK, st, std::string("batch tuning: ") + pbs_last_error());
+  });
+}
+
+pbs_status pbs_vqe_set_config(pbs_vqe* v, uint32_t config) {
+  return guarded([&] {
+    PBS_REQUIRE(v != nullptr, PBS_ERR_ARG, "null pbs_vqe");
+    const pbs_status st = pbs_batch_set_config(v->batch, config);
+    PBS_REQUIRE(st == PBS_OK, st, std::string("batch schedule: ") + pbs_last_error());
+  });
+}
+
 pbs_status pbs_vqe_info(const pbs_vqe* v, uint32_t* n_blocks, uint32_t* n_transposed) {
   return guarded([&] {
     PBS_REQUIRE(v != nullptr, PBS_ERR_ARG, "null pbs_vqe");

@@ -164,3 +164,21 @@ def test_vqe_28_qubit_full_space_against_sparse_oracle(dev, dtype, molecular_28q
     assert np.abs(got - np.array([want[s] for s in sorted(want)])).max() < tol_a
     # unit norm with these amplitudes in place leaves nothing elsewhere
     assert abs(torch.linalg.vector_norm(psi.to(torch.complex128)).item() - 1.0) < (1e-13 if tol_a < 1e-9 else 1e-6)
+
+
+def test_vqe_schedule_tuning_keeps_results(dev):
+    api = _api()
+    G, op, rots, x, z, ref, theta = _problem(dev, 4, 10, seed=71)
+    v = api.VQE(G, 4, x, z, ref)
+    with pytest.raises(Exception, match="first evaluation"):
+        v.tune(1)
+    e0, g0 = v.energy_grad(theta)
+    config, ms = v.tune(2)
+    assert 0 <= config < 16 and ms > 0.0
+    e1, g1 = v.energy_grad(theta)
+    scale = float(np.abs(op.coeff).sum())
+    assert abs(e1 - e0) < 1e-12 * scale and np.abs(g1 - g0).max() < 1e-11 * scale
+    for c in (0, 6, 15):
+        v.set_config(c)
+        e2, g2 = v.energy_grad(theta)
+        assert abs(e2 - e0) < 1e-12 * scale and np.abs(g2 - g0).max() < 1e-11 * scale
