@@ -59,10 +59,12 @@ def _source_hash():
     return h.hexdigest()[:16]
 
 
-def _connected_groups(x_groups, n_orb, n_alpha, n_beta):
+def _connected_groups(x_groups, n_orb, n_alpha, n_beta, weights=None):
     """Average number of groups whose source lies in the sector, per target:
     a group with masks (X_alpha, X_beta) connects a target iff each half flips
-    as many occupied as empty orbitals; counted exactly by combinatorics."""
+    as many occupied as empty orbitals; counted exactly by combinatorics.
+    With ``weights`` (one per group, e.g. its number of strings) the average
+    of the connected groups' weights summed per target."""
     from math import comb as _comb
 
     def comb(n, k):
@@ -71,7 +73,8 @@ def _connected_groups(x_groups, n_orb, n_alpha, n_beta):
     mask = (1 << n_orb) - 1
     total = 0
     da, db = comb(n_orb, n_alpha), comb(n_orb, n_beta)
-    for x in x_groups.tolist():
+    w = [1] * len(x_groups) if weights is None else [int(v) for v in weights]
+    for x, wg in zip(x_groups.tolist(), w):
         xa, xb = x & mask, x >> n_orb
         pa, pb = bin(xa).count("1"), bin(xb).count("1")
         if pa % 2 or pb % 2:
@@ -79,7 +82,7 @@ def _connected_groups(x_groups, n_orb, n_alpha, n_beta):
         # targets whose alpha string has exactly pa/2 ones inside xa
         ca = comb(pa, pa // 2) * comb(n_orb - pa, n_alpha - pa // 2)
         cb = comb(pb, pb // 2) * comb(n_orb - pb, n_beta - pb // 2)
-        total += ca * cb
+        total += ca * cb * wg
     return total / (da * db)
 
 
@@ -397,8 +400,9 @@ def main():
     work = torch.empty(max(1, sp.workspace_bytes() // 8), dtype=torch.float64, device=dev)
     D = sp.dim
     M = H.n_terms
-    xg = G.read()[0]
+    xg, goff = G.read()[:2]
     g_conn = _connected_groups(xg, n_orb, na, nb)
+    t_conn = _connected_groups(xg, n_orb, na, nb, weights=np.diff(goff.astype(np.int64)))
     del H, G, sp
 
     def step(ev0=None, ev1=None):
@@ -471,13 +475,15 @@ def main():
         "dtype": "f64",
         "data": "synthetic (seeded Gaussian integrals and states)",
         "config": {"workload": args.workload, "n_orb": n_orb, "n_alpha": na, "n_beta": nb, "dim": D,
-                   "n_strings": M, "groups_connected_per_target": round(g_conn, 3), "storage": "complex64",
+                   "n_strings": M, "groups_connected_per_target": round(g_conn, 3),
+                   "strings_connected_per_target": round(t_conn, 3), "storage": "complex64",
                    "step": "jw_transform+group_by_xmask+space_sector+fused(apply_pauli_sum+expval)"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
         "apply_ms_c64": c64_ms,
         "apply_ms_c128": c128_ms,
         "apply_rate_c64": D * M / (c64_ms * 1e-3),
+        "apply_connected_rate_c64": D * t_conn / (c64_ms * 1e-3),
         "apply_rate_c128": D * M / (c128_ms * 1e-3),
         "speedup_c64_vs_c128": c128_ms / c64_ms,
         "rel_err_c64_vs_c128_same_input": err_kernel,
