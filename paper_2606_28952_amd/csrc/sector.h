@@ -446,8 +446,24 @@ __device__ __forceinline__ void sector_body(const SectorArgs& P, const T* __rest
   const uint32_t f_cap = P.f_cap;
 
   if (R16) {
-    for (uint32_t i = threadIdx.x; i < kRank16Lds; i += kSB)
-      s_rank[i] = i < 256u ? P.rank16[i] : (P.n_chunks > 1 ? P.rank16[(P.n_orb + 1) * 256u + (i - 256u)] : 0);
+    // 256 entries of chunk 0 (no ones below), then the chunk-1 entries for 0..8
+    // ones below (zeros for a single chunk), copied as 32-bit words with every
+    // load issued before the first LDS store
+    constexpr uint32_t kWords = kRank16Lds / 2u, kIters = (kWords + kSB - 1u) / kSB;
+    const uint32_t* r0 = reinterpret_cast<const uint32_t*>(P.rank16);
+    const uint32_t* r1 = reinterpret_cast<const uint32_t*>(P.rank16 + (P.n_orb + 1) * 256u);
+    uint32_t* s_rank32 = reinterpret_cast<uint32_t*>(s_rank);
+    uint32_t v[kIters];
+#pragma unroll
+    for (uint32_t k = 0; k < kIters; ++k) {
+      const uint32_t w = threadIdx.x + k * kSB;
+      v[k] = w < 128u ? r0[w] : (w < kWords && P.n_chunks > 1 ? r1[w - 128u] : 0u);
+    }
+#pragma unroll
+    for (uint32_t k = 0; k < kIters; ++k) {
+      const uint32_t w = threadIdx.x + k * kSB;
+      if (w < kWords) s_rank32[w] = v[k];
+    }
   }
   if (threadIdx.x < kZeroSlots) {  // zero slots for absent groups and padding entries
     s_F[f_cap + threadIdx.x] = C::zero();
