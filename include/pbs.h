@@ -245,20 +245,32 @@ pbs_status pbs_batch_create(uint32_t n, const pbs_grouped* const* h, const pbs_s
 pbs_status pbs_batch_run(const pbs_batch* b, double* energies, void* stream);
 
 /* Schedule of a batched launch: bits of `config` (0 = the default schedule).
- * Every schedule computes the same products and energies. */
+ * Every schedule computes the same products and energies up to the order of
+ * floating-point additions within a target; the workgroup order alone
+ * changes no output bit. */
 #define PBS_BATCH_GIVEN_ORDER 1u       /* jobs in the caller's order (default: largest first) */
 #define PBS_BATCH_NO_ROW_STAGING 2u    /* gather source rows from HBM/L2 instead of staging them in LDS */
 #define PBS_BATCH_NO_DOUBLE_MOVES 4u   /* scan double-flip groups instead of enumerating double moves */
 #define PBS_BATCH_NO_SINGLE_MOVES 8u   /* scan pair groups instead of enumerating single moves */
+/* workgroup -> (alpha row, beta chunk) order of every job (bits 4-5); the
+ * default is the single launch's: rows fastest when rows are staged in LDS,
+ * else a row's chunks kept together on one XCD (shared L2) */
+#define PBS_BATCH_ORDER_MASK 48u
+#define PBS_BATCH_ORDER_PLAIN 16u      /* row-major: a row's chunks consecutive */
+#define PBS_BATCH_ORDER_ROW_FAST 32u   /* rows fastest */
+#define PBS_BATCH_ORDER_XCD_ROWS 48u   /* a row's chunks on one XCD */
 
-/* Rebuilds the batch's job table for schedule `config` (0..15).  Synchronizes. */
+/* Rebuilds the batch's job table for schedule `config` (0..63).  Synchronizes. */
 pbs_status pbs_batch_set_config(pbs_batch* b, uint32_t config);
 
-/* Autotuner: times every distinct schedule (a warm-up run, then `reps` runs,
- * 1..100, with HIP events on the stream), keeps the fastest, and returns it
- * in *config and its time per run in *ms (either may be NULL).  Runs the
- * batch, so the output buffers are overwritten.  Call it before capturing
- * pbs_batch_run in a graph: it rebuilds the job table.  Synchronizes. */
+/* Autotuner: times schedules (a warm-up run, then `reps` runs, 1..100, with
+ * HIP events on the stream; schedules that build the same job table are
+ * timed once), greedily: the four workgroup orders with the default flags,
+ * then the 16 flag combinations with the best order.  Keeps the fastest and
+ * returns it in *config and its time per run in *ms (either may be NULL).
+ * Runs the batch, so the output buffers are overwritten.  Call it before
+ * capturing pbs_batch_run in a graph: it rebuilds the job table.
+ * Synchronizes. */
 pbs_status pbs_batch_tune(pbs_batch* b, uint32_t reps, void* stream, uint32_t* config, double* ms);
 
 /* Schedule in use, its tuned time per run (-1 when not chosen by the tuner)

@@ -62,7 +62,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_finish(const BatchJob* jobs, u
     b += partial[3ull * i + 1];
     c += partial[3ull * i + 2];
   }
-  block_reduce3_store<kBlock>(a, b, c, result + 3ull * jobs[j].pad);
+  block_reduce3_store<kBlock>(a, b, c, result + 3ull * jobs[j].slot);
 }
 
 // Sums per-workgroup partials in a fixed order (deterministic).
@@ -321,14 +321,18 @@ struct pbs_batch {
 namespace pbs {
 namespace {
 
-constexpr uint32_t kBatchConfigs = 16;  // every combination of the four PBS_BATCH_* bits
+constexpr uint32_t kBatchConfigs = 64;  // four PBS_BATCH_* flags and the 2-bit workgroup order
 
 // Builds and uploads the job table of batch B for schedule `config`:
 // PBS_BATCH_GIVEN_ORDER keeps the caller's job order (else largest first),
 // PBS_BATCH_NO_ROW_STAGING gathers source rows from HBM/L2 instead of staging
 // them in LDS, PBS_BATCH_NO_DOUBLE_MOVES scans double-flip groups instead of
 // enumerating each target's double moves, PBS_BATCH_NO_SINGLE_MOVES scans
-// pair groups instead of enumerating single moves.  Synchronizes (plain copy).
+// pair groups instead of enumerating single moves, and the order field
+// (PBS_BATCH_ORDER_*) maps a job's workgroups to (row, chunk): by default as
+// a single launch does (rows fastest when rows are staged, else a row's
+// chunks kept on one XCD), or forced plain row-major, rows fastest or
+// XCD-grouped.  Synchronizes (plain copy).
 void fill_batch(pbs_batch& B, uint32_t config) {
   const uint32_t n = B.n_jobs;
   const size_t esz = B.dt == PBS_C128 ? 16 : 8;
@@ -356,13 +360,21 @@ void fill_batch(pbs_batch& B, uint32_t config) {
     jobs[i].out = B.out[i];
     jobs[i].chunks = L.chunks;
     jobs[i].block_base = 0;
-    jobs[i].pad = i;  // original position (energies are written there)
+    jobs[i].slot = i;  // original position (energies are written there)
+    jobs[i].rows = static_cast<uint32_t>(B.sp[i]->dim_alpha);
+    jobs[i].pad = 0;
     lds = std::max(lds, L.lds);
     cost[i] = static_cast<double>(B.sp[i]->dim) * static_cast<double>(B.h[i]->n_pterm + 1);
     order[i] = i;
   }
   // largest jobs first, so the launch does not end on a long straggler
   if (!given) std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return cost[a] > cost[b]; });
+  const uint32_t order_field = config & PBS_BATCH_ORDER_MASK;
+  const uint32_t grid_order = order_field == PBS_BATCH_ORDER_PLAIN     ? kOrderPlain
+                              : order_field == PBS_BATCH_ORDER_ROW_FAST ? kOrderRowFast
+                              : order_field == PBS_BATCH_ORDER_XCD_ROWS ? kOrderXcdRows
+                              : (rowlds ? kOrderRowFast : kOrderXcdRows);
+  for (uint32_t i = 0; i < n; ++i) jobs[i].order = grid_order;
   std::vector<BatchJob> sorted(n);
   uint64_t base = 0;
   for (uint32_t k = 0; k < n; ++k) {
@@ -464,31 +476,47 @@ pbs_status pbs_batch_tune(pbs_batch* b, uint32_t reps, void* stream, uint32_t* c
     hipEvent_t e0, e1;
     PBS_HIP(hipEventCreate(&e0));
     PBS_HIP(hipEventCreate(&e1));
+    std::vector<std::pair<std::string, double>> seen;  // job table + variant -> time
+    // time of schedule c (schedules with the same table and variant share one measurement)
+    auto time_config = [&](uint32_t c) {
+      fill_batch(*b, c);
+      std::string key(1, static_cast<char>(b->row_lds));
+      std::vector<BatchJob> table(b->n_jobs);
+      PBS_HIP(hipMemcpy(table.data(), b->jobs.get(), b->n_jobs * sizeof(BatchJob), hipMemcpyDeviceToHost));
+      key.append(reinterpret_cast<const char*>(table.data()), table.size() * sizeof(BatchJob));
+      for (const auto& e : seen)
+        if (e.first == key) return e.second;
+      launch_batch(*b, nullptr, s);  // warm-up
+      PBS_HIP(hipEventRecord(e0, s));
+      for (uint32_t r = 0; r < reps; ++r) launch_batch(*b, nullptr, s);
+      PBS_HIP(hipEventRecord(e1, s));
+      PBS_HIP(hipEventSynchronize(e1));
+      float t = 0.f;
+      PBS_HIP(hipEventElapsedTime(&t, e0, e1));
+      const double per = static_cast<double>(t) / reps;
+      seen.emplace_back(std::move(key), per);
+      return per;
+    };
     uint32_t best = 0;
     double best_ms = 0.0;
-    std::vector<std::string> seen;  // schedules that produce the same job table are timed once
     try {
-      for (uint32_t c = 0; c < kBatchConfigs; ++c) {
-        fill_batch(*b, c);
-        std::string key(reinterpret_cast<const char*>(&b->row_lds), 1);
-        {
-          std::vector<BatchJob> table(b->n_jobs);
-          PBS_HIP(hipMemcpy(table.data(), b->jobs.get(), b->n_jobs * sizeof(BatchJob), hipMemcpyDeviceToHost));
-          key.append(reinterpret_cast<const char*>(table.data()), table.size() * sizeof(BatchJob));
-        }
-        if (std::find(seen.begin(), seen.end(), key) != seen.end()) continue;
-        seen.push_back(std::move(key));
-        launch_batch(*b, nullptr, s);  // warm-up
-        PBS_HIP(hipEventRecord(e0, s));
-        for (uint32_t r = 0; r < reps; ++r) launch_batch(*b, nullptr, s);
-        PBS_HIP(hipEventRecord(e1, s));
-        PBS_HIP(hipEventSynchronize(e1));
-        float t = 0.f;
-        PBS_HIP(hipEventElapsedTime(&t, e0, e1));
-        const double per = static_cast<double>(t) / reps;
-        if (seen.size() == 1 || per < best_ms) {
+      // greedy: the workgroup order first (default flags), then the four
+      // flags with that order
+      best_ms = time_config(0);
+      for (uint32_t o = 1; o < 4; ++o) {
+        const uint32_t c = o << 4;
+        const double t = time_config(c);
+        if (t < best_ms) {
           best = c;
-          best_ms = per;
+          best_ms = t;
+        }
+      }
+      const uint32_t ord = best & PBS_BATCH_ORDER_MASK;
+      for (uint32_t f = 1; f < 16; ++f) {
+        const double t = time_config(ord | f);
+        if (t < best_ms) {
+          best = ord | f;
+          best_ms = t;
         }
       }
       fill_batch(*b, best);

@@ -795,8 +795,12 @@ struct BatchJob {
   void* out;
   uint32_t block_base;  // first workgroup of the job
   uint32_t chunks;      // beta-column chunks per row
-  uint64_t pad;
+  uint32_t slot;        // the job's position in the caller's list (energies go there)
+  uint32_t rows;        // alpha rows
+  uint32_t order;       // workgroup -> (row, chunk): kOrderPlain, kOrderRowFast or kOrderXcdRows
+  uint32_t pad;
 };
+constexpr uint32_t kOrderPlain = 0, kOrderRowFast = 1, kOrderXcdRows = 2;
 
 // All jobs of a batch in one launch: workgroup b belongs to the job with the
 // largest block_base <= b (jobs are stored in block order).
@@ -815,8 +819,12 @@ __global__ __launch_bounds__(kSB) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
   // the record is not held in registers for the whole kernel
   const BatchJob& J = jobs[lo];
   const uint32_t b = blockIdx.x - J.block_base;
+  // a row's chunks share b mod 8 under kOrderXcdRows, hence one XCD whatever
+  // the job's first workgroup
+  uint32_t row = b / J.chunks, chunk = b % J.chunks;
+  if (J.order != kOrderPlain) row_chunk_of(b, J.rows, J.chunks, J.order == kOrderRowFast, row, chunk);
   sector_body<T, EXPVAL, R16, ROWLDS, REALC>(J.args, static_cast<const T*>(J.psi), static_cast<T*>(J.out),
-                                             partial + 3ull * blockIdx.x, b / J.chunks, b % J.chunks);
+                                             partial + 3ull * blockIdx.x, row, chunk);
 }
 
 // Address of one sector kernel variant (single launch or batch).

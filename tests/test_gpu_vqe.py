@@ -174,11 +174,11 @@ def test_vqe_schedule_tuning_keeps_results(dev):
         v.tune(1)
     e0, g0 = v.energy_grad(theta)
     config, ms = v.tune(2)
-    assert 0 <= config < 16 and ms > 0.0
+    assert 0 <= config < 64 and ms > 0.0
     e1, g1 = v.energy_grad(theta)
     scale = float(np.abs(op.coeff).sum())
     assert abs(e1 - e0) < 1e-12 * scale and np.abs(g1 - g0).max() < 1e-11 * scale
-    for c in (0, 6, 15):
+    for c in (0, 6, 15, 16, 32 | 3, 48 | 12):
         v.set_config(c)
         e2, g2 = v.energy_grad(theta)
         assert abs(e2 - e0) < 1e-12 * scale and np.abs(g2 - g0).max() < 1e-11 * scale
