@@ -30,10 +30,11 @@ def lib():
     return _abi.lib()
 
 
-def test_header_declares_the_north_star_calls():
+def test_header_declares_the_core_calls():
     names = set(_declared())
     for fn in ["pbs_pauli_mul", "pbs_pauli_canonicalize", "pbs_jw_transform", "pbs_group_by_xmask",
-               "pbs_apply_pauli_sum", "pbs_expval"]:
+               "pbs_apply_pauli_sum", "pbs_expval", "pbs_krylov_step", "pbs_batch_tune", "pbs_vqe_energy_grad",
+               "pbs_mlp_train", "pbs_lbfgs_minimize"]:
         assert fn in names
 
 
