@@ -312,6 +312,7 @@ pbs_status pbs_krylov_step(const pbs_grouped* h, const pbs_space* sp, pbs_dtype 
  * (N_alpha, N_beta) blocks of the full space.
  *  h      grouped operator on 2 n_orb qubits (1 <= n_orb <= 14), with sector
  *         tables; it must outlive the handle.
+ *  n_rot  number of rotations, 0..4096 (PBS_ERR_RANGE beyond).
  *  x, z   host, n_rot words: the Hermitian letter-form strings P_k (phase 0).
  *  ref    basis index of the reference state (bit k = qubit k).
  *  dt     storage of the state vectors; energies, overlaps and gradients are
@@ -347,6 +348,12 @@ pbs_status pbs_vqe_minimize(pbs_vqe* v, double* theta, uint32_t max_iter, double
  * one tuned at another geometry of the same shape).  Both synchronize. */
 pbs_status pbs_vqe_tune(pbs_vqe* v, uint32_t reps, void* stream, uint32_t* config, double* ms);
 pbs_status pbs_vqe_set_config(pbs_vqe* v, uint32_t config);
+
+/* Most consecutive rotations applied in one pass over the state (forward
+ * sweep) and undone in one pass over state and adjoint (gradient sweep), each
+ * 1, 2 or 3; rotations are fused when their X masks are linearly
+ * independent.  The results do not depend on it beyond rounding. */
+pbs_status pbs_vqe_set_groups(pbs_vqe* v, uint32_t forward, uint32_t adjoint);
 
 /* Number of (N_alpha, N_beta) blocks of the handle, and how many of them are
  * stored and applied as sector (N_beta, N_alpha): blocks with fewer beta than

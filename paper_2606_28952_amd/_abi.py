@@ -59,6 +59,7 @@ SIGNATURES = {
                                    POINTER(c_uint32), POINTER(c_uint32), POINTER(c_int32)]),
     "pbs_vqe_tune": (c_int32, [_vp, c_uint32, _vp, POINTER(c_uint32), POINTER(c_double)]),
     "pbs_vqe_set_config": (c_int32, [_vp, c_uint32]),
+    "pbs_vqe_set_groups": (c_int32, [_vp, c_uint32, c_uint32]),
     "pbs_vqe_info": (c_int32, [_vp, POINTER(c_uint32), POINTER(c_uint32)]),
     "pbs_vqe_destroy": (None, [_vp]),
     "pbs_lbfgs_minimize": (c_int32, [c_uint32, _vp, _vp, _vp, c_uint32, c_uint32, c_double, c_double,

@@ -385,6 +385,10 @@ class VQE:
     def set_config(self, config):
         call("pbs_vqe_set_config", self._h, int(config))
 
+    def set_groups(self, forward, adjoint):
+        """Most rotations fused per forward / adjoint pass (1..3)."""
+        call("pbs_vqe_set_groups", self._h, int(forward), int(adjoint))
+
     def blocks(self):
         """(sector blocks, blocks stored as sector (N_beta, N_alpha))."""
         nb, nt = c_uint32(), c_uint32()

@@ -133,12 +133,15 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_step(T* __restrict__ psi, T*
   block_reduce3_store<kBlock>(sr, si, 0.0, partial + 3ull * blockIdx.x);
 }
 
-// ---------------------------------------------------------------- two rotations per pass
-// Rotations a and b with independent nonzero X masks act together on the
-// orbits {t, t^xa, t^xb, t^xa^xb}.  Pivot bits: h1 = highest bit of xa and
-// h2 = highest bit of y, where y is xb or xb^xa, whichever has bit h1 clear.
-// Every orbit holds exactly one index with both pivot bits clear, which is
-// enumerated by inserting zero bits at the two pivots (lo < hi) into i.
+// ---------------------------------------------------------------- K rotations per pass
+// K consecutive rotations whose X masks are linearly independent over GF(2)
+// act together on the orbits t ^ span{x_0 .. x_{K-1}} of 2^K indices.
+// Gaussian elimination gives a basis b_j of the span with leading bit p_j and
+// bit p_i of b_j clear for i < j; projecting the span onto the pivot bits is
+// then one to one, so every orbit holds exactly one index with all pivot bits
+// clear, enumerated by inserting zero bits at the sorted pivots into i.
+// Element e of an orbit is t0 ^ (sum over the set bits j of e of x_j), so
+// rotation j pairs the elements that differ in bit j of e.
 struct PairRot {
   uint64_t x, z;
   uint32_t omega;
@@ -191,91 +194,110 @@ __device__ inline void store_cx(T* p, uint64_t i, const Cx& v) {
   Amp<T>::store(p, i, v.r, v.i);
 }
 
-// psi <- R_b R_a psi
-template <class T>
-__global__ __launch_bounds__(kBlock) void k_rotate2(T* __restrict__ psi, uint64_t dim, PairRot A, PairRot B,
-                                                     uint32_t lo, uint32_t hi) {
-  for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < dim / 4;
+template <int K>
+struct RotGroup {
+  PairRot r[K];      // in application order
+  uint32_t piv[K];   // pivot bits, ascending
+};
+
+template <int K>
+__device__ inline uint64_t orbit_base(uint64_t i, const RotGroup<K>& G) {
+  uint64_t t = i;
+#pragma unroll
+  for (int j = 0; j < K; ++j) t = insert_zero(t, G.piv[j]);
+  return t;
+}
+
+// psi <- R_{K-1} ... R_0 psi
+template <class T, int K>
+__global__ __launch_bounds__(kBlock) void k_rotate_group(T* __restrict__ psi, uint64_t dim, RotGroup<K> G) {
+  constexpr int N = 1 << K;
+  for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < (dim >> K);
        i += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
-    const uint64_t t0 = insert_zero(insert_zero(i, lo), hi);
-    const uint64_t t1 = t0 ^ A.x, t2 = t0 ^ B.x, t3 = t1 ^ B.x;
-    Cx v0 = load_cx(psi, t0), v1 = load_cx(psi, t1), v2 = load_cx(psi, t2), v3 = load_cx(psi, t3);
-    rotate_pair(v0, v1, t0, t1, A);
-    rotate_pair(v2, v3, t2, t3, A);
-    rotate_pair(v0, v2, t0, t2, B);
-    rotate_pair(v1, v3, t1, t3, B);
-    store_cx(psi, t0, v0);
-    store_cx(psi, t1, v1);
-    store_cx(psi, t2, v2);
-    store_cx(psi, t3, v3);
+    uint64_t t[N];
+    t[0] = orbit_base(i, G);
+#pragma unroll
+    for (int e = 1; e < N; ++e) t[e] = t[e & (e - 1)] ^ G.r[__builtin_ctz(e)].x;
+    Cx v[N];
+#pragma unroll
+    for (int e = 0; e < N; ++e) v[e] = load_cx(psi, t[e]);
+#pragma unroll
+    for (int j = 0; j < K; ++j)
+#pragma unroll
+      for (int e = 0; e < N; ++e)
+        if (!(e & (1 << j))) rotate_pair(v[e], v[e | (1 << j)], t[e], t[e | (1 << j)], G.r[j]);
+#pragma unroll
+    for (int e = 0; e < N; ++e) store_cx(psi, t[e], v[e]);
   }
 }
 
-// Two adjoint steps in one pass: with psi = psi_b and lam = lam_b on entry,
-// partials of <lam|P_b|psi>, then R_b^dagger on both vectors, partials of
-// <lam|P_a|psi>, then R_a^dagger on both (A and B carry cos, sin of -theta).
-template <class T>
-__global__ __launch_bounds__(kBlock) void k_adjoint_step2(T* __restrict__ psi, T* __restrict__ lam, uint64_t dim,
-                                                           PairRot A, PairRot B, uint32_t lo, uint32_t hi,
-                                                           double* __restrict__ partial_a,
-                                                           double* __restrict__ partial_b) {
-  double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0;
-  for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < dim / 4;
+// K adjoint steps in one pass: with psi and lam taken after rotation K-1 on
+// entry, for j = K-1 down to 0: partials of <lam|P_j|psi>, then R_j^dagger
+// on both vectors (G carries cos, sin of -theta).  partial_j = partial +
+// 3 * stride * j.
+template <class T, int K>
+__global__ __launch_bounds__(kBlock) void k_adjoint_group(T* __restrict__ psi, T* __restrict__ lam, uint64_t dim,
+                                                           RotGroup<K> G, double* __restrict__ partial,
+                                                           uint64_t stride) {
+  constexpr int N = 1 << K;
+  double ov[2 * K];
+#pragma unroll
+  for (int j = 0; j < 2 * K; ++j) ov[j] = 0.0;
+  for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < (dim >> K);
        i += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
-    const uint64_t t0 = insert_zero(insert_zero(i, lo), hi);
-    const uint64_t t1 = t0 ^ A.x, t2 = t0 ^ B.x, t3 = t1 ^ B.x;
-    Cx p0 = load_cx(psi, t0), p1 = load_cx(psi, t1), p2 = load_cx(psi, t2), p3 = load_cx(psi, t3);
-    Cx l0 = load_cx(lam, t0), l1 = load_cx(lam, t1), l2 = load_cx(lam, t2), l3 = load_cx(lam, t3);
-    overlap_pair(p0, p2, l0, l2, t0, t2, B, br, bi);
-    overlap_pair(p1, p3, l1, l3, t1, t3, B, br, bi);
-    rotate_pair(p0, p2, t0, t2, B);
-    rotate_pair(p1, p3, t1, t3, B);
-    rotate_pair(l0, l2, t0, t2, B);
-    rotate_pair(l1, l3, t1, t3, B);
-    overlap_pair(p0, p1, l0, l1, t0, t1, A, ar, ai);
-    overlap_pair(p2, p3, l2, l3, t2, t3, A, ar, ai);
-    rotate_pair(p0, p1, t0, t1, A);
-    rotate_pair(p2, p3, t2, t3, A);
-    rotate_pair(l0, l1, t0, t1, A);
-    rotate_pair(l2, l3, t2, t3, A);
-    store_cx(psi, t0, p0);
-    store_cx(psi, t1, p1);
-    store_cx(psi, t2, p2);
-    store_cx(psi, t3, p3);
-    store_cx(lam, t0, l0);
-    store_cx(lam, t1, l1);
-    store_cx(lam, t2, l2);
-    store_cx(lam, t3, l3);
+    uint64_t t[N];
+    t[0] = orbit_base(i, G);
+#pragma unroll
+    for (int e = 1; e < N; ++e) t[e] = t[e & (e - 1)] ^ G.r[__builtin_ctz(e)].x;
+    Cx p[N], l[N];
+#pragma unroll
+    for (int e = 0; e < N; ++e) {
+      p[e] = load_cx(psi, t[e]);
+      l[e] = load_cx(lam, t[e]);
+    }
+#pragma unroll
+    for (int j = K - 1; j >= 0; --j) {
+#pragma unroll
+      for (int e = 0; e < N; ++e)
+        if (!(e & (1 << j)))
+          overlap_pair(p[e], p[e | (1 << j)], l[e], l[e | (1 << j)], t[e], t[e | (1 << j)], G.r[j], ov[2 * j],
+                       ov[2 * j + 1]);
+#pragma unroll
+      for (int e = 0; e < N; ++e)
+        if (!(e & (1 << j))) {
+          rotate_pair(p[e], p[e | (1 << j)], t[e], t[e | (1 << j)], G.r[j]);
+          rotate_pair(l[e], l[e | (1 << j)], t[e], t[e | (1 << j)], G.r[j]);
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < N; ++e) {
+      store_cx(psi, t[e], p[e]);
+      store_cx(lam, t[e], l[e]);
+    }
   }
-  __shared__ double red[4][kBlock / 64];
-  for (int d = 32; d > 0; d >>= 1) {
-    ar += __shfl_xor(ar, d, 64);
-    ai += __shfl_xor(ai, d, 64);
-    br += __shfl_xor(br, d, 64);
-    bi += __shfl_xor(bi, d, 64);
-  }
+  __shared__ double red[2 * K][kBlock / 64];
+#pragma unroll
+  for (int j = 0; j < 2 * K; ++j)
+    for (int d = 32; d > 0; d >>= 1) ov[j] += __shfl_xor(ov[j], d, 64);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (lane == 0) {
-    red[0][wave] = ar;
-    red[1][wave] = ai;
-    red[2][wave] = br;
-    red[3][wave] = bi;
+#pragma unroll
+    for (int j = 0; j < 2 * K; ++j) red[j][wave] = ov[j];
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    for (int w = 0; w < kBlock / 64; ++w) {
-      s0 += red[0][w];
-      s1 += red[1][w];
-      s2 += red[2][w];
-      s3 += red[3][w];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      double sr = 0.0, si = 0.0;
+      for (int w = 0; w < kBlock / 64; ++w) {
+        sr += red[2 * j][w];
+        si += red[2 * j + 1][w];
+      }
+      double* out = partial + 3ull * stride * j + 3ull * blockIdx.x;
+      out[0] = sr;
+      out[1] = si;
+      out[2] = 0.0;
     }
-    partial_a[3ull * blockIdx.x] = s0;
-    partial_a[3ull * blockIdx.x + 1] = s1;
-    partial_a[3ull * blockIdx.x + 2] = 0.0;
-    partial_b[3ull * blockIdx.x] = s2;
-    partial_b[3ull * blockIdx.x + 1] = s3;
-    partial_b[3ull * blockIdx.x + 2] = 0.0;
   }
 }
 
@@ -405,6 +427,7 @@ struct pbs_vqe {
   uint32_t nparts = 0;
   bool evaluated = false;  // blk_in holds psi(theta) of the last evaluation
   uint32_t n_transposed = 0;  // blocks stored as sector (N_beta, N_alpha)
+  uint32_t group_fwd = 3, group_adj = 3;  // most rotations fused per forward / adjoint pass (1..3)
   ~pbs_vqe() {
     if (batch) pbs_batch_destroy(batch);
     for (pbs_space* sp : spaces) pbs_space_destroy(sp);
@@ -414,20 +437,27 @@ struct pbs_vqe {
 namespace pbs {
 namespace {
 constexpr unsigned kVqeGrid = 4096;
-
-// Pivot bits (lo < hi) for rotations a, b fused in one pass, or false when
-// their X masks are zero or equal (then they run one at a time).
-bool pair_pivots(const Rot& a, const Rot& b, uint32_t& lo, uint32_t& hi) {
-  if (a.x == 0 || b.x == 0 || a.x == b.x) return false;
-  const uint32_t h1 = 63u - static_cast<uint32_t>(__builtin_clzll(a.x));
-  const uint64_t y = ((b.x >> h1) & 1ull) ? (b.x ^ a.x) : b.x;
-  const uint32_t h2 = 63u - static_cast<uint32_t>(__builtin_clzll(y));
-  lo = h1 < h2 ? h1 : h2;
-  hi = h1 < h2 ? h2 : h1;
-  return true;
-}
+constexpr uint32_t kMaxRotations = 4096;  // overlap partials: 3 doubles x <= 4096 workgroups per rotation
 
 PairRot pair_rot(const Rot& r, double angle) { return PairRot{r.x, r.z, r.omega, cos(angle), sin(angle)}; }
+
+// Rotations first .. first+K-1 as one group, or false when their X masks are
+// not linearly independent (a zero or repeated mask included).
+template <int K>
+bool make_group(const pbs_vqe& v, uint32_t first, const double* theta, double sign, RotGroup<K>& G) {
+  uint64_t basis[K];
+  for (int j = 0; j < K; ++j) {
+    uint64_t y = v.rots[first + j].x;
+    for (int i = 0; i < j; ++i)
+      if ((y >> G.piv[i]) & 1ull) y ^= basis[i];
+    if (y == 0) return false;
+    basis[j] = y;
+    G.piv[j] = 63u - static_cast<uint32_t>(__builtin_clzll(y));
+    G.r[j] = pair_rot(v.rots[first + j], sign * theta[first + j]);
+  }
+  std::sort(G.piv, G.piv + K);
+  return true;
+}
 
 template <class T>
 void rotate_all(pbs_vqe& v, T* psi, const double* theta, bool inverse, uint32_t k, hipStream_t s) {
@@ -447,10 +477,15 @@ void energy_grad(pbs_vqe& v, const double* theta, double* energy, double* grad, 
   hipLaunchKernelGGL(k_basis_state, grid, dim3(kBlock), 0, s, sizeof(T) == 16 ? reinterpret_cast<double2*>(psi) : nullptr,
                      sizeof(T) == 8 ? reinterpret_cast<float2*>(psi) : nullptr, v.dim, v.ref);
   for (uint32_t k = 0; k < v.n_rot;) {
-    uint32_t lo, hi;
-    if (k + 1 < v.n_rot && pair_pivots(v.rots[k], v.rots[k + 1], lo, hi)) {
-      hipLaunchKernelGGL((k_rotate2<T>), dim3(grid_for(v.dim / 4, kBlock, kVqeGrid)), dim3(kBlock), 0, s, psi, v.dim,
-                         pair_rot(v.rots[k], theta[k]), pair_rot(v.rots[k + 1], theta[k + 1]), lo, hi);
+    RotGroup<3> G3;
+    RotGroup<2> G2;
+    if (v.group_fwd >= 3 && k + 2 < v.n_rot && v.dim >= 8 && make_group<3>(v, k, theta, 1.0, G3)) {
+      hipLaunchKernelGGL((k_rotate_group<T, 3>), dim3(grid_for(v.dim / 8, kBlock, kVqeGrid)), dim3(kBlock), 0, s,
+                         psi, v.dim, G3);
+      k += 3;
+    } else if (v.group_fwd >= 2 && k + 1 < v.n_rot && make_group<2>(v, k, theta, 1.0, G2)) {
+      hipLaunchKernelGGL((k_rotate_group<T, 2>), dim3(grid_for(v.dim / 4, kBlock, kVqeGrid)), dim3(kBlock), 0, s,
+                         psi, v.dim, G2);
       k += 2;
     } else {
       rotate_all<T>(v, psi, theta, false, k, s);
@@ -471,11 +506,15 @@ void energy_grad(pbs_vqe& v, const double* theta, double* energy, double* grad, 
                        sp0.n_chunks, v.rank_tab.get(), v.off.get(), v.binom_n.get());
     // adjoint sweep: g_k = -2 Im <lam_k|P_k|psi_k>, then undo rotation k on both vectors
     for (uint32_t k = v.n_rot; k > 0;) {
-      uint32_t lo, hi;
-      if (k >= 2 && pair_pivots(v.rots[k - 2], v.rots[k - 1], lo, hi)) {
-        hipLaunchKernelGGL((k_adjoint_step2<T>), dim3(v.nparts), dim3(kBlock), 0, s, psi, lam, v.dim,
-                           pair_rot(v.rots[k - 2], -theta[k - 2]), pair_rot(v.rots[k - 1], -theta[k - 1]), lo, hi,
-                           v.partial.get() + 3ull * v.nparts * (k - 2), v.partial.get() + 3ull * v.nparts * (k - 1));
+      RotGroup<3> G3;
+      RotGroup<2> G2;
+      if (v.group_adj >= 3 && k >= 3 && v.dim >= 8 && make_group<3>(v, k - 3, theta, -1.0, G3)) {
+        hipLaunchKernelGGL((k_adjoint_group<T, 3>), dim3(v.nparts), dim3(kBlock), 0, s, psi, lam, v.dim, G3,
+                           v.partial.get() + 3ull * v.nparts * (k - 3), static_cast<uint64_t>(v.nparts));
+        k -= 3;
+      } else if (v.group_adj >= 2 && k >= 2 && make_group<2>(v, k - 2, theta, -1.0, G2)) {
+        hipLaunchKernelGGL((k_adjoint_group<T, 2>), dim3(v.nparts), dim3(kBlock), 0, s, psi, lam, v.dim, G2,
+                           v.partial.get() + 3ull * v.nparts * (k - 2), static_cast<uint64_t>(v.nparts));
         k -= 2;
       } else {
         --k;
@@ -523,6 +562,8 @@ pbs_status pbs_vqe_create(const pbs_grouped* h, uint32_t n_orb, uint32_t n_rot, 
     PBS_REQUIRE(n_orb >= 1 && n_orb <= 14, PBS_ERR_RANGE, "the full space needs 1 <= n_orb <= 14");
     PBS_REQUIRE(h->n_qubits == 2 * n_orb && h->has_sector && h->half == n_orb, PBS_ERR_ARG,
                 "operator must act on 2 n_orb qubits with sector tables");
+    PBS_REQUIRE(n_rot <= kMaxRotations, PBS_ERR_RANGE,
+                "at most " + std::to_string(kMaxRotations) + " rotations (the gradient keeps per-rotation partials)");
     PBS_REQUIRE(n_rot == 0 || (x != nullptr && z != nullptr), PBS_ERR_ARG, "null rotation strings");
     const uint64_t dim = 1ull << (2 * n_orb);
     PBS_REQUIRE(ref < dim, PBS_ERR_ARG, "reference state outside the space");
@@ -537,6 +578,9 @@ pbs_status pbs_vqe_create(const pbs_grouped* h, uint32_t n_orb, uint32_t n_rot, 
       v->n_rot = n_rot;
       v->dt = dt;
       v->dim = dim;
+      // measured at 24 qubits: three-rotation adjoint passes need 328 registers
+      // per lane (one wave per SIMD), which pays off for complex128 only
+      v->group_adj = dt == PBS_C128 ? 3u : 2u;
       v->ref = ref;
       for (uint32_t k = 0; k < n_rot; ++k) v->rots.push_back(rot_of(x[k], z[k]));
       const size_t esz = dt == PBS_C128 ? 16 : 8;
@@ -656,6 +700,16 @@ pbs_status pbs_vqe_set_config(pbs_vqe* v, uint32_t config) {
     PBS_REQUIRE(v != nullptr, PBS_ERR_ARG, "null pbs_vqe");
     const pbs_status st = pbs_batch_set_config(v->batch, config);
     PBS_REQUIRE(st == PBS_OK, st, std::string("batch schedule: ") + pbs_last_error());
+  });
+}
+
+pbs_status pbs_vqe_set_groups(pbs_vqe* v, uint32_t forward, uint32_t adjoint) {
+  return guarded([&] {
+    PBS_REQUIRE(v != nullptr, PBS_ERR_ARG, "null pbs_vqe");
+    PBS_REQUIRE(forward >= 1 && forward <= 3 && adjoint >= 1 && adjoint <= 3, PBS_ERR_RANGE,
+                "rotations fused per pass must be 1, 2 or 3");
+    v->group_fwd = forward;
+    v->group_adj = adjoint;
   });
 }
 
