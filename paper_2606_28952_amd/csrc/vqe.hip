@@ -177,6 +177,29 @@ __device__ inline void overlap_pair(const Cx& at, const Cx& au, const Cx& lt, co
   si = fma(lu.r, pu.i, fma(-lu.i, pu.r, si));
 }
 
+// One adjoint step on the pair (t, u = t ^ x) of both vectors:
+// acc += conj(l) (P p) over the pair, then p <- R p and l <- R l with the
+// pair's two Z parities evaluated once.
+__device__ inline void adjoint_pair(Cx& pt, Cx& pu, Cx& lt, Cx& lu, uint64_t t, uint64_t u, const PairRot& R,
+                                    double& sr, double& si) {
+  const uint32_t qt = __popcll(R.z & t), qu = __popcll(R.z & u);
+  auto image = [&](const Cx& v, uint32_t q) {
+    double r = signed_by(v.r, q), m = signed_by(v.i, q);
+    times_i_pow(R.omega, r, m);
+    return Cx{r, m};
+  };
+  const Cx a_t = image(pu, qu), a_u = image(pt, qt);  // (P p)[t], (P p)[u]
+  sr = fma(lt.r, a_t.r, fma(lt.i, a_t.i, sr));
+  si = fma(lt.r, a_t.i, fma(-lt.i, a_t.r, si));
+  sr = fma(lu.r, a_u.r, fma(lu.i, a_u.i, sr));
+  si = fma(lu.r, a_u.i, fma(-lu.i, a_u.r, si));
+  const Cx b_t = image(lu, qu), b_u = image(lt, qt);  // (P l)[t], (P l)[u]
+  pt = Cx{R.c * pt.r - R.s * a_t.i, R.c * pt.i + R.s * a_t.r};
+  pu = Cx{R.c * pu.r - R.s * a_u.i, R.c * pu.i + R.s * a_u.r};
+  lt = Cx{R.c * lt.r - R.s * b_t.i, R.c * lt.i + R.s * b_t.r};
+  lu = Cx{R.c * lu.r - R.s * b_u.i, R.c * lu.i + R.s * b_u.r};
+}
+
 __device__ inline uint64_t insert_zero(uint64_t v, uint32_t b) {
   const uint64_t low = (1ull << b) - 1ull;
   return ((v & ~low) << 1) | (v & low);
@@ -260,14 +283,8 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_group(T* __restrict__ psi, T
 #pragma unroll
       for (int e = 0; e < N; ++e)
         if (!(e & (1 << j)))
-          overlap_pair(p[e], p[e | (1 << j)], l[e], l[e | (1 << j)], t[e], t[e | (1 << j)], G.r[j], ov[2 * j],
+          adjoint_pair(p[e], p[e | (1 << j)], l[e], l[e | (1 << j)], t[e], t[e | (1 << j)], G.r[j], ov[2 * j],
                        ov[2 * j + 1]);
-#pragma unroll
-      for (int e = 0; e < N; ++e)
-        if (!(e & (1 << j))) {
-          rotate_pair(p[e], p[e | (1 << j)], t[e], t[e | (1 << j)], G.r[j]);
-          rotate_pair(l[e], l[e | (1 << j)], t[e], t[e | (1 << j)], G.r[j]);
-        }
     }
 #pragma unroll
     for (int e = 0; e < N; ++e) {
