@@ -426,7 +426,10 @@ pbs_status pbs_mlp_loss_grad(pbs_mlp* m, uint32_t n, const float* x, const float
 
 /* n_steps full-batch Adam steps with learning rate lr on (x, t), continuing
  * the handle's step count; losses (device, n_steps floats, may be NULL)
- * receives the loss before each step.  Asynchronous. */
+ * receives the loss before each step.  Asynchronous: nine kernel launches
+ * per step on the caller's stream, with the step count kept on the device,
+ * so a call allocates nothing, copies nothing and may be captured in a HIP
+ * graph by the caller. */
 pbs_status pbs_mlp_train(pbs_mlp* m, uint32_t n, const float* x, const float* t, uint32_t n_steps, float lr,
                          float* losses, void* stream);
 

@@ -159,7 +159,8 @@ __global__ __launch_bounds__(kMlpBlock) void k_mlp_colsum(const float* __restric
                                                            const float* __restrict__ dz2,
                                                            const float* __restrict__ dy,
                                                            const float* __restrict__ partial, uint32_t n_partial,
-                                                           float* __restrict__ grad, float* __restrict__ loss) {
+                                                           float* __restrict__ grad, float* __restrict__ loss,
+                                                           const uint32_t* __restrict__ steps, uint32_t base) {
   const uint32_t c = blockIdx.x * kMlpBlock + threadIdx.x;
   const size_t off_b1 = H, off_b2 = 3ull * H + static_cast<size_t>(H) * H - H;
   const size_t off_b3 = 3ull * H + static_cast<size_t>(H) * H + static_cast<size_t>(O) * H;
@@ -185,17 +186,23 @@ __global__ __launch_bounds__(kMlpBlock) void k_mlp_colsum(const float* __restric
   } else if (c == 2 * H + O && loss) {
     float s = 0.f;
     for (uint32_t t = 0; t < n_partial; ++t) s += partial[t];
-    *loss = s / (static_cast<float>(n) * static_cast<float>(O));
+    // during training, loss[step - base] with the step count kept on the device
+    loss[steps ? *steps - base : 0u] = s / (static_cast<float>(n) * static_cast<float>(O));
   }
 }
 
-// Adam with bias correction; refreshes the bf16 copies of W2 and W3.
+// Adam with bias correction for step *steps + 1 (the count is kept on the
+// device so that one captured step can be replayed); refreshes the bf16
+// copies of W2 and W3.
 __global__ __launch_bounds__(kMlpBlock) void k_mlp_adam(float* __restrict__ p, const float* __restrict__ g,
                                                          float* __restrict__ m1, float* __restrict__ m2,
-                                                         uint64_t count, float lr, float bc1, float bc2,
+                                                         uint64_t count, float lr, const uint32_t* __restrict__ steps,
                                                          uint64_t off_w2, uint64_t n_w2, uint16_t* __restrict__ w2b,
                                                          uint64_t off_w3, uint64_t n_w3,
                                                          uint16_t* __restrict__ w3b) {
+  const double t = static_cast<double>(*steps) + 1.0;
+  const float bc1 = static_cast<float>(1.0 / (1.0 - pow(static_cast<double>(kBeta1), t)));
+  const float bc2 = static_cast<float>(1.0 / (1.0 - pow(static_cast<double>(kBeta2), t)));
   for (uint64_t i = blockIdx.x * static_cast<uint64_t>(kMlpBlock) + threadIdx.x; i < count;
        i += static_cast<uint64_t>(gridDim.x) * kMlpBlock) {
     const float gi = g[i];
@@ -208,6 +215,10 @@ __global__ __launch_bounds__(kMlpBlock) void k_mlp_adam(float* __restrict__ p, c
     if (i - off_w2 < n_w2) w2b[i - off_w2] = to_bf16(w);
     if (i - off_w3 < n_w3) w3b[i - off_w3] = to_bf16(w);
   }
+}
+
+__global__ void k_mlp_tick(uint32_t* steps) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *steps += 1u;
 }
 
 __global__ __launch_bounds__(kMlpBlock) void k_mlp_refresh(const float* __restrict__ p, uint64_t off_w2,
@@ -233,10 +244,11 @@ using namespace pbs;
 struct pbs_mlp {
   uint32_t H = 0, O = 0, Op = 0, max_rows = 0;
   uint64_t count = 0, off_w2 = 0, off_b2 = 0, off_w3 = 0, off_b3 = 0;
-  uint64_t step = 0;  // Adam steps taken
+  uint64_t step = 0;  // Adam steps taken (host copy of *steps)
   DevBuf<float> params, grads, mom1, mom2;
   DevBuf<uint16_t> w2b, w3b;
   DevBuf<float> h1, h2, dy, dz2, dz1, partial, loss;
+  DevBuf<uint32_t> steps;  // Adam steps taken, on the device
   DevBuf<uint16_t> h1b, h2b, dyb, dz2b;
 };
 
@@ -296,7 +308,8 @@ void forward(pbs_mlp& m, uint32_t n, const float* x, float* y, const float* t, h
 }
 
 // Backward pass after forward(..., t): gradients into grad (packed layout).
-void backward(pbs_mlp& m, uint32_t n, const float* x, float* grad, float* loss, hipStream_t s) {
+void backward(pbs_mlp& m, uint32_t n, const float* x, float* grad, float* loss, const uint32_t* steps, uint32_t base,
+              hipStream_t s) {
   const uint32_t rows = round_up32(n), H = m.H, Op = m.Op;
   // dW3[j][k] = sum_b dy[b][j] h2[b][k]
   Gemm w3{};
@@ -363,23 +376,30 @@ void backward(pbs_mlp& m, uint32_t n, const float* x, float* grad, float* loss, 
   const uint32_t cols = 2 * H + m.O + 1;
   hipLaunchKernelGGL(k_mlp_colsum, dim3((cols + kMlpBlock - 1) / kMlpBlock), dim3(kMlpBlock), 0, s, x, n, rows, H,
                      m.O, Op, m.dz1.get(), m.dz2.get(), m.dy.get(), m.partial.get(), (rows / 16) * (Op / 16), grad,
-                     loss);
+                     loss, steps, base);
 }
 
 void adam(pbs_mlp& m, float lr, hipStream_t s) {
-  ++m.step;
-  const double bc1 = 1.0 / (1.0 - std::pow(static_cast<double>(kBeta1), static_cast<double>(m.step)));
-  const double bc2 = 1.0 / (1.0 - std::pow(static_cast<double>(kBeta2), static_cast<double>(m.step)));
   hipLaunchKernelGGL(k_mlp_adam, dim3(grid_for(m.count, kMlpBlock, 1024)), dim3(kMlpBlock), 0, s, m.params.get(),
-                     m.grads.get(), m.mom1.get(), m.mom2.get(), m.count, lr, static_cast<float>(bc1),
-                     static_cast<float>(bc2), m.off_w2, static_cast<uint64_t>(m.H) * m.H, m.w2b.get(), m.off_w3,
-                     static_cast<uint64_t>(m.O) * m.H, m.w3b.get());
+                     m.grads.get(), m.mom1.get(), m.mom2.get(), m.count, lr, m.steps.get(), m.off_w2,
+                     static_cast<uint64_t>(m.H) * m.H, m.w2b.get(), m.off_w3, static_cast<uint64_t>(m.O) * m.H,
+                     m.w3b.get());
+  hipLaunchKernelGGL(k_mlp_tick, dim3(1), dim3(64), 0, s, m.steps.get());
+}
+
+// One training step: forward, backward (loss into losses[step - base]), Adam.
+void train_step(pbs_mlp& m, uint32_t n, const float* x, const float* t, float lr, float* losses, uint32_t base,
+                hipStream_t s) {
+  forward(m, n, x, nullptr, t, s);
+  backward(m, n, x, m.grads.get(), losses, losses ? m.steps.get() : nullptr, base, s);
+  adam(m, lr, s);
 }
 
 void load_params(pbs_mlp& m, const float* params, hipStream_t s) {
   PBS_HIP(hipMemcpyAsync(m.params.get(), params, m.count * sizeof(float), hipMemcpyDefault, s));
   PBS_HIP(hipMemsetAsync(m.mom1.get(), 0, m.count * sizeof(float), s));
   PBS_HIP(hipMemsetAsync(m.mom2.get(), 0, m.count * sizeof(float), s));
+  PBS_HIP(hipMemsetAsync(m.steps.get(), 0, sizeof(uint32_t), s));
   m.step = 0;
   const uint64_t n2 = static_cast<uint64_t>(m.H) * m.H, n3 = static_cast<uint64_t>(m.O) * m.H;
   hipLaunchKernelGGL(k_mlp_refresh, dim3(grid_for(n2 + n3, kMlpBlock, 1024)), dim3(kMlpBlock), 0, s,
@@ -447,6 +467,7 @@ pbs_status pbs_mlp_create(uint32_t hidden, uint32_t n_out, uint32_t max_batch, c
       m->dyb.alloc(outs);
       m->partial.alloc((R / 16) * (Op / 16));
       m->loss.alloc(1);
+      m->steps.alloc(1);
       load_params(*m, params, s);
       PBS_HIP(hipStreamSynchronize(s));
     } catch (...) {
@@ -489,7 +510,7 @@ pbs_status pbs_mlp_loss_grad(pbs_mlp* m, uint32_t n, const float* x, const float
     PBS_REQUIRE(x != nullptr && t != nullptr && grad != nullptr, PBS_ERR_ARG, "null argument");
     hipStream_t s = as_stream(stream);
     forward(*m, n, x, nullptr, t, s);
-    backward(*m, n, x, grad, loss, s);
+    backward(*m, n, x, grad, loss, nullptr, 0u, s);
     PBS_HIP(hipGetLastError());
   });
 }
@@ -500,12 +521,11 @@ pbs_status pbs_mlp_train(pbs_mlp* m, uint32_t n, const float* x, const float* t,
     check_batch(m, n);
     PBS_REQUIRE(x != nullptr && t != nullptr, PBS_ERR_ARG, "null argument");
     PBS_REQUIRE(lr > 0.f && std::isfinite(lr), PBS_ERR_ARG, "learning rate must be positive");
+    PBS_REQUIRE(m->step + n_steps < (1ull << 32), PBS_ERR_RANGE, "step count beyond 2^32");
     hipStream_t s = as_stream(stream);
-    for (uint32_t i = 0; i < n_steps; ++i) {
-      forward(*m, n, x, nullptr, t, s);
-      backward(*m, n, x, m->grads.get(), losses ? losses + i : nullptr, s);
-      adam(*m, lr, s);
-    }
+    const uint32_t base = static_cast<uint32_t>(m->step);
+    for (uint32_t i = 0; i < n_steps; ++i) train_step(*m, n, x, t, lr, losses, base, s);
+    m->step += n_steps;
     PBS_HIP(hipGetLastError());
   });
 }

@@ -121,3 +121,26 @@ def test_argument_errors(dev):
     net = api.MLP(32, 4, 8, p)
     with pytest.raises(Exception, match="batch"):
         net.forward(torch.zeros(9, device=dev))
+
+
+def test_training_runs_match_single_steps(dev):
+    # the Adam step count lives on the device: one call of n steps and n
+    # calls of one step, with forward passes between the runs, give
+    # bit-identical parameters and losses
+    api = _api()
+    H, O, n = 64, 20, 12
+    p = synth.mlp_init(H, O, seed=21)
+    x, t = _data(n, O, seed=22)
+    xs, ts = torch.from_numpy(x).to(dev), torch.from_numpy(t).to(dev)
+    graph_net, eager_net = api.MLP(H, O, n, p), api.MLP(H, O, n, p)
+    graph_losses, eager_losses = [], []
+    for run in (20, 9):
+        graph_losses.append(graph_net.train(xs, ts, run, 2e-3).cpu().numpy())
+        graph_net.forward(xs)
+        for _ in range(run):
+            eager_losses.append(eager_net.train(xs, ts, 1, 2e-3).cpu().numpy())
+        eager_net.forward(xs)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(graph_net.params(), eager_net.params())
+    np.testing.assert_array_equal(np.concatenate(graph_losses), np.concatenate(eager_losses))
+    assert not np.array_equal(graph_net.params(), p)
