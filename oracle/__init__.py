@@ -22,7 +22,11 @@ obviously correct.  It shares no code, table or helper with the HIP path:
   enumerated ascending list, not by a combinatorial formula.
 * Operator application scatters term by term over source configurations,
   the plain definition behind Eq. grouped_contraction, while the kernels
-  gather per X-mask group (Eq. reverse_sum).
+  gather per X-mask group (Eq. reverse_sum).  ``capply.c`` (loaded by
+  ``native``) is a plain C float64 twin of that scatter and of the ungrouped
+  per-target gather, threaded with OpenMP, for full-size workloads; it
+  ranks sector configurations through position tables built from the
+  enumerated spin strings.
 
 Readings of points the paper leaves open are listed in the module that uses
 them and in the design notes of the repository.
