@@ -9,11 +9,15 @@ float64 energy <psi|H|psi>.  The metric is amplitude*terms per second,
 D * M / t_step with M the number of canonical Pauli strings.
 
 The dominant kernel (the sector apply) is timed with HIP events on the
-stream it runs on; its roofline fraction uses the algorithmic gather bytes
-per launch, D * b * (1 + G_conn) with b = 8 bytes per complex64 amplitude and
-G_conn the connected groups per target.  The complex128 (FP64 plain) apply
-is timed beside it, and the oracle is timed on a bounded sample of the same
-workload on the host cores.
+stream it runs on.  On the molecular sector it is bound by vector-ALU issue:
+its roofline is its VALU wave-instructions per launch (from the committed
+rocprofv3 counters of the same kernel source) per second against 614.4 G/s,
+with the measured HBM traffic and the method's algorithmic gather bytes,
+D * b * (1 + G_conn) (b = 8 bytes per complex64 amplitude, G_conn connected
+groups per target), reported beside it.  On the Hubbard sector it is bound by
+HBM bandwidth and the algorithmic bytes are the roofline.  The complex128
+(FP64 plain) apply is timed beside it, and the oracle's C twin is timed on a
+bounded sample of the same workload on the host cores.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 """
@@ -32,11 +36,14 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+VALU_PEAK_GINST = 256 * 4 * 2.4 / 4  # wave64 VALU issue: CUs x SIMDs x GHz / cycles per instruction
 WORKLOADS = {
-    # name: (kind, params)
-    "molecular-28q-sector": ("molecular", dict(n_orb=14, n_alpha=7, n_beta=7, h_seed=2001, psi_seed=2101)),
-    "molecular-12q-sector": ("molecular", dict(n_orb=6, n_alpha=3, n_beta=3, h_seed=1001, psi_seed=1102)),
-    "hubbard-32q-sector": ("hubbard", dict(rows=4, cols=4, n_alpha=8, n_beta=8, psi_seed=4101)),
+    # name: (kind, params); "bound" names the resource that limits the sector apply
+    "molecular-28q-sector": ("molecular", dict(n_orb=14, n_alpha=7, n_beta=7, h_seed=2001, psi_seed=2101,
+                                               bound="alu")),
+    "molecular-12q-sector": ("molecular", dict(n_orb=6, n_alpha=3, n_beta=3, h_seed=1001, psi_seed=1102,
+                                               bound="alu")),
+    "hubbard-32q-sector": ("hubbard", dict(rows=4, cols=4, n_alpha=8, n_beta=8, psi_seed=4101, bound="hbm")),
 }
 
 
@@ -86,9 +93,10 @@ def _connected_groups(x_groups, n_orb, n_alpha, n_beta, weights=None):
     return total / (da * db)
 
 
-def _traffic(kernel_tag):
-    """HBM bytes per launch from committed rocprofv3 counter summaries, or
-    None when absent or taken on a different kernel source."""
+def _counters(kernel_tag):
+    """Committed rocprofv3 counter summary of a kernel (HBM bytes and VALU
+    wave-instructions per launch), or None when absent or taken on a
+    different kernel source."""
     path = os.path.join(ROOT, "profiles", f"{kernel_tag}_counters.json")
     if not os.path.exists(path):
         return None
@@ -96,47 +104,69 @@ def _traffic(kernel_tag):
         rec = json.load(fh)
     if rec.get("source_hash") != _source_hash():
         return None
-    return rec.get("hbm_bytes_per_launch")
+    return rec
 
 
-def cpu_baseline(h1, h2, n_orb, n_alpha, n_beta, psi, budget_s=20.0):
-    """Oracle (plain NumPy, float64, scatter order) on the first K canonical
-    terms over every source configuration; K grows until ~budget_s of work."""
-    from oracle import apply as oapply
+def _host_cpu():
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)), "model": model,
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
+
+
+def cpu_baseline(h1, h2, n_orb, n_alpha, n_beta, psi, target_s=3.0):
+    """The oracle's C twin (float64, term by term in scatter order, OpenMP)
+    timed on a bounded sample of the same workload: every canonical string
+    applied to all configurations of K whole source rows (alpha strings),
+    scattered into the full output.  One warm-up, then the median of three
+    runs, on all the threads OpenMP is given and on one thread; K is sized
+    so that each run takes about target_s seconds."""
     from oracle import jw as ojw
+    from oracle import native
     from oracle import space as ospace
-    from oracle.pauli import PauliSum
 
     op = ojw.jw_sum(h1, h2)
     osp = ospace.SectorSpace(n_orb, n_alpha, n_beta)
+    prep = native.prepare(op, osp)
     psi = np.asarray(psi, dtype=np.complex128)
-    done_terms = 0
-    elapsed = 0.0
-    k = 1
-    while elapsed < budget_s and done_terms < op.n_terms:
-        sub = PauliSum(op.n_qubits, op.letters[done_terms:done_terms + k], op.coeff[done_terms:done_terms + k])
+    rows_all = np.linspace(0, osp.dim_alpha - 1, osp.dim_alpha, dtype=np.int64)
+    rng = np.random.default_rng(0)
+
+    def sources(k):
+        rows = np.sort(rng.choice(rows_all, k, replace=False))
+        return (rows[:, None] * osp.dim_beta + np.arange(osp.dim_beta)[None, :]).reshape(-1)
+
+    def timed(k, threads):
+        src = sources(k)
         t0 = time.perf_counter()
-        oapply.apply_scatter(sub, osp, psi)
-        elapsed += time.perf_counter() - t0
-        done_terms += sub.n_terms
-        k = min(2 * k, 64)
-    rate = osp.dim * done_terms / elapsed
-    return {"value": rate, "unit": "amplitude*terms/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {done_terms} of {op.n_terms} canonical strings applied to all {osp.dim} "
-                      f"sector configurations (NumPy float64 scatter), {elapsed:.1f} s"}
+        _, used = native.apply_scatter(op, osp, psi, sources=src, threads=threads, prepared=prep)
+        return time.perf_counter() - t0, used
 
-
-def batched_jobs():
-    """64 molecular jobs over uneven sectors: job i has n_orb = 10 + i % 4,
-    N_e = n_orb + (-2, -1, 0, 1)[(i // 4) % 4], 2 S_z = N_e % 2 + 2 ((i // 16) % 2),
-    its own integrals (seed 3000 + i) and state (seed 3100 + i)."""
-    out = []
-    for i in range(64):
-        n_orb = 10 + i % 4
-        n_e = n_orb + (-2, -1, 0, 1)[(i // 4) % 4]
-        two_sz = n_e % 2 + 2 * ((i // 16) % 2)
-        out.append((n_orb, (n_e + two_sz) // 2, (n_e - two_sz) // 2, 3000 + i, 3100 + i))
-    return out
+    res = {}
+    for name, threads in (("all", 0), ("one", 1)):
+        dt, used = timed(1, threads)                     # warm-up and size probe
+        k = int(max(1, min(osp.dim_alpha, round(target_s / max(dt, 1e-3)))))
+        runs = sorted(timed(k, threads)[0] for _ in range(3))
+        rate = k * osp.dim_beta * op.n_terms / runs[1]
+        res[name] = (rate, used, k, runs[1])
+    rate, used, k, t_med = res["all"]
+    rate1, _, k1, t1 = res["one"]
+    return {"value": rate, "unit": "amplitude*terms/s", "cores": used, "kind": "oracle",
+            "sample": f"C/OpenMP float64 oracle, scatter order: all {op.n_terms} canonical strings applied to "
+                      f"every configuration of {k} whole source rows ({k * osp.dim_beta} of {osp.dim} "
+                      f"configurations), median of 3 runs ({t_med:.2f} s) on {used} threads",
+            "value_1core": rate1,
+            "sample_1core": f"{k1} source rows, median of 3 runs ({t1:.2f} s) on 1 thread",
+            "full_apply_s_all_threads": osp.dim * op.n_terms / rate,
+            "full_apply_s_1core": osp.dim * op.n_terms / rate1,
+            "host": _host_cpu()}
 
 
 def bench_batched(args):
@@ -149,7 +179,7 @@ def bench_batched(args):
     dev = torch.device("cuda:0")
     jobs32, jobs64, work = [], [], 0.0
     handles = []
-    for n_orb, na, nb, hs, ps in batched_jobs():
+    for n_orb, na, nb, hs, ps in synth.batched_sector_jobs():
         h1, h2 = synth.molecular_spin_integrals(n_orb, hs)
         H = api.jw_transform(torch.from_numpy(h1).to(dev), torch.from_numpy(h2).to(dev))
         G = H.group()
@@ -457,10 +487,38 @@ def main():
     e64 = api.expval(G, sp, psi64).cpu().numpy()
     e32 = api.expval(G, sp, psi32).cpu().numpy()
 
+    # roofline of the dominant kernel.  The sector apply is bound by vector-ALU
+    # issue (one wave64 VALU instruction per 4 cycles per SIMD: 256 CUs x 4
+    # SIMDs x 2.4 GHz / 4 = 614.4 G wave-instructions/s); its VALU count and
+    # HBM bytes per launch come from the committed counter runs of the same
+    # kernel source (null when the kernel has changed since).  The method's
+    # algorithmic gather bytes per launch, D * 8 B * (1 + G_conn), are
+    # reported beside it: most of them are served from LDS and caches.
     bytes_per_launch = D * 8 * (1.0 + g_conn)
-    achieved = bytes_per_launch / (apply_ms * 1e-3) / 1e9
+    gather_gbs = bytes_per_launch / (apply_ms * 1e-3) / 1e9
     kernel_tag = f"apply_sector_c64_{args.workload}"
-    traffic = _traffic(kernel_tag)
+    ctr = _counters(kernel_tag)
+    traffic = ctr.get("hbm_bytes_per_launch") if ctr else None
+    valu = ctr.get("valu_wave_insts_per_launch") if ctr else None
+    valu_peak = VALU_PEAK_GINST
+    if prm["bound"] == "hbm":
+        # bandwidth-bound (few groups per target, rows too long for LDS): the
+        # algorithmic gather bytes against the HBM peak
+        roofline = {"bound": "hbm", "achieved": gather_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": gather_gbs / HBM_PEAK_GBS, "traffic": traffic,
+                    "hbm_GBs": traffic / (apply_ms * 1e-3) / 1e9 if traffic else None,
+                    "valu_frac": valu / (apply_ms * 1e-3) / 1e9 / valu_peak if valu else None,
+                    "apply_ms": apply_ms}
+    else:
+        roofline = {"bound": "alu", "resource": "VALU issue (wave64 instructions)",
+                    "achieved": valu / (apply_ms * 1e-3) / 1e9 if valu else None, "peak": valu_peak,
+                    "unit": "G VALU wave-instructions/s",
+                    "frac": valu / (apply_ms * 1e-3) / 1e9 / valu_peak if valu else None,
+                    "traffic": traffic,
+                    "hbm_GBs": traffic / (apply_ms * 1e-3) / 1e9 if traffic else None,
+                    "hbm_frac": traffic / (apply_ms * 1e-3) / 1e9 / HBM_PEAK_GBS if traffic else None,
+                    "algorithmic_gather_bytes": bytes_per_launch, "algorithmic_gather_GBs": gather_gbs,
+                    "apply_ms": apply_ms}
     line = {
         "metric": "H|psi> amplitude*terms/s (complex64 storage, float64 accumulation)",
         "value": D * M / (ms_step * 1e-3),
@@ -472,14 +530,13 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "complex64 storage, f64 accumulation",
         "data": "synthetic (seeded Gaussian integrals and states)",
         "config": {"workload": args.workload, "n_orb": n_orb, "n_alpha": na, "n_beta": nb, "dim": D,
                    "n_strings": M, "groups_connected_per_target": round(g_conn, 3),
                    "strings_connected_per_target": round(t_conn, 3), "storage": "complex64",
                    "step": "jw_transform+group_by_xmask+space_sector+fused(apply_pauli_sum+expval)"},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
+        "roofline": roofline,
         "apply_ms_c64": c64_ms,
         "apply_ms_c128": c128_ms,
         "apply_rate_c64": D * M / (c64_ms * 1e-3),

@@ -309,7 +309,10 @@ pbs_status pbs_krylov_step(const pbs_grouped* h, const pbs_space* sp, pbs_dtype 
  * its energy <psi|H|psi> (Section 2.1, Eq. vqe_energy).  H must conserve
  * N_alpha and N_beta (a JW Hamiltonian of spin-orbital integrals): the
  * product H|psi> runs through the batched sector kernel over all
- * (N_alpha, N_beta) blocks of the full space.
+ * (N_alpha, N_beta) blocks of the full space.  This is checked on the
+ * grouped terms when the handle is created: an operator with a sector-changing
+ * part (a pairing term, a lone X_p X_q) is refused with PBS_ERR_UNSUPPORTED
+ * rather than having that part dropped.
  *  h      grouped operator on 2 n_orb qubits (1 <= n_orb <= 14), with sector
  *         tables; it must outlive the handle.
  *  n_rot  number of rotations, 0..4096 (PBS_ERR_RANGE beyond).
@@ -426,10 +429,13 @@ pbs_status pbs_mlp_loss_grad(pbs_mlp* m, uint32_t n, const float* x, const float
 
 /* n_steps full-batch Adam steps with learning rate lr on (x, t), continuing
  * the handle's step count; losses (device, n_steps floats, may be NULL)
- * receives the loss before each step.  Asynchronous: nine kernel launches
- * per step on the caller's stream, with the step count kept on the device,
- * so a call allocates nothing, copies nothing and may be captured in a HIP
- * graph by the caller. */
+ * receives the loss before each step of this call.  Asynchronous: a one-thread
+ * kernel marks the start of the call, then nine kernel launches per step on
+ * the caller's stream.  The step count and the call's first step are kept on
+ * the device and loss slots are bounded by n_steps, so a call allocates
+ * nothing, copies nothing and may be captured in a HIP graph by the caller:
+ * each replay, and each direct call after replays, continues the count and
+ * writes losses[0 .. n_steps-1] of its own buffer. */
 pbs_status pbs_mlp_train(pbs_mlp* m, uint32_t n, const float* x, const float* t, uint32_t n_steps, float lr,
                          float* losses, void* stream);
 

@@ -488,12 +488,20 @@ class MLP:
         return loss, g
 
     def train(self, x, t, n_steps, lr):
+        losses = torch.empty(max(1, int(n_steps)), dtype=torch.float32, device="cuda")
+        self.train_into(x, t, n_steps, lr, losses)
+        return losses[:n_steps]
+
+    def train_into(self, x, t, n_steps, lr, losses):
+        """Training call writing the per-step losses into a caller buffer of
+        at least n_steps floats (device); allocates nothing when x and t are
+        contiguous float32 device tensors, so it can be graph-captured."""
         x, n = self._rows(x)
         t = torch.as_tensor(t, dtype=torch.float32, device="cuda").reshape(n, self.n_out).contiguous()
-        losses = torch.empty(max(1, int(n_steps)), dtype=torch.float32, device="cuda")
-        call("pbs_mlp_train", self._h, n, _ptr(x), _ptr(t), int(n_steps), ctypes.c_float(lr), _ptr(losses),
-             _stream())
-        return losses[:n_steps]
+        if losses is not None and losses.numel() < int(n_steps):
+            raise ValueError("losses buffer shorter than n_steps")
+        call("pbs_mlp_train", self._h, n, _ptr(x), _ptr(t), int(n_steps), ctypes.c_float(lr),
+             _ptr(losses) if losses is not None else None, _stream())
 
     def __del__(self):
         h = getattr(self, "_h", None)

@@ -160,7 +160,7 @@ __global__ __launch_bounds__(kMlpBlock) void k_mlp_colsum(const float* __restric
                                                            const float* __restrict__ dy,
                                                            const float* __restrict__ partial, uint32_t n_partial,
                                                            float* __restrict__ grad, float* __restrict__ loss,
-                                                           const uint32_t* __restrict__ steps, uint32_t base) {
+                                                           const uint32_t* __restrict__ steps, uint32_t n_slots) {
   const uint32_t c = blockIdx.x * kMlpBlock + threadIdx.x;
   const size_t off_b1 = H, off_b2 = 3ull * H + static_cast<size_t>(H) * H - H;
   const size_t off_b3 = 3ull * H + static_cast<size_t>(H) * H + static_cast<size_t>(O) * H;
@@ -186,8 +186,10 @@ __global__ __launch_bounds__(kMlpBlock) void k_mlp_colsum(const float* __restric
   } else if (c == 2 * H + O && loss) {
     float s = 0.f;
     for (uint32_t t = 0; t < n_partial; ++t) s += partial[t];
-    // during training, loss[step - base] with the step count kept on the device
-    loss[steps ? *steps - base : 0u] = s / (static_cast<float>(n) * static_cast<float>(O));
+    // during training, loss[steps[0] - steps[1]]: the step count and the
+    // count at the start of the current call, both kept on the device
+    const uint32_t slot = steps ? steps[0] - steps[1] : 0u;
+    if (slot < n_slots) loss[slot] = s / (static_cast<float>(n) * static_cast<float>(O));
   }
 }
 
@@ -218,7 +220,12 @@ __global__ __launch_bounds__(kMlpBlock) void k_mlp_adam(float* __restrict__ p, c
 }
 
 __global__ void k_mlp_tick(uint32_t* steps) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *steps += 1u;
+  if (threadIdx.x == 0 && blockIdx.x == 0) steps[0] += 1u;
+}
+
+// Start of a training call: the loss slots of the call count from here.
+__global__ void k_mlp_mark(uint32_t* steps) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) steps[1] = steps[0];
 }
 
 __global__ __launch_bounds__(kMlpBlock) void k_mlp_refresh(const float* __restrict__ p, uint64_t off_w2,
@@ -244,11 +251,11 @@ using namespace pbs;
 struct pbs_mlp {
   uint32_t H = 0, O = 0, Op = 0, max_rows = 0;
   uint64_t count = 0, off_w2 = 0, off_b2 = 0, off_w3 = 0, off_b3 = 0;
-  uint64_t step = 0;  // Adam steps taken (host copy of *steps)
+  uint64_t step = 0;  // Adam steps requested through direct calls (a bound, not the count)
   DevBuf<float> params, grads, mom1, mom2;
   DevBuf<uint16_t> w2b, w3b;
   DevBuf<float> h1, h2, dy, dz2, dz1, partial, loss;
-  DevBuf<uint32_t> steps;  // Adam steps taken, on the device
+  DevBuf<uint32_t> steps;  // [Adam steps taken, steps taken when the current call began], on the device
   DevBuf<uint16_t> h1b, h2b, dyb, dz2b;
 };
 
@@ -308,7 +315,7 @@ void forward(pbs_mlp& m, uint32_t n, const float* x, float* y, const float* t, h
 }
 
 // Backward pass after forward(..., t): gradients into grad (packed layout).
-void backward(pbs_mlp& m, uint32_t n, const float* x, float* grad, float* loss, const uint32_t* steps, uint32_t base,
+void backward(pbs_mlp& m, uint32_t n, const float* x, float* grad, float* loss, const uint32_t* steps, uint32_t n_slots,
               hipStream_t s) {
   const uint32_t rows = round_up32(n), H = m.H, Op = m.Op;
   // dW3[j][k] = sum_b dy[b][j] h2[b][k]
@@ -376,7 +383,7 @@ void backward(pbs_mlp& m, uint32_t n, const float* x, float* grad, float* loss, 
   const uint32_t cols = 2 * H + m.O + 1;
   hipLaunchKernelGGL(k_mlp_colsum, dim3((cols + kMlpBlock - 1) / kMlpBlock), dim3(kMlpBlock), 0, s, x, n, rows, H,
                      m.O, Op, m.dz1.get(), m.dz2.get(), m.dy.get(), m.partial.get(), (rows / 16) * (Op / 16), grad,
-                     loss, steps, base);
+                     loss, steps, n_slots);
 }
 
 void adam(pbs_mlp& m, float lr, hipStream_t s) {
@@ -387,11 +394,12 @@ void adam(pbs_mlp& m, float lr, hipStream_t s) {
   hipLaunchKernelGGL(k_mlp_tick, dim3(1), dim3(64), 0, s, m.steps.get());
 }
 
-// One training step: forward, backward (loss into losses[step - base]), Adam.
-void train_step(pbs_mlp& m, uint32_t n, const float* x, const float* t, float lr, float* losses, uint32_t base,
+// One training step: forward, backward (loss into the call's next slot of
+// losses, of which there are n_slots), Adam.
+void train_step(pbs_mlp& m, uint32_t n, const float* x, const float* t, float lr, float* losses, uint32_t n_slots,
                 hipStream_t s) {
   forward(m, n, x, nullptr, t, s);
-  backward(m, n, x, m.grads.get(), losses, losses ? m.steps.get() : nullptr, base, s);
+  backward(m, n, x, m.grads.get(), losses, losses ? m.steps.get() : nullptr, n_slots, s);
   adam(m, lr, s);
 }
 
@@ -399,7 +407,7 @@ void load_params(pbs_mlp& m, const float* params, hipStream_t s) {
   PBS_HIP(hipMemcpyAsync(m.params.get(), params, m.count * sizeof(float), hipMemcpyDefault, s));
   PBS_HIP(hipMemsetAsync(m.mom1.get(), 0, m.count * sizeof(float), s));
   PBS_HIP(hipMemsetAsync(m.mom2.get(), 0, m.count * sizeof(float), s));
-  PBS_HIP(hipMemsetAsync(m.steps.get(), 0, sizeof(uint32_t), s));
+  PBS_HIP(hipMemsetAsync(m.steps.get(), 0, 2 * sizeof(uint32_t), s));
   m.step = 0;
   const uint64_t n2 = static_cast<uint64_t>(m.H) * m.H, n3 = static_cast<uint64_t>(m.O) * m.H;
   hipLaunchKernelGGL(k_mlp_refresh, dim3(grid_for(n2 + n3, kMlpBlock, 1024)), dim3(kMlpBlock), 0, s,
@@ -467,7 +475,7 @@ pbs_status pbs_mlp_create(uint32_t hidden, uint32_t n_out, uint32_t max_batch, c
       m->dyb.alloc(outs);
       m->partial.alloc((R / 16) * (Op / 16));
       m->loss.alloc(1);
-      m->steps.alloc(1);
+      m->steps.alloc(2);
       load_params(*m, params, s);
       PBS_HIP(hipStreamSynchronize(s));
     } catch (...) {
@@ -510,7 +518,7 @@ pbs_status pbs_mlp_loss_grad(pbs_mlp* m, uint32_t n, const float* x, const float
     PBS_REQUIRE(x != nullptr && t != nullptr && grad != nullptr, PBS_ERR_ARG, "null argument");
     hipStream_t s = as_stream(stream);
     forward(*m, n, x, nullptr, t, s);
-    backward(*m, n, x, grad, loss, nullptr, 0u, s);
+    backward(*m, n, x, grad, loss, nullptr, 1u, s);
     PBS_HIP(hipGetLastError());
   });
 }
@@ -523,8 +531,8 @@ pbs_status pbs_mlp_train(pbs_mlp* m, uint32_t n, const float* x, const float* t,
     PBS_REQUIRE(lr > 0.f && std::isfinite(lr), PBS_ERR_ARG, "learning rate must be positive");
     PBS_REQUIRE(m->step + n_steps < (1ull << 32), PBS_ERR_RANGE, "step count beyond 2^32");
     hipStream_t s = as_stream(stream);
-    const uint32_t base = static_cast<uint32_t>(m->step);
-    for (uint32_t i = 0; i < n_steps; ++i) train_step(*m, n, x, t, lr, losses, base, s);
+    hipLaunchKernelGGL(k_mlp_mark, dim3(1), dim3(64), 0, s, m->steps.get());
+    for (uint32_t i = 0; i < n_steps; ++i) train_step(*m, n, x, t, lr, losses, n_steps, s);
     m->step += n_steps;
     PBS_HIP(hipGetLastError());
   });

@@ -10,6 +10,8 @@
 // launch, and permuting back.  Rotations and overlaps are bandwidth-bound
 // passes over the full-space vectors.
 #include <algorithm>
+#include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <vector>
 
@@ -383,6 +385,79 @@ __global__ __launch_bounds__(kBlock) void k_fock_permute(const T* __restrict__ i
 
 Rot rot_of(uint64_t x, uint64_t z) { return Rot{x, z, static_cast<uint32_t>(__builtin_popcountll(x & z) & 3)}; }
 
+// Whether H conserves N_alpha and N_beta (H commutes with both), decided on
+// the grouped XZ form.  Group g couples s to t = s ^ X_g with matrix element
+// f_g(s) = sum_k C_k (-1)^popcount(Z_k & s).  The numbers are conserved iff
+// f_g(s) = 0 for every s on which X_g flips unequal numbers of set and unset
+// bits in either half; that set depends only on the bits of s inside X_g, so
+// splitting Z_k into its parts inside and outside X_g (the characters of the
+// outside bits are independent) leaves, per distinct outside part, a function
+// of the |X_g| inside bits to evaluate at every bad pattern.  Sums that cancel
+// are accepted up to 1e-12 of the absolute coefficient sum (rounding).
+bool conserves_spin_numbers(const pbs_grouped& h, hipStream_t s, std::string* why) {
+  const uint32_t n = h.half;
+  std::vector<uint64_t> xg(h.n_groups), zk(h.n_terms);
+  std::vector<uint32_t> off(h.n_groups + 1);
+  std::vector<double> ck(2 * h.n_terms);
+  PBS_HIP(hipMemcpyAsync(xg.data(), h.xg.get(), xg.size() * 8, hipMemcpyDeviceToHost, s));
+  PBS_HIP(hipMemcpyAsync(off.data(), h.off.get(), off.size() * 4, hipMemcpyDeviceToHost, s));
+  PBS_HIP(hipMemcpyAsync(zk.data(), h.zk.get(), zk.size() * 8, hipMemcpyDeviceToHost, s));
+  PBS_HIP(hipMemcpyAsync(ck.data(), h.ck.get(), ck.size() * 8, hipMemcpyDeviceToHost, s));
+  PBS_HIP(hipStreamSynchronize(s));
+  const uint64_t mask = (1ull << n) - 1ull;
+  for (uint64_t g = 0; g < h.n_groups; ++g) {
+    const uint64_t x = xg[g];
+    if (x == 0) continue;  // diagonal
+    const int fa = __builtin_popcountll(x & mask), fb = __builtin_popcountll(x >> n);
+    const int m = fa + fb;
+    if (m > 20) {
+      *why = "a group flips more than 20 qubits; conservation of N_alpha and N_beta cannot be checked";
+      return false;
+    }
+    uint32_t bit[64];
+    for (int i = 0, q = 0; q < 64; ++q)
+      if ((x >> q) & 1ull) bit[i++] = static_cast<uint32_t>(q);
+    // inside patterns u (bit i of u = qubit bit[i] of s) that change N_alpha or N_beta
+    std::vector<uint32_t> bad;
+    for (uint32_t u = 0; u < (1u << m); ++u) {
+      const int ua = __builtin_popcount(u & ((1u << fa) - 1u)), ub = __builtin_popcount(u >> fa);
+      if (2 * ua != fa || 2 * ub != fb) bad.push_back(u);
+    }
+    // terms of the group ordered by their Z part outside X
+    std::vector<uint32_t> ks;
+    for (uint32_t k = off[g]; k < off[g + 1]; ++k) ks.push_back(k);
+    std::stable_sort(ks.begin(), ks.end(), [&](uint32_t a, uint32_t b) { return (zk[a] & ~x) < (zk[b] & ~x); });
+    for (size_t i0 = 0; i0 < ks.size();) {
+      size_t i1 = i0;
+      double scale = 0.0;
+      while (i1 < ks.size() && (zk[ks[i1]] & ~x) == (zk[ks[i0]] & ~x)) {
+        scale += std::fabs(ck[2 * ks[i1]]) + std::fabs(ck[2 * ks[i1] + 1]);
+        ++i1;
+      }
+      for (uint32_t u : bad) {
+        double fr = 0.0, fi = 0.0;
+        for (size_t i = i0; i < i1; ++i) {
+          const uint64_t zin = zk[ks[i]] & x;
+          int par = 0;
+          for (int b = 0; b < m; ++b) par ^= static_cast<int>(((u >> b) & 1u) & ((zin >> bit[b]) & 1ull));
+          fr += par ? -ck[2 * ks[i]] : ck[2 * ks[i]];
+          fi += par ? -ck[2 * ks[i] + 1] : ck[2 * ks[i] + 1];
+        }
+        if (std::fabs(fr) + std::fabs(fi) > 1e-12 * scale) {
+          char buf[96];
+          std::snprintf(buf, sizeof(buf), "the group with X mask 0x%llx changes N_alpha or N_beta",
+                        static_cast<unsigned long long>(x));
+          *why = buf;
+          return false;
+        }
+      }
+      i0 = i1;
+    }
+  }
+  return true;
+}
+
+
 // True when exchanging the two qubit halves maps the operator onto itself
 // term by term (bit-identical coefficients), as for the Jordan-Wigner
 // Hamiltonian of spin-free integrals.  Then H = S H S for the half-exchange
@@ -612,6 +687,10 @@ pbs_status pbs_vqe_create(const pbs_grouped* h, uint32_t n_orb, uint32_t n_rot, 
       std::vector<uint64_t> off((n_orb + 1) * (n_orb + 1), 0);
       std::vector<uint32_t> bn(n_orb + 1);
       for (uint32_t k = 0; k <= n_orb; ++k) bn[k] = static_cast<uint32_t>(host_binom(n_orb, k));
+      std::string why;
+      PBS_REQUIRE(conserves_spin_numbers(*h, s, &why), PBS_ERR_UNSUPPORTED,
+                  "the energy is evaluated block by block over (N_alpha, N_beta) sectors, which needs an operator "
+                  "that conserves N_alpha and N_beta: " + why);
       const bool sym = halves_symmetric(*h, s);
       std::vector<const pbs_grouped*> hs;
       std::vector<const pbs_space*> sps;

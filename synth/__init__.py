@@ -277,3 +277,18 @@ def mlp_init(hidden, n_out, seed):
     parts = [rng.uniform(-4, 4, H), rng.uniform(-2, 2, H), rng.uniform(-a, a, H * H), np.zeros(H),
              rng.uniform(-0.1 * a, 0.1 * a, O * H), np.zeros(O)]
     return np.concatenate(parts).astype(np.float32)
+
+
+def batched_sector_jobs(n_jobs=64):
+    """Uneven sector jobs of the batched workload: job i has n_orb = 10 + i % 4,
+    N_e = n_orb + (-2, -1, 0, 1)[(i // 4) % 4] electrons,
+    2 S_z = N_e % 2 + 2 ((i // 16) % 2), its own integrals (seed 3000 + i) and
+    its own state (seed 3100 + i).  Returns (n_orb, N_alpha, N_beta,
+    integral seed, state seed) per job."""
+    out = []
+    for i in range(n_jobs):
+        n_orb = 10 + i % 4
+        n_e = n_orb + (-2, -1, 0, 1)[(i // 4) % 4]
+        two_sz = n_e % 2 + 2 * ((i // 16) % 2)
+        out.append((n_orb, (n_e + two_sz) // 2, (n_e - two_sz) // 2, 3000 + i, 3100 + i))
+    return out

@@ -93,6 +93,24 @@ def test_twelve_qubit_molecular_full_and_sector(dev):
         assert abs(e32[0] - e32_ref.real) < 1e-10 * abs(e32_ref)
 
 
+def _sector_compatible_op(n_o, seed, m=400):
+    """Random non-conserving operator on 2 n_o qubits whose strings mostly
+    (~70%) flip an even number of orbitals in each spin half, so that a
+    sector sees nonzero coupling."""
+    n = 2 * n_o
+    rng = np.random.default_rng(seed)
+    letters, _ = synth.random_pauli_strings(m, n, seed=n_o + 7)
+    for k in range(m):
+        if rng.random() < 0.7:
+            for half in (0, 1):
+                cols = np.arange(half * n_o, (half + 1) * n_o)
+                flips = cols[(letters[k, cols] == 1) | (letters[k, cols] == 2)]
+                if len(flips) % 2 == 1:
+                    letters[k, flips[0]] = 3
+    coeff = rng.standard_normal(m) + 1j * rng.standard_normal(m)
+    return opauli.PauliSum(n, letters, coeff)
+
+
 @pytest.mark.parametrize("n_o,na,nb", [(1, 0, 1), (1, 1, 1), (3, 1, 2), (4, 0, 4), (5, 2, 3), (9, 4, 5),
                                        (11, 5, 5), (12, 6, 6), (13, 6, 6), (15, 1, 7), (16, 1, 8)])
 def test_sector_projection_random_operator(dev, n_o, na, nb):
@@ -102,20 +120,7 @@ def test_sector_projection_random_operator(dev, n_o, na, nb):
     (several lanes per thread, ragged tails; rows of 6,435 and 12,870
     columns exceed LDS and are staged in tiles)."""
     api = _api()
-    n = 2 * n_o
-    rng = np.random.default_rng(n_o * 31 + na)
-    m = 400
-    letters, _ = synth.random_pauli_strings(m, n, seed=n_o + 7)
-    # make ~70% of the strings sector-compatible: pair up X/Y flips within each spin
-    for k in range(m):
-        if rng.random() < 0.7:
-            for half in (0, 1):
-                cols = np.arange(half * n_o, (half + 1) * n_o)
-                flips = cols[(letters[k, cols] == 1) | (letters[k, cols] == 2)]
-                if len(flips) % 2 == 1:
-                    letters[k, flips[0]] = 3
-    coeff = rng.standard_normal(m) + 1j * rng.standard_normal(m)
-    op = opauli.PauliSum(n, letters, coeff)
+    op = _sector_compatible_op(n_o, n_o * 31 + na)
     osp = ospace.SectorSpace(n_o, na, nb)
     G = _gpu_op(dev, op)
     sp = api.Space.sector(n_o, na, nb)
@@ -128,6 +133,54 @@ def test_sector_projection_random_operator(dev, n_o, na, nb):
         got = _run(dev, G, sp, psi, np.complex128)[sel]
         ref = oapply.apply_targets(op, osp, psi, sel)
         assert rel_err(got, ref) < 1e-12
+
+
+@pytest.mark.parametrize("n_o,na,nb", [(17, 1, 1), (20, 1, 2), (24, 2, 1)])
+def test_sector_above_sixteen_orbitals(dev, n_o, na, nb):
+    """More than 16 orbitals: spin strings are ranked through the global
+    rank tables (the kernel variants without LDS rank tables); both storage
+    types, the plain apply and the fused energy, against the oracle."""
+    api = _api()
+    op = _sector_compatible_op(n_o, n_o * 17 + nb)
+    osp = ospace.SectorSpace(n_o, na, nb)
+    G = _gpu_op(dev, op)
+    sp = api.Space.sector(n_o, na, nb)
+    psi = synth.random_state(osp.dim, seed=n_o + 200)
+    ref = oapply.apply_scatter(op, osp, psi)
+    assert rel_err(_run(dev, G, sp, psi, np.complex128), ref) < 1e-12
+    psi32 = psi.astype(np.complex64)
+    ref32 = oapply.apply_scatter(op, osp, psi32.astype(np.complex128))
+    assert rel_err(_run(dev, G, sp, psi32, np.complex64), ref32) < 1e-6
+    for p, r, tol in ((psi, ref, 1e-12), (psi32.astype(np.complex128), ref32, 1e-10)):
+        for dt in ((torch.complex128,) if tol == 1e-12 else (torch.complex64,)):
+            e = api.expval(G, sp, torch.from_numpy(p).to(dev).to(dt)).cpu().numpy()
+            e_ref = np.vdot(p, r)
+            assert abs(e[0] - e_ref.real) < tol * max(1.0, abs(e_ref))
+            assert abs(e[1] - e_ref.imag) < tol * max(1.0, abs(e_ref))
+
+
+def test_batch_mixes_orbital_counts_above_and_below_sixteen(dev):
+    """One launch over jobs with n_orb <= 16 and > 16 takes the global rank
+    tables for all of them; each job still matches the oracle."""
+    api = _api()
+    specs = [(6, 3, 2, 61), (17, 1, 1, 62), (9, 4, 4, 63), (20, 2, 1, 64)]
+    jobs, refs = [], []
+    for n_o, na, nb, seed in specs:
+        op = _sector_compatible_op(n_o, seed)
+        osp = ospace.SectorSpace(n_o, na, nb)
+        psi = synth.random_state(osp.dim, seed=seed + 1)
+        t = torch.from_numpy(psi).to(dev)
+        jobs.append((_gpu_op(dev, op), api.Space.sector(n_o, na, nb), t, torch.empty_like(t)))
+        refs.append((psi, oapply.apply_scatter(op, osp, psi)))
+    batch = api.Batch(jobs)
+    energies = torch.zeros(3 * len(jobs), dtype=torch.float64, device=dev)
+    batch.run(energies)
+    torch.cuda.synchronize()
+    e = energies.cpu().numpy().reshape(-1, 3)
+    for k, ((_, _, _, out), (psi, ref)) in enumerate(zip(jobs, refs)):
+        assert rel_err(out.cpu().numpy(), ref) < 1e-12, f"job {k}"
+        e_ref = np.vdot(psi, ref)
+        assert abs(e[k, 0] - e_ref.real) < 1e-12 * max(1.0, abs(e_ref)), f"job {k}"
 
 
 def test_twenty_qubit_molecular_sector(dev):
@@ -190,72 +243,3 @@ def test_argument_errors(dev):
         api.expval(G, sp, psi, work=work)
     with pytest.raises(PbsError, match="overlaps"):
         api.expval(G, sp, psi, out=psi)
-
-
-def _sampled_targets(rng, dim, k, extra=()):
-    sel = set(int(v) for v in rng.integers(0, dim, k))
-    sel.update(int(v) for v in extra)
-    return np.array(sorted(sel), dtype=np.int64)
-
-
-def test_28_qubit_sector_sampled(dev):
-    """Full-size molecular workload: n_orb = 14, (7, 7) sector, D = 11,778,624,
-    in the launch configuration the benchmark uses; sampled outputs against
-    the oracle's one-by-one targets, plus Hermiticity and the energy."""
-    api = _api()
-    h1, h2 = synth.molecular_spin_integrals(14, seed=2001)
-    H = api.jw_transform(torch.from_numpy(h1).to(dev), torch.from_numpy(h2).to(dev))
-    G = H.group()
-    sp = api.Space.sector(14, 7, 7)
-    osp = ospace.SectorSpace(14, 7, 7)
-    assert sp.dim == 11_778_624
-    op = ojw.jw_sum(h1, h2)
-    psi = synth.random_state(sp.dim, seed=2101)
-    rng = np.random.default_rng(3)
-    sel = _sampled_targets(rng, sp.dim, 48, extra=[0, sp.dim - 1, 3431, 3432])
-    ref = oapply.apply_targets(op, osp, psi, sel)
-    tpsi = torch.from_numpy(psi).to(dev)
-    out = api.apply_pauli_sum(G, sp, tpsi)
-    assert rel_err(out[torch.from_numpy(sel).to(dev)].cpu().numpy(), ref) < 1e-12
-    psi32 = psi.astype(np.complex64)
-    ref32 = oapply.apply_targets(op, osp, psi32, sel)
-    t32 = torch.from_numpy(psi32).to(dev)
-    out32 = api.apply_pauli_sum(G, sp, t32)
-    assert rel_err(out32[torch.from_numpy(sel).to(dev)].cpu().numpy(), ref32) < 1e-6
-    # whole-vector properties: Hermiticity and the fused energy
-    phi = torch.from_numpy(synth.random_state(sp.dim, seed=2102)).to(dev)
-    hphi = api.apply_pauli_sum(G, sp, phi)
-    lhs = torch.vdot(phi, out).item()
-    rhs = torch.vdot(tpsi, hphi).item().conjugate()
-    assert abs(lhs - rhs) < 1e-11 * max(1.0, abs(lhs))
-    e = api.expval(G, sp, tpsi).cpu().numpy()
-    e_dot = torch.vdot(tpsi, out).item()
-    assert abs(e[0] - e_dot.real) < 1e-11 * abs(e_dot) and abs(e[1]) < 1e-11 * abs(e_dot)
-    fused32 = torch.empty_like(t32)
-    e32 = api.expval(G, sp, t32, out=fused32).cpu().numpy()
-    assert torch.equal(torch.view_as_real(fused32), torch.view_as_real(out32))
-    h32 = api.apply_pauli_sum(G, sp, t32.to(torch.complex128))
-    e32_dot = torch.vdot(t32.to(torch.complex128), h32).item()
-    assert abs(e32[0] - e32_dot.real) < 1e-11 * abs(e32_dot)
-
-
-def test_32_qubit_hubbard_sampled(dev):
-    """4x4 periodic Hubbard model, (8, 8) sector, D = 165,636,900 (complex64
-    1.33 GB); sampled outputs against the oracle."""
-    api = _api()
-    h1, h2 = synth.hubbard_spin_integrals(4, 4)
-    G = api.jw_transform(torch.from_numpy(h1).to(dev), torch.from_numpy(h2).to(dev)).group()
-    sp = api.Space.sector(16, 8, 8)
-    osp = ospace.SectorSpace(16, 8, 8)
-    assert sp.dim == 165_636_900
-    op = ojw.jw_sum(h1, h2)
-    psi32 = synth.random_state(sp.dim, seed=4101).astype(np.complex64)
-    sel = _sampled_targets(np.random.default_rng(4), sp.dim, 64, extra=[0, sp.dim - 1, 12869, 12870])
-    ref = oapply.apply_targets(op, osp, psi32, sel)
-    t32 = torch.from_numpy(psi32).to(dev)
-    out = api.apply_pauli_sum(G, sp, t32)
-    assert rel_err(out[torch.from_numpy(sel).to(dev)].cpu().numpy(), ref) < 1e-6
-    del out
-    t64 = t32.to(torch.complex128)
-    out64 = api.apply_pauli_sum(G, sp, t64)
-    assert rel_err(out64[torch.from_numpy(sel).to(dev)].cpu().numpy(), ref) < 1e-12

@@ -132,15 +132,53 @@ def test_training_runs_match_single_steps(dev):
     p = synth.mlp_init(H, O, seed=21)
     x, t = _data(n, O, seed=22)
     xs, ts = torch.from_numpy(x).to(dev), torch.from_numpy(t).to(dev)
-    graph_net, eager_net = api.MLP(H, O, n, p), api.MLP(H, O, n, p)
-    graph_losses, eager_losses = [], []
+    run_net, eager_net = api.MLP(H, O, n, p), api.MLP(H, O, n, p)
+    run_losses, eager_losses = [], []
     for run in (20, 9):
-        graph_losses.append(graph_net.train(xs, ts, run, 2e-3).cpu().numpy())
-        graph_net.forward(xs)
+        run_losses.append(run_net.train(xs, ts, run, 2e-3).cpu().numpy())
+        run_net.forward(xs)
         for _ in range(run):
             eager_losses.append(eager_net.train(xs, ts, 1, 2e-3).cpu().numpy())
         eager_net.forward(xs)
     torch.cuda.synchronize()
-    np.testing.assert_array_equal(graph_net.params(), eager_net.params())
-    np.testing.assert_array_equal(np.concatenate(graph_losses), np.concatenate(eager_losses))
-    assert not np.array_equal(graph_net.params(), p)
+    np.testing.assert_array_equal(run_net.params(), eager_net.params())
+    np.testing.assert_array_equal(np.concatenate(run_losses), np.concatenate(eager_losses))
+    assert not np.array_equal(run_net.params(), p)
+
+
+def test_captured_training_replays_continue_the_count(dev):
+    """A training call captured in a HIP graph and replayed several times,
+    then called directly: every replay and call writes its losses into slots
+    0..n_steps-1 of its own buffer (nothing past them), and parameters and
+    losses equal those of the same calls made directly, bit for bit."""
+    api = _api()
+    H, O, n, k = 64, 20, 12, 3
+    p = synth.mlp_init(H, O, seed=31)
+    x, t = _data(n, O, seed=32)
+    xs, ts = torch.from_numpy(x).to(dev), torch.from_numpy(t).to(dev)
+    cap_net, eager_net = api.MLP(H, O, n, p), api.MLP(H, O, n, p)
+    guard = 5
+    buf = torch.full((k + guard,), float("nan"), dtype=torch.float32, device=dev)
+    torch.cuda.synchronize()
+    stream = torch.cuda.Stream()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(stream):
+        with torch.cuda.graph(graph, stream=stream):
+            cap_net.train_into(xs, ts, k, 2e-3, buf)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        buf.fill_(float("nan"))
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        want = eager_net.train(xs, ts, k, 2e-3).cpu().numpy()
+        got = buf.cpu().numpy()
+        np.testing.assert_array_equal(got[:k], want, err_msg=f"replay {rep}")
+        assert np.isnan(got[k:]).all(), f"replay {rep} wrote past its losses"
+    direct = torch.full((2 + guard,), float("nan"), dtype=torch.float32, device=dev)
+    cap_net.train_into(xs, ts, 2, 2e-3, direct)
+    want = eager_net.train(xs, ts, 2, 2e-3).cpu().numpy()
+    got = direct.cpu().numpy()
+    np.testing.assert_array_equal(got[:2], want)
+    assert np.isnan(got[2:]).all()
+    np.testing.assert_array_equal(cap_net.params(), eager_net.params())

@@ -218,3 +218,35 @@ def test_vqe_fusion_depths_agree(dev, dtype):
         assert len(set(energies)) == 1
     with pytest.raises(Exception, match="1, 2 or 3"):
         v.set_groups(4, 1)
+
+
+@pytest.mark.parametrize("extra", ["pairing", "lone_hop"])
+def test_vqe_refuses_sector_changing_operators(dev, extra):
+    """The energy runs block by block over (N_alpha, N_beta) sectors, so an
+    operator with a part that changes N_alpha or N_beta must be refused, not
+    silently truncated: a pairing term a+_{0a} a+_{0b} + h.c. (JW: X_0 X_n and
+    Y_0 Y_n parts with the Z string between) and a lone X_0 X_1 (an alpha hop
+    without its Y_0 Y_1 partner).  The conserving operator is accepted."""
+    api = _api()
+    from paper_2606_28952_amd._abi import PbsError
+
+    n_orb = 3
+    h1, h2 = synth.molecular_spin_integrals(n_orb, seed=77)
+    op = ojw.jw_sum(h1, h2)
+    x, z = op.xz()
+    G_ok = api.PauliSum.create(2 * n_orb, x.reshape(-1), z.reshape(-1), op.coeff)
+    G_ok.canonicalize()
+    api.VQE(G_ok.group(), n_orb, np.zeros(0, np.uint64), np.zeros(0, np.uint64), 0b111)
+    n = 2 * n_orb
+    if extra == "pairing":
+        zs = sum(1 << q for q in range(1, n_orb))  # JW string between qubit 0 and qubit n_orb
+        add = [((1 << 0) | (1 << n_orb), zs, 0.3), ((1 << 0) | (1 << n_orb), zs | 1 | (1 << n_orb), -0.3)]
+    else:
+        add = [(0b11, 0, 0.2)]
+    xs = np.concatenate([x.reshape(-1), np.array([a[0] for a in add], np.uint64)])
+    zz = np.concatenate([z.reshape(-1), np.array([a[1] for a in add], np.uint64)])
+    cc = np.concatenate([op.coeff, np.array([a[2] for a in add], np.complex128)])
+    S = api.PauliSum.create(n, xs, zz, cc)
+    S.canonicalize()
+    with pytest.raises(PbsError, match="N_alpha and N_beta"):
+        api.VQE(S.group(), n_orb, np.zeros(0, np.uint64), np.zeros(0, np.uint64), 0b111)
