@@ -221,6 +221,24 @@ pbs_status pbs_expval_workspace_bytes(const pbs_space* sp, uint64_t* bytes);
 pbs_status pbs_expval(const pbs_grouped* h, const pbs_space* sp, pbs_dtype dt, const void* psi, void* out,
                       double* result, void* work, uint64_t work_bytes, void* stream);
 
+/* Size of the fixed device workspace behind pbs_expval_noalloc. */
+#define PBS_EXPVAL_NOALLOC_MAX_BYTES (8u * 1024u * 1024u)
+
+/* pbs_expval without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, kernels and results as pbs_expval
+ * (bit-identical); the per-workgroup energy partials go to a fixed array of
+ * PBS_EXPVAL_NOALLOC_MAX_BYTES that the library holds on each device until
+ * the process ends.  Spaces whose partials exceed it
+ * (pbs_expval_workspace_bytes > PBS_EXPVAL_NOALLOC_MAX_BYTES) are refused
+ * with PBS_ERR_RANGE before anything is enqueued.  Every call on one device
+ * shares that device's array: calls that overlap on one device (concurrent
+ * streams, or host threads racing on one stream) race on it, so serialize
+ * them.  The first call on each device looks up the array's address (no
+ * allocation).  Asynchronous; calls no allocating routine. */
+pbs_status pbs_expval_noalloc(const pbs_grouped* h, const pbs_space* sp, pbs_dtype dt, const void* psi, void* out,
+                              double* result, void* stream);
+
 /* ------------------------------------------------------------------ batched apply */
 
 /* Prepares one launch that applies n operators to n states in spin sectors:

@@ -16,7 +16,7 @@ from . import _abi
 from ._abi import PBS_C64, PBS_C128, call
 
 __all__ = [
-    "PauliSum", "Grouped", "Space", "pauli_mul", "jw_transform", "apply_pauli_sum", "expval",
+    "PauliSum", "Grouped", "Space", "pauli_mul", "jw_transform", "apply_pauli_sum", "expval", "expval_noalloc",
     "words_for", "PBS_C64", "PBS_C128", "KrylovPropagator", "Batch", "VQE", "MLP", "lbfgs_minimize",
     "STOP_REASONS",
 ]
@@ -258,6 +258,18 @@ def expval(grouped, space, psi, work=None, result=None, out=None):
         result = torch.empty(3, dtype=torch.float64, device=psi.device)
     call("pbs_expval", grouped._h, space._h, _dtype_code(psi), _ptr(psi), _ptr(out), _ptr(result), _ptr(work),
          work.numel() * 8, _stream())
+    return result
+
+
+def expval_noalloc(grouped, space, psi, result, out=None):
+    """expval with the library's fixed device workspace instead of a caller
+    workspace; ``result`` (3 float64 on the device) is caller-owned, so the
+    call itself allocates nothing.  Calls on one device must not overlap."""
+    _check_states(space, psi, out)
+    if result.dtype != torch.float64 or result.numel() < 3 or result.device != psi.device:
+        raise ValueError("result must be a float64 device tensor of at least 3 values")
+    call("pbs_expval_noalloc", grouped._h, space._h, _dtype_code(psi), _ptr(psi), _ptr(out), _ptr(result),
+         _stream())
     return result
 
 

@@ -2,6 +2,8 @@
 // sectors Eq. sreverse_sum) and the fused energy of Eq. vqe_energy: the
 // full-space kernel, launch planning of the sector kernels (whose device code
 // lives in sector.h), and the C ABI entry points, single and batched.
+#include <mutex>
+
 #include "sector.h"
 
 namespace pbs {
@@ -196,6 +198,33 @@ Launch plan_sector(const pbs_grouped& h, const pbs_space& sp, size_t elem_bytes,
 
 constexpr unsigned kFullGridCap = 1u << 16;
 
+// Fixed workspace of pbs_expval_noalloc (per-workgroup energy partials): one
+// copy per device, alive until the process ends.  Host code never uses the
+// array's name as an address; it uses the device address looked up once per
+// device by noalloc_scratch().
+static_assert(PBS_EXPVAL_NOALLOC_MAX_BYTES % 256 == 0, "workspace size");
+static __device__ __align__(256) double scratch[PBS_EXPVAL_NOALLOC_MAX_BYTES / sizeof(double)];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up on the first
+// call on each device, with that device current).
+double* noalloc_scratch() {
+  int dev = 0;
+  PBS_HIP(hipGetDevice(&dev));
+  PBS_REQUIRE(dev >= 0 && dev < kMaxDevices, PBS_ERR_RANGE, "device ordinal beyond the fixed workspace table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void* p = nullptr;
+    PBS_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    PBS_REQUIRE(p != nullptr, PBS_ERR_DEVICE, "no device address for the fixed workspace");
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  return g_scratch_ptr[dev];
+}
+
 uint64_t partial_count(const pbs_space& sp) {
   if (!sp.sector) return grid_for(sp.dim, kBlock, kFullGridCap);
   return sp.dim_alpha * ((sp.dim_beta + kSB - 1) / kSB);
@@ -291,6 +320,31 @@ pbs_status pbs_expval(const pbs_grouped* h, const pbs_space* sp, pbs_dtype dt, c
                 "workspace of " + std::to_string(work_bytes) + " bytes, need " + std::to_string(need));
     hipStream_t s = as_stream(stream);
     double* partial = static_cast<double*>(work);
+    if (dt == PBS_C128)
+      launch<double2, true>(*h, *sp, psi, out, partial, s);
+    else
+      launch<float2, true>(*h, *sp, psi, out, partial, s);
+    hipLaunchKernelGGL(k_expval_finish, dim3(1), dim3(kBlock), 0, s, partial, partial_count(*sp), result);
+    PBS_HIP(hipGetLastError());
+  });
+}
+
+pbs_status pbs_expval_noalloc(const pbs_grouped* h, const pbs_space* sp, pbs_dtype dt, const void* psi, void* out,
+                              double* result, void* stream) {
+  return guarded([&] {
+    validate(h, sp, dt);
+    PBS_REQUIRE(psi != nullptr && result != nullptr, PBS_ERR_ARG, "null pointer");
+    if (out) {
+      const uint64_t bytes = sp->dim * (dt == PBS_C128 ? 16ull : 8ull);
+      const auto a = reinterpret_cast<uintptr_t>(psi), b = reinterpret_cast<uintptr_t>(out);
+      PBS_REQUIRE(a + bytes <= b || b + bytes <= a, PBS_ERR_ARG, "out overlaps psi");
+    }
+    const uint64_t need = partial_count(*sp) * 3 * sizeof(double);
+    PBS_REQUIRE(need <= PBS_EXPVAL_NOALLOC_MAX_BYTES, PBS_ERR_RANGE,
+                "space needs " + std::to_string(need) + " bytes of energy partials, the fixed workspace holds " +
+                    std::to_string(static_cast<uint64_t>(PBS_EXPVAL_NOALLOC_MAX_BYTES)));
+    double* partial = noalloc_scratch();
+    hipStream_t s = as_stream(stream);
     if (dt == PBS_C128)
       launch<double2, true>(*h, *sp, psi, out, partial, s);
     else
