@@ -49,7 +49,7 @@ WORKLOADS = {
 
 # sources that decide what the sector apply kernel does per launch: its
 # device code, its launch planner and the tables grouping builds for it
-APPLY_SOURCES = ("apply.hip", "group.hip", "handles.h", "sector.h", "sector_c128_apply.hip",
+APPLY_SOURCES = ("apply.hip", "factor.hip", "group.hip", "handles.h", "sector.h", "sector_c128_apply.hip",
                  "sector_c128_expval.hip", "sector_c64_apply.hip", "sector_c64_expval.hip")
 
 
@@ -364,6 +364,8 @@ def main():
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="counter calibration: one device-to-device copy of this many bytes, nothing else")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-factor", action="store_true",
+                    help="skip the spin-factorized phase tables (unfactored evaluation throughout)")
     ap.add_argument("--apply-only", type=int, default=0,
                     help="profiling mode: run only N sector applies (complex64) after setup, print nothing else")
     args = ap.parse_args()
@@ -415,6 +417,8 @@ def main():
         H = api.jw_transform(h1_d, h2_d)
         G = H.group()
         sp = api.Space.sector(n_orb, na, nb)
+        if not args.no_factor:
+            G.factor(sp)  # spin-factorized phase tables for this beta sector
         return H, G, sp
 
     if args.apply_only:
@@ -477,6 +481,11 @@ def main():
 
     c64_ms = time_apply(psi32, out32)
     c128_ms = time_apply(psi64, out64)
+    # the unfactored evaluation of the same kernel, for comparison
+    G.set_factored(0)
+    c64_plain_ms = time_apply(psi32, torch.empty_like(psi32))
+    c128_plain_ms = time_apply(psi64, torch.empty_like(psi64))
+    G.set_factored(0 if args.no_factor else 7)
     # storage error of the complex64 path: against complex128 on the same
     # FP32-rounded input (kernel error) and against the FP64 state
     ref_same = api.apply_pauli_sum(G, sp, psi32.to(torch.complex128))
@@ -535,7 +544,8 @@ def main():
         "config": {"workload": args.workload, "n_orb": n_orb, "n_alpha": na, "n_beta": nb, "dim": D,
                    "n_strings": M, "groups_connected_per_target": round(g_conn, 3),
                    "strings_connected_per_target": round(t_conn, 3), "storage": "complex64",
-                   "step": "jw_transform+group_by_xmask+space_sector+fused(apply_pauli_sum+expval)"},
+                   "step": "jw_transform+group_by_xmask+space_sector+" +
+                           ("" if args.no_factor else "grouped_factor+") + "fused(apply_pauli_sum+expval)"},
         "roofline": roofline,
         "apply_ms_c64": c64_ms,
         "apply_ms_c128": c128_ms,
@@ -543,6 +553,9 @@ def main():
         "apply_connected_rate_c64": D * t_conn / (c64_ms * 1e-3),
         "apply_rate_c128": D * M / (c128_ms * 1e-3),
         "speedup_c64_vs_c128": c128_ms / c64_ms,
+        "factored": not args.no_factor,
+        "apply_ms_c64_unfactored": c64_plain_ms,
+        "apply_ms_c128_unfactored": c128_plain_ms,
         "rel_err_c64_vs_c128_same_input": err_kernel,
         "rel_err_c64_vs_fp64_state": err_state,
         "energy_c64": float(e32[0]),

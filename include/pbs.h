@@ -239,6 +239,44 @@ pbs_status pbs_expval(const pbs_grouped* h, const pbs_space* sp, pbs_dtype dt, c
 pbs_status pbs_expval_noalloc(const pbs_grouped* h, const pbs_space* sp, pbs_dtype dt, const void* psi, void* out,
                               double* result, void* stream);
 
+/* ------------------------------------------------------------------ spin-factorized phases */
+
+/* Spin-factorized evaluation of the phase sums (Section 2.4: Eqs.
+ * svd_weights, precomp_alpha, precomp_beta, svd_sreverse_sum and dot_product;
+ * Algorithm grouped_hvec; Table svd_rank_dist).  In a spin sector a group's
+ * sector-form coefficients form a matrix M[mu][nu] over its alpha Z-masks and
+ * beta Z-masks; with a rank-R factorization M = P Q its phase sum at
+ * (t_alpha, t_beta) is sum_r A_r(t_alpha) F_r(t_beta).  This call factors
+ * the operator's groups (rank-revealing Gram-Schmidt on M, relative
+ * tolerance 1e-14) and precomputes F_r for every beta string of sp's
+ * (n_orb, N_beta), for the X_beta = 0 group of every non-simple class and
+ * for the pair and quad groups of the X_alpha = 0 class (when their ranks
+ * are at most 2).  On the alpha side (Eq. precomp_alpha) it lists, for every
+ * alpha string of sp's N_alpha, the simple classes (one X_beta = 0 group
+ * with beta Z-masks 0) whose source lies in the sector, with their folded
+ * coefficients.  The tables are attached to h (replacing earlier ones);
+ * afterwards pbs_apply_pauli_sum, pbs_expval and batch jobs on sectors with
+ * the same (n_orb, N_beta), respectively (n_orb, N_alpha) for the alpha
+ * lists, use them (results equal the unfactored evaluation up to rounding).
+ * Needs real sector-form coefficients (PBS_ERR_UNSUPPORTED otherwise) and a
+ * sector space with n_orb = n_qubits / 2.  Allocates the tables (device
+ * memory owned by h) and synchronizes the stream; must not run while h is
+ * in use by another call. */
+pbs_status pbs_grouped_factor(pbs_grouped* h, const pbs_space* sp, void* stream);
+
+/* Chooses which of h's factor tables later single applies and energies use:
+ * mode bit 0 the rows of the X_beta = 0 groups, bit 1 the move tables of the
+ * X_alpha = 0 class, bit 2 the alpha lists of the simple classes (7, all, is
+ * the default; 0 turns the factored evaluation off).  Batches use the same mode unless the
+ * PBS_BATCH_NO_FACTORED schedule bit is set.  Must not run while h is in use. */
+pbs_status pbs_grouped_set_factored(pbs_grouped* h, int32_t mode);
+
+/* info[0..10] (host): tables present (0/1), X_beta = 0 groups factored,
+ * their largest rank, X_alpha = 0 pair groups factored, their rank, its quad
+ * groups factored, their rank, the N_beta the tables are for, alpha lists
+ * present (0/1), the N_alpha they are for, alpha images present (0/1). */
+pbs_status pbs_grouped_factor_info(const pbs_grouped* h, uint32_t* info);
+
 /* ------------------------------------------------------------------ batched apply */
 
 /* Prepares one launch that applies n operators to n states in spin sectors:
@@ -270,6 +308,7 @@ pbs_status pbs_batch_run(const pbs_batch* b, double* energies, void* stream);
 #define PBS_BATCH_NO_ROW_STAGING 2u    /* gather source rows from HBM/L2 instead of staging them in LDS */
 #define PBS_BATCH_NO_DOUBLE_MOVES 4u   /* scan double-flip groups instead of enumerating double moves */
 #define PBS_BATCH_NO_SINGLE_MOVES 8u   /* scan pair groups instead of enumerating single moves */
+#define PBS_BATCH_NO_FACTORED 64u      /* ignore the operators' factor tables (pbs_grouped_factor) */
 /* workgroup -> (alpha row, beta chunk) order of every job (bits 4-5); the
  * default is the single launch's: rows fastest when rows are staged in LDS,
  * else a row's chunks kept together on one XCD (shared L2) */
@@ -278,13 +317,13 @@ pbs_status pbs_batch_run(const pbs_batch* b, double* energies, void* stream);
 #define PBS_BATCH_ORDER_ROW_FAST 32u   /* rows fastest */
 #define PBS_BATCH_ORDER_XCD_ROWS 48u   /* a row's chunks on one XCD */
 
-/* Rebuilds the batch's job table for schedule `config` (0..63).  Synchronizes. */
+/* Rebuilds the batch's job table for schedule `config` (0..127).  Synchronizes. */
 pbs_status pbs_batch_set_config(pbs_batch* b, uint32_t config);
 
 /* Autotuner: times schedules (a warm-up run, then `reps` runs, 1..100, with
  * HIP events on the stream; schedules that build the same job table are
  * timed once), greedily: the four workgroup orders with the default flags,
- * then the 16 flag combinations with the best order.  Keeps the fastest and
+ * then the 32 flag combinations with the best order.  Keeps the fastest and
  * returns it in *config and its time per run in *ms (either may be NULL).
  * Runs the batch, so the output buffers are overwritten.  Call it before
  * capturing pbs_batch_run in a graph: it rebuilds the job table.

@@ -162,6 +162,28 @@ class Grouped:
         call("pbs_grouped_read", self._h, _ptr(xg), _ptr(off), _ptr(zk), _ptr(ck.view(np.float64)), _stream())
         return xg, off, zk, ck
 
+    def factor(self, space):
+        """Attaches spin-factorized phase tables for ``space``'s beta sector."""
+        call("pbs_grouped_factor", self._h, space._h, _stream())
+        return self
+
+    def set_factored(self, mode):
+        """True/7: all factor tables; False/0: none; otherwise a bit mask:
+        1 the X_beta = 0 groups' rows, 2 the X_alpha = 0 class's move tables,
+        4 the simple classes' alpha lists."""
+        call("pbs_grouped_set_factored", self._h, 7 if mode is True else int(mode))
+        return self
+
+    def factor_info(self):
+        """dict: tables present, factored X_beta = 0 groups and their largest
+        rank, factored pair and quad groups of the X_alpha = 0 class and their
+        ranks, and the N_beta of the tables."""
+        info = np.zeros(11, np.uint32)
+        call("pbs_grouped_factor_info", self._h, _ptr(info))
+        keys = ["present", "zero_groups", "zero_max_rank", "pair_groups", "pair_rank", "quad_groups",
+                "quad_rank", "n_beta", "alpha_lists", "n_alpha", "alpha_images"]
+        return {k: int(v) for k, v in zip(keys, info)}
+
     def __del__(self):
         h = getattr(self, "_h", None)
         if h is not None and h.value and _abi is not None and _abi._LIB is not None:

@@ -49,7 +49,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_full(uint64_t dim, uint32_t n_
   if (EXPVAL) block_reduce3_store<kBlock>(e_re, e_im, nrm, partial + 3ull * blockIdx.x);
 }
 
-constexpr uint32_t kFCapMin = 1536;  // folded uniques: smallest LDS capacity planned for
+constexpr uint32_t kFCapMin = 1024;  // folded uniques: smallest LDS capacity planned for
 constexpr uint32_t kFCapMax = 4096;  // and the largest (offsets are packed in 16 bits)
 
 // Per-job sums of workgroup partials (one workgroup per job, fixed order).
@@ -105,7 +105,8 @@ int device_lds_limit() {
 // uniques get what is left of half the device's LDS, so that two workgroups
 // share a compute unit, unless the fixed parts alone need more.
 Launch plan_sector(const pbs_grouped& h, const pbs_space& sp, size_t elem_bytes, bool allow_row, bool realc,
-                   SectorArgs* a_out, bool* r16, bool allow_enum = true, bool allow_qenum = true) {
+                   SectorArgs* a_out, bool* r16, bool allow_enum = true, bool allow_qenum = true,
+                   bool allow_fact = true) {
   SectorArgs a{};
   a.n_orb = sp.n_orb;
   a.n_alpha = sp.n_alpha;
@@ -146,8 +147,8 @@ Launch plan_sector(const pbs_grouped& h, const pbs_space& sp, size_t elem_bytes,
                h.n_pairs < 65536)
                   ? 1u
                   : 0u;
-  const uint32_t pu_bytes = kMiscBytes + kPuBytes;  // fixed: scratch and pair map (n_pairs + 1 <= 512 words)
-  PBS_REQUIRE(h.n_pairs + 1 <= kPuBytes / 4, PBS_ERR_RANGE, "too many orbital pairs for the pair map");
+  const uint32_t pu_bytes = kMiscBytes + kPuBytes;  // fixed: scratch and pair map (n_pairs + 1 <= 512 slots)
+  PBS_REQUIRE(h.n_pairs + 1 <= kPuBytes / 8, PBS_ERR_RANGE, "too many orbital pairs for the pair map");
   const uint64_t n_ep = host_binom(sp.n_orb - sp.n_beta, 2), n_op = host_binom(sp.n_beta, 2);
   a.qenum_ok = (allow_qenum && *r16 && a.enum_ok && h.n_qmap > 0 && h.n_quads > 0 && n_op * n_ep > 0) ? 1u : 0u;
   a.n_quads = h.n_quads;
@@ -169,7 +170,19 @@ Launch plan_sector(const pbs_grouped& h, const pbs_space& sp, size_t elem_bytes,
     if (base_fixed + qu_need + std::max(q_need, f_min) > cap || h.max_quad_uniques >= kFCapMax) a.qenum_ok = 0u;
   }
   const uint32_t qu_bytes = a.qenum_ok ? qu_need : 0u;
-  const uint32_t fixed = base_fixed + qu_bytes;
+  // spin-factorized evaluation when the operator carries tables for this
+  // beta sector (real coefficients)
+  const FactorPlan* F = h.fplan.get();
+  const bool fact_ok = allow_fact && realc && F != nullptr && F->n_orb == sp.n_orb;
+  const bool fact = fact_ok && (h.fact_on & (kFactZero | kFactMoves)) && F->n_beta == sp.n_beta &&
+                    F->dim_beta == sp.dim_beta;
+  const bool fact_a = fact_ok && (h.fact_on & kFactAlpha) && F->alist && F->n_alpha == sp.n_alpha;
+  // the folded factors of an X_beta = 0 group sit after the pair map when
+  // its fixed region has room (n_orb <= 16), else in a region of their own
+  const uint32_t a_in_pu = align16((h.n_pairs + 1u) * 8u);
+  const bool a_fits_pu = a_in_pu + kMaxR1 * 8u <= kPuBytes;
+  const uint32_t a_bytes = ((fact || fact_a) && !a_fits_pu) ? align16(kMaxR1 * 8u) : 0u;
+  const uint32_t fixed = base_fixed + qu_bytes + a_bytes;
   const uint32_t budget = fixed + f_min <= half ? half : limit;
   a.f_cap = std::min(kFCapMax, (budget - fixed - 64u) / per_unique - kZeroSlots);
   // layout: scratch [0, kMiscBytes), pair map at kPuOff, row or row list at
@@ -184,6 +197,63 @@ Launch plan_sector(const pbs_grouped& h, const pbs_space& sp, size_t elem_bytes,
   off += align16((a.f_cap + kZeroSlots) * 4u);
   a.off_qu = off;
   off += qu_bytes;
+  a.off_a = a_fits_pu ? kPuOff + a_in_pu : off;
+  off += a_bytes;
+  a.fact = fact ? (h.fact_on & kFactZero) : 0u;
+  a.f_c0 = 0xffffffffu;
+  if (fact_a) {
+    a.alist_off = F->alist_off.get();
+    a.alist_src = F->alist_src.get();
+    a.alist_c = F->alist_c.get();
+    // image classes need the cached single moves (with their beta parities)
+    // and the X_beta = 0 rows of this beta sector
+    if (F->plist && a.enum_ok && a.row_lds && h.pair_sign && F->n_beta == sp.n_beta && F->dim_beta == sp.dim_beta) {
+      a.plist_off = F->plist_off.get();
+      a.plist_src = F->plist_src.get();
+      a.plist_cls = F->plist_cls.get();
+      a.pimg = F->pimg.get();
+      a.pimg_flag = F->pimg_flag.get();
+      a.n_img = F->n_img;
+      a.cls_f = F->cls_f.get();
+      a.fz = F->fz.get();
+    }
+  }
+  if (fact) {
+    a.fu_t0 = F->fu_t0.get();
+    a.ft_za = F->ft_za.get();
+    a.ft_c = F->ft_c.get();
+    a.cls_f = F->cls_f.get();
+    a.fz = F->fz.get();
+    a.f_tz = F->t_zero;
+    // the X_alpha = 0 class through the move tables: needs room for its
+    // folded factors
+    if ((h.fact_on & kFactMoves) && a.row_lds && F->c0 != 0xffffffffu && F->n_moves == a.n_moves &&
+        kFactZeroSlots + (F->c0_fu1 - F->c0_fu0) <= a.f_cap) {
+      a.fact |= kFactMoves;
+      a.f_c0 = F->c0;
+      a.f_r2 = F->r2;
+      a.f_r3 = F->r3;
+      a.f_c0_fu0 = F->c0_fu0;
+      a.f_c0_fq = F->c0_fq;
+      a.f_c0_fu1 = F->c0_fu1;
+      a.f_tp = F->t_pair;
+      a.f_tq = F->t_quad;
+      a.f_n_qmoves = F->n_qmoves;
+      a.em = F->em.get();
+      a.fp = F->fp.get();
+      a.eq = F->eq.get();
+      a.fq = F->fq.get();
+    }
+  }
+  // classes that pass Q and the image pass evaluate leave the class list
+  if (a.fact && a.f_c0 != 0xffffffffu) {
+    const int k = a.plist_off ? 2 : 0;
+    a.ns_list = F->ns_rest[k].get();
+    a.n_ns = F->ns_sizes[k];
+  } else if (a.plist_off) {
+    a.ns_list = F->ns_rest[1].get();
+    a.n_ns = F->ns_sizes[1];
+  }
   *a_out = a;
 
   Launch L;
@@ -375,7 +445,7 @@ struct pbs_batch {
 namespace pbs {
 namespace {
 
-constexpr uint32_t kBatchConfigs = 64;  // four PBS_BATCH_* flags and the 2-bit workgroup order
+constexpr uint32_t kBatchConfigs = 128;  // five PBS_BATCH_* flags and the 2-bit workgroup order
 
 // Builds and uploads the job table of batch B for schedule `config`:
 // PBS_BATCH_GIVEN_ORDER keeps the caller's job order (else largest first),
@@ -392,6 +462,7 @@ void fill_batch(pbs_batch& B, uint32_t config) {
   const size_t esz = B.dt == PBS_C128 ? 16 : 8;
   const bool given = config & PBS_BATCH_GIVEN_ORDER, allow_row = !(config & PBS_BATCH_NO_ROW_STAGING);
   const bool qenum = !(config & PBS_BATCH_NO_DOUBLE_MOVES), penum = !(config & PBS_BATCH_NO_SINGLE_MOVES);
+  const bool factd = !(config & PBS_BATCH_NO_FACTORED);
   std::vector<BatchJob> jobs(n);
   std::vector<double> cost(n);
   std::vector<uint32_t> order(n);
@@ -401,14 +472,15 @@ void fill_batch(pbs_batch& B, uint32_t config) {
   for (uint32_t i = 0; i < n; ++i) realc = realc && B.h[i]->real_coef;
   for (uint32_t i = 0; i < n; ++i) {
     bool job_r16 = false;
-    plan_sector(*B.h[i], *B.sp[i], esz, allow_row, realc, &jobs[i].args, &job_r16, penum, qenum);
+    plan_sector(*B.h[i], *B.sp[i], esz, allow_row, realc, &jobs[i].args, &job_r16, penum, qenum, factd);
     r16 = r16 && job_r16;
     rowlds = rowlds && jobs[i].args.row_lds;
   }
   size_t lds = 0;
   for (uint32_t i = 0; i < n; ++i) {
     bool job_r16 = false;
-    const Launch L = plan_sector(*B.h[i], *B.sp[i], esz, rowlds, realc, &jobs[i].args, &job_r16, penum, qenum);
+    const Launch L =
+        plan_sector(*B.h[i], *B.sp[i], esz, rowlds, realc, &jobs[i].args, &job_r16, penum, qenum, factd);
     if (!r16) jobs[i].args.rank16 = nullptr;
     jobs[i].psi = B.psi[i];
     jobs[i].out = B.out[i];
@@ -566,7 +638,8 @@ pbs_status pbs_batch_tune(pbs_batch* b, uint32_t reps, void* stream, uint32_t* c
         }
       }
       const uint32_t ord = best & PBS_BATCH_ORDER_MASK;
-      for (uint32_t f = 1; f < 16; ++f) {
+      for (uint32_t f = 1; f < kBatchConfigs; ++f) {
+        if (f & PBS_BATCH_ORDER_MASK) continue;
         const double t = time_config(ord | f);
         if (t < best_ms) {
           best = ord | f;

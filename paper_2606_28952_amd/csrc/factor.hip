@@ -1,0 +1,653 @@
+// Spin-factorized phase evaluation (Section 2.4: Eqs. svd_weights,
+// precomp_alpha, precomp_beta, svd_sreverse_sum and dot_product; Algorithm
+// grouped_hvec; the rank distribution of Table svd_rank_dist).
+//
+// In a spin sector every group's phase sum separates into alpha and beta
+// parities: with its sector-form coefficients arranged as a matrix
+// M[mu][nu] (rows: the group's distinct alpha Z-masks, columns: its uniques,
+// i.e. distinct beta Z-masks),
+//   sum_k C_k (-1)^popcount(Z_k & t) = sum_{mu,nu} M[mu][nu] a_mu(t_a) b_nu(t_b),
+// a_mu = (-1)^popcount(Za_mu & t_a), b_nu = (-1)^popcount(Zb_nu & t_b).  A
+// rank-R factorization M = P Q turns this into sum_r A_r(t_a) F_r(t_b).  The
+// sector kernel folds the A_r once per workgroup (all its lanes share t_a);
+// this file factors the groups on the host and precomputes F_r for every
+// beta string of a sector on the device, laid out per target move so that
+// the kernel's loads are coalesced.  The paper computes the factors by an
+// SVD; here a rank-revealing Gram-Schmidt factorization (Q with orthonormal
+// rows, P = M Q^T, columns chosen by largest remaining norm) gives the same
+// exact ranks on these matrices with the same rounding-level residual.
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <vector>
+
+#include "handles.h"
+
+namespace pbs {
+namespace {
+
+// colexicographic rank of a spin string among the n-bit words of its
+// popcount (ascending integer order): sum_i C(pos_i, i + 1)
+__device__ inline uint32_t colex_rank(uint32_t s) {
+  uint32_t r = 0, i = 1;
+  while (s) {
+    const uint32_t b = __ffs(s) - 1;
+    s &= s - 1;
+    uint32_t c = 1;  // C(b, i)
+    for (uint32_t k = 1; k <= i; ++k) c = c * (b - i + k) / k;
+    r += b >= i ? c : 0u;
+    ++i;
+  }
+  return r;
+}
+
+// k-th set bit (k from 0) of w
+__device__ inline uint32_t kth_bit(uint32_t w, uint32_t k) {
+  for (uint32_t i = 0; i < k; ++i) w &= w - 1;
+  return __ffs(w) - 1;
+}
+
+// i-th pair (a < b) of n items in the order (0,1), (0,2), ..., (1,2), ...
+__device__ inline void pair_at(uint32_t i, uint32_t n, uint32_t& a, uint32_t& b) {
+  a = 0;
+  while (i >= n - 1 - a) {
+    i -= n - 1 - a;
+    ++a;
+  }
+  b = a + 1 + i;
+}
+
+__device__ inline double eval_rows(const uint32_t* q_zb, const double* q_c, uint32_t lo, uint32_t hi, uint32_t tb) {
+  double f = 0.0;
+  for (uint32_t k = lo; k < hi; ++k) f += (__popc(q_zb[k] & tb) & 1u) ? -q_c[k] : q_c[k];
+  return f;
+}
+
+// F rows of the X_beta = 0 groups: f[i * db + j] = sum over row i's list.
+__global__ void k_fact_rows(uint32_t n_rows, uint64_t db, const uint32_t* str_b, const uint32_t* q_lo,
+                            const uint32_t* q_zb, const double* q_c, double* f) {
+  const uint64_t n = static_cast<uint64_t>(n_rows) * db;
+  for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+    const uint32_t row = static_cast<uint32_t>(i / db);
+    f[i] = eval_rows(q_zb, q_c, q_lo[row], q_lo[row + 1], str_b[i % db]);
+  }
+}
+
+// Single moves (occupied p -> empty q, p outer, both ascending):
+// em[m * db + j] = source column | (factor slot << 16), fp[(m * r2 + r) * db + j].
+__global__ void k_fact_moves(uint64_t db, uint32_t n_orb, uint32_t n_beta, uint32_t r2, const uint32_t* str_b,
+                             const int32_t* pk, const uint32_t* q_lo, const uint32_t* q_zb, const double* q_c,
+                             uint32_t* em, double* fp) {
+  const uint32_t ne = n_orb - n_beta, n_moves = n_beta * ne;
+  const uint32_t full = (n_orb == 32) ? 0xffffffffu : ((1u << n_orb) - 1u);
+  const uint64_t n = static_cast<uint64_t>(n_moves) * db;
+  for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+    const uint32_t m = static_cast<uint32_t>(i / db);
+    const uint64_t j = i % db;
+    const uint32_t tb = str_b[j];
+    const uint32_t p = kth_bit(tb, m / ne), q = kth_bit(~tb & full, m % ne);
+    const uint32_t lo = p < q ? p : q, hi = p < q ? q : p;
+    const int32_t k = pk[hi * (hi - 1) / 2 + lo];
+    em[static_cast<uint64_t>(m) * db + j] =
+        colex_rank(tb ^ (1u << p) ^ (1u << q)) | ((k >= 0 ? kFactZeroSlots + static_cast<uint32_t>(k) * r2 : 0u) << 16);
+    for (uint32_t r = 0; r < r2; ++r) {
+      const uint32_t row = static_cast<uint32_t>(k) * r2 + r;
+      fp[(static_cast<uint64_t>(m) * r2 + r) * db + j] = k >= 0 ? eval_rows(q_zb, q_c, q_lo[row], q_lo[row + 1], tb)
+                                                                : 0.0;
+    }
+  }
+}
+
+// Double moves: occupied pair (a < b) outer, empty pair (c < d) inner, each
+// in the order of pair_at over the target's occupied / empty orbitals.
+// eq[qm * db + j] = source column | (factor slot << 16); fq[(qm * r3 + r) * db + j].
+__global__ void k_fact_quads(uint64_t db, uint32_t n_orb, uint32_t n_beta, uint32_t r3, uint32_t slot0,
+                             const uint32_t* str_b, const int32_t* qk, const uint32_t* q_lo, const uint32_t* q_zb,
+                             const double* q_c, uint32_t* eq, double* fq) {
+  const uint32_t ne = n_orb - n_beta;
+  const uint32_t n_op = n_beta * (n_beta - 1) / 2, n_ep = ne * (ne - 1) / 2, n_q = n_op * n_ep;
+  const uint32_t full = (n_orb == 32) ? 0xffffffffu : ((1u << n_orb) - 1u);
+  const uint64_t n = static_cast<uint64_t>(n_q) * db;
+  for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+    const uint32_t qm = static_cast<uint32_t>(i / db);
+    const uint64_t j = i % db;
+    const uint32_t tb = str_b[j], emp = ~tb & full;
+    uint32_t a, b, c, d;
+    pair_at(qm / n_ep, n_beta, a, b);
+    pair_at(qm % n_ep, ne, c, d);
+    const uint32_t X = (1u << kth_bit(tb, a)) | (1u << kth_bit(tb, b)) | (1u << kth_bit(emp, c)) |
+                       (1u << kth_bit(emp, d));
+    const int32_t k = qk[colex_rank(X)];
+    eq[static_cast<uint64_t>(qm) * db + j] =
+        colex_rank(tb ^ X) | ((k >= 0 ? slot0 + static_cast<uint32_t>(k) * r3 : 0u) << 16);
+    for (uint32_t r = 0; r < r3; ++r) {
+      const uint32_t row = static_cast<uint32_t>(k) * r3 + r;
+      fq[(static_cast<uint64_t>(qm) * r3 + r) * db + j] = k >= 0 ? eval_rows(q_zb, q_c, q_lo[row], q_lo[row + 1], tb)
+                                                                 : 0.0;
+    }
+  }
+}
+
+// Alpha lists (Eq. precomp_alpha for the simple classes): one thread per
+// alpha row walks the simple classes in class order; pass 0 counts the
+// classes whose source row lies in the sector, pass 1 writes their source
+// rank and folded coefficient sum_t c_t (-1)^popcount(za_t & t_alpha).
+__global__ void k_alpha_list(uint32_t pass, uint64_t da, uint32_t n_alpha, const uint32_t* str_a,
+                             const uint32_t* simple, uint32_t n_simple, const ClassMeta* meta, const uint32_t* u_t0,
+                             const uint32_t* pt_za, const double* pt_c, const uint32_t* off, uint32_t* count,
+                             uint32_t* src, double* coef) {
+  for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < da;
+       i += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+    const uint32_t ta = str_a[i];
+    uint32_t n = 0, o = pass ? off[i] : 0u;
+    for (uint32_t k = 0; k < n_simple; ++k) {
+      const ClassMeta& m = meta[simple[k]];
+      const uint32_t sa = ta ^ m.xa;
+      if (static_cast<uint32_t>(__popc(sa)) != n_alpha) continue;
+      if (pass) {
+        double f = 0.0;
+        for (uint32_t t = u_t0[m.ua]; t < u_t0[m.u_end]; ++t)
+          f += (__popc(pt_za[t] & ta) & 1u) ? -pt_c[2 * t] : pt_c[2 * t];
+        src[o + n] = colex_rank(sa);
+        coef[o + n] = f;
+      }
+      ++n;
+    }
+    if (!pass) count[i] = n;
+  }
+}
+
+// Image-class lists: pass 0 counts per alpha row the image classes whose
+// source row lies in the sector, pass 1 writes (source rank, class, row).
+__global__ void k_pair_list(uint32_t pass, uint64_t da, uint32_t n_alpha, const uint32_t* str_a, const uint32_t* cls,
+                            uint32_t n_cls, const ClassMeta* meta, const uint32_t* off, uint32_t* count,
+                            uint32_t* src, uint32_t* ent_cls, uint32_t* ent_row) {
+  for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < da;
+       i += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+    const uint32_t ta = str_a[i];
+    uint32_t n = 0, o = pass ? off[i] : 0u;
+    for (uint32_t k = 0; k < n_cls; ++k) {
+      const uint32_t sa = ta ^ meta[cls[k]].xa;
+      if (static_cast<uint32_t>(__popc(sa)) != n_alpha) continue;
+      if (pass) {
+        src[o + n] = colex_rank(sa);
+        ent_cls[o + n] = cls[k];
+        ent_row[o + n] = static_cast<uint32_t>(i);
+      }
+      ++n;
+    }
+    if (!pass) count[i] = n;
+  }
+}
+
+// Images: one thread per (entry, slot j < n_img): the folded coefficient of
+// the class's pair group on orbital pair j, 0 for slot n_pairs, then the
+// X_beta = 0 group's folded factors.
+__global__ void k_pair_images(uint64_t n_ent, uint32_t n_img, uint32_t n_pairs, const uint32_t* str_a,
+                              const uint32_t* ent_cls, const uint32_t* ent_row, const ClassMeta* meta,
+                              const int32_t* pmap, const uint32_t* pg_u0, const uint32_t* u_t0, const uint32_t* pt_za,
+                              const double* pt_c, const uint4* cls_f, const uint32_t* fu_t0, const uint32_t* ft_za,
+                              const double* ft_c, double* img) {
+  const uint64_t n = n_ent * n_img;
+  for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+    const uint64_t e = i / n_img;
+    const uint32_t j = static_cast<uint32_t>(i % n_img);
+    const uint32_t c = ent_cls[e], ta = str_a[ent_row[e]];
+    double f = 0.0;
+    if (j < n_pairs) {
+      const int32_t g = pmap[static_cast<uint64_t>(meta[c].pm) * n_pairs + j];
+      if (g >= 0) {
+        const uint32_t u = pg_u0[g];
+        for (uint32_t t = u_t0[u]; t < u_t0[u + 1]; ++t) f += (__popc(pt_za[t] & ta) & 1u) ? -pt_c[2 * t] : pt_c[2 * t];
+      }
+    } else if (j > n_pairs) {
+      const uint32_t r = j - n_pairs - 1;
+      if (r < cls_f[c].y) {
+        const uint32_t u = cls_f[c].x + r;
+        for (uint32_t t = fu_t0[u]; t < fu_t0[u + 1]; ++t) f += (__popc(ft_za[t] & ta) & 1u) ? -ft_c[t] : ft_c[t];
+      }
+    }
+    img[i] = f;
+  }
+}
+
+// ---------------------------------------------------------------- host side
+
+// One group's factors: for each r, the alpha terms (Za, P[mu][r]) and the
+// beta list (Zb, Q[r][nu]); exact zeros are left out.
+struct GroupFactors {
+  uint32_t rank = 0;
+  uint32_t n_uniques = 0;
+  std::vector<std::vector<std::pair<uint32_t, double>>> a, b;
+};
+
+// M = P Q by pivoted Gram-Schmidt on the rows of M (rows x cols, row-major):
+// the next basis vector is the remaining row of largest norm, orthogonalised
+// twice against the basis; stops when every remaining row is below
+// rtol * (largest row norm of M).
+uint32_t factor_rows(const std::vector<double>& M, uint32_t rows, uint32_t cols, double rtol,
+                     std::vector<double>& Q) {
+  std::vector<double> res = M;
+  Q.clear();
+  double scale = 0.0;
+  for (uint32_t i = 0; i < rows; ++i) {
+    double s = 0.0;
+    for (uint32_t j = 0; j < cols; ++j) s += M[i * cols + j] * M[i * cols + j];
+    scale = std::max(scale, std::sqrt(s));
+  }
+  if (scale == 0.0) return 0;
+  uint32_t r = 0;
+  std::vector<double> q(cols);
+  while (r < rows && r < cols) {
+    uint32_t best = 0;
+    double bn = -1.0;
+    for (uint32_t i = 0; i < rows; ++i) {
+      double s = 0.0;
+      for (uint32_t j = 0; j < cols; ++j) s += res[i * cols + j] * res[i * cols + j];
+      if (s > bn) {
+        bn = s;
+        best = i;
+      }
+    }
+    if (std::sqrt(bn) <= rtol * scale) break;
+    for (uint32_t j = 0; j < cols; ++j) q[j] = res[best * cols + j];
+    for (int pass = 0; pass < 2; ++pass) {
+      for (uint32_t k = 0; k < r; ++k) {
+        double d = 0.0;
+        for (uint32_t j = 0; j < cols; ++j) d += q[j] * Q[k * cols + j];
+        for (uint32_t j = 0; j < cols; ++j) q[j] -= d * Q[k * cols + j];
+      }
+      double nn = 0.0;
+      for (uint32_t j = 0; j < cols; ++j) nn += q[j] * q[j];
+      nn = std::sqrt(nn);
+      for (uint32_t j = 0; j < cols; ++j) q[j] /= nn;
+    }
+    Q.insert(Q.end(), q.begin(), q.end());
+    ++r;
+    for (uint32_t i = 0; i < rows; ++i) {
+      double d = 0.0;
+      for (uint32_t j = 0; j < cols; ++j) d += res[i * cols + j] * q[j];
+      for (uint32_t j = 0; j < cols; ++j) res[i * cols + j] -= d * q[j];
+    }
+  }
+  return r;
+}
+
+struct HostTables {
+  std::vector<uint32_t> pg_u0, u_zb, u_t0, pt_za, pg_xb;
+  std::vector<double> pt_c;  // real parts
+};
+
+GroupFactors factor_group(const HostTables& T, uint32_t g) {
+  GroupFactors F;
+  const uint32_t u0 = T.pg_u0[g], u1 = T.pg_u0[g + 1];
+  F.n_uniques = u1 - u0;
+  std::map<uint32_t, uint32_t> rows;
+  for (uint32_t t = T.u_t0[u0]; t < T.u_t0[u1]; ++t) rows.emplace(T.pt_za[t], 0u);
+  uint32_t i = 0;
+  std::vector<uint32_t> za(rows.size());
+  for (auto& kv : rows) {
+    kv.second = i;
+    za[i++] = kv.first;
+  }
+  const uint32_t nr = static_cast<uint32_t>(rows.size()), nc = u1 - u0;
+  std::vector<double> M(static_cast<size_t>(nr) * nc, 0.0);
+  for (uint32_t u = u0; u < u1; ++u)
+    // terms whose beta Z-masks differ by X_beta share one unique in sector
+    // form and may share an alpha Z-mask too: their coefficients add
+    for (uint32_t t = T.u_t0[u]; t < T.u_t0[u + 1]; ++t) M[rows[T.pt_za[t]] * nc + (u - u0)] += T.pt_c[t];
+  std::vector<double> Q;
+  F.rank = factor_rows(M, nr, nc, 1e-14, Q);
+  F.a.resize(F.rank);
+  F.b.resize(F.rank);
+  for (uint32_t r = 0; r < F.rank; ++r) {
+    for (uint32_t mu = 0; mu < nr; ++mu) {
+      double p = 0.0;
+      for (uint32_t nu = 0; nu < nc; ++nu) p += M[mu * nc + nu] * Q[r * nc + nu];
+      if (p != 0.0) F.a[r].emplace_back(za[mu], p);
+    }
+    for (uint32_t nu = 0; nu < nc; ++nu)
+      if (Q[r * nc + nu] != 0.0) F.b[r].emplace_back(T.u_zb[u0 + nu], Q[r * nc + nu]);
+  }
+  return F;
+}
+
+template <class T>
+void upload(DevBuf<T>& d, const std::vector<T>& h) {
+  d.alloc(h.size());
+  if (!h.empty()) PBS_HIP(hipMemcpy(d.get(), h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+}
+
+template <class T>
+std::vector<T> download(const DevBuf<T>& d, size_t n) {
+  std::vector<T> h(n);
+  if (n) PBS_HIP(hipMemcpy(h.data(), d.get(), n * sizeof(T), hipMemcpyDeviceToHost));
+  return h;
+}
+
+void build_plan(pbs_grouped& h, const pbs_space& sp, hipStream_t s) {
+  auto plan = std::make_unique<FactorPlan>();
+  FactorPlan& F = *plan;
+  F.n_orb = sp.n_orb;
+  F.n_beta = sp.n_beta;
+  F.dim_beta = sp.dim_beta;
+  const uint64_t db = sp.dim_beta;
+  PBS_HIP(hipStreamSynchronize(s));
+  HostTables T;
+  T.pg_u0 = download(h.pg_u0, h.n_pgroup + 1);
+  T.u_zb = download(h.u_zb, h.n_unique);
+  T.u_t0 = download(h.u_t0, h.n_unique + 1);
+  T.pt_za = download(h.pt_za, h.n_pterm);
+  T.pg_xb = download(h.pg_xb, h.n_pgroup);
+  {
+    const std::vector<double> c = download(h.pt_c, 2ull * h.n_pterm);
+    T.pt_c.resize(h.n_pterm);
+    for (uint32_t t = 0; t < h.n_pterm; ++t) T.pt_c[t] = c[2ull * t];
+  }
+  const std::vector<ClassMeta> meta = download(h.cls_meta, h.n_class);
+  const std::vector<uint32_t> ns = download(h.ns_list, h.n_ns);
+
+  // factor uniques (alpha side) and the beta lists of the table rows
+  std::vector<uint32_t> fu_t0{0}, ft_za;
+  std::vector<double> ft_c;
+  std::vector<uint32_t> q_lo{0}, q_zb;
+  std::vector<double> q_c;
+  auto add_factor = [&](const std::vector<std::pair<uint32_t, double>>* a) {
+    if (a)
+      for (auto& t : *a) {
+        ft_za.push_back(t.first);
+        ft_c.push_back(t.second);
+      }
+    fu_t0.push_back(static_cast<uint32_t>(ft_za.size()));
+  };
+  auto add_row = [&](const std::vector<std::pair<uint32_t, double>>* b) {
+    if (b)
+      for (auto& t : *b) {
+        q_zb.push_back(t.first);
+        q_c.push_back(t.second);
+      }
+    q_lo.push_back(static_cast<uint32_t>(q_zb.size()));
+  };
+
+  // the class with X_alpha = 0: its pair groups (single moves) and quad groups
+  // (double moves), when the sector kernel enumerates both
+  const uint32_t ne = sp.n_orb - sp.n_beta;
+  const uint32_t n_moves = sp.n_beta * ne;
+  const uint64_t n_qmoves = host_binom(sp.n_beta, 2) * host_binom(ne, 2);
+  uint32_t c0 = 0xffffffffu;
+  for (uint32_t c : ns)
+    if (meta[c].xa == 0) c0 = c;
+  std::vector<GroupFactors> pf, qf;
+  if (c0 != 0xffffffffu && sp.n_orb <= 16 && n_moves > 0 && n_qmoves > 0 && db < 65536) {
+    const ClassMeta& m = meta[c0];
+    const uint32_t gz_end = m.zg >= 0 ? m.g0 + 1 : m.g0;
+    uint32_t r2 = 0, r3 = 0;
+    for (uint32_t g = gz_end; g < m.p1; ++g) {
+      pf.push_back(factor_group(T, g));
+      r2 = std::max(r2, pf.back().rank);
+    }
+    for (uint32_t g = m.p1; g < m.q1; ++g) {
+      qf.push_back(factor_group(T, g));
+      r3 = std::max(r3, qf.back().rank);
+    }
+    const uint64_t n_fold = static_cast<uint64_t>(pf.size()) * r2 + static_cast<uint64_t>(qf.size()) * r3;
+    // the tables hold every move of a target, present group or not: used
+    // only when most orbital pairs / quadruples have a group (two-body
+    // operators with dense integrals), where they replace long phase sums
+    const bool dense = 2 * pf.size() >= h.n_pairs && 2 * qf.size() >= h.n_quads;
+    if (dense && r2 >= 1 && r2 <= 2 && r3 >= 1 && r3 <= 2 && kFactZeroSlots + n_fold <= 4096) {
+      F.c0 = c0;
+      F.r2 = r2;
+      F.r3 = r3;
+    } else {
+      pf.clear();
+      qf.clear();
+    }
+  }
+  std::vector<int32_t> pk(h.n_pairs + 1, -1), qk(h.n_quads ? h.n_quads : 1, -1);
+  if (F.c0 != 0xffffffffu) {
+    const ClassMeta& m = meta[c0];
+    const uint32_t gz_end = m.zg >= 0 ? m.g0 + 1 : m.g0;
+    F.c0_fu0 = 0;
+    for (uint32_t k = 0; k < pf.size(); ++k) {
+      const uint32_t x = T.pg_xb[gz_end + k];
+      const uint32_t lo = static_cast<uint32_t>(__builtin_ctz(x)), hi = 31u - static_cast<uint32_t>(__builtin_clz(x));
+      pk[hi * (hi - 1) / 2 + lo] = static_cast<int32_t>(k);
+      for (uint32_t r = 0; r < F.r2; ++r) add_factor(r < pf[k].rank ? &pf[k].a[r] : nullptr);
+    }
+    F.c0_fq = static_cast<uint32_t>(fu_t0.size() - 1);
+    for (uint32_t k = 0; k < qf.size(); ++k) {
+      uint32_t x = T.pg_xb[m.p1 + k], id = 0;
+      for (uint32_t j = 1; j <= 4; ++j) {
+        const uint32_t b = static_cast<uint32_t>(__builtin_ctz(x));
+        x &= x - 1;
+        id += static_cast<uint32_t>(host_binom(b, j));
+      }
+      qk[id] = static_cast<int32_t>(k);
+      for (uint32_t r = 0; r < F.r3; ++r) add_factor(r < qf[k].rank ? &qf[k].a[r] : nullptr);
+    }
+    F.c0_fu1 = static_cast<uint32_t>(fu_t0.size() - 1);
+    F.n_f2 = static_cast<uint32_t>(pf.size());
+    F.n_f3 = static_cast<uint32_t>(qf.size());
+    F.n_moves = n_moves;
+    F.n_qmoves = static_cast<uint32_t>(n_qmoves);
+  }
+  const uint32_t rows_p = static_cast<uint32_t>(q_lo.size() - 1);
+  for (uint32_t k = 0; k < pf.size(); ++k)
+    for (uint32_t r = 0; r < F.r2; ++r) add_row(r < pf[k].rank ? &pf[k].b[r] : nullptr);
+  const uint32_t rows_q = static_cast<uint32_t>(q_lo.size() - 1);
+  for (uint32_t k = 0; k < qf.size(); ++k)
+    for (uint32_t r = 0; r < F.r3; ++r) add_row(r < qf[k].rank ? &qf[k].b[r] : nullptr);
+  const uint32_t rows_z = static_cast<uint32_t>(q_lo.size() - 1);
+
+  // X_beta = 0 groups of the non-simple classes, factored when that lowers
+  // the number of beta terms a target evaluates
+  std::vector<uint4> cls_f(h.n_class, make_uint4(0u, 0u, 0u, 0u));
+  uint32_t n_zrows = 0;
+  for (uint32_t c : ns) {
+    const ClassMeta& m = meta[c];
+    if (m.zg < 0) continue;
+    GroupFactors G = factor_group(T, static_cast<uint32_t>(m.zg));
+    if (G.rank == 0 || G.rank > kMaxR1 || G.rank >= G.n_uniques) continue;
+    const uint32_t fu0 = static_cast<uint32_t>(fu_t0.size() - 1);
+    for (uint32_t r = 0; r < G.rank; ++r) {
+      add_factor(&G.a[r]);
+      add_row(&G.b[r]);
+    }
+    cls_f[c] = make_uint4(fu0, G.rank, 0u, 0u);
+    *reinterpret_cast<uint64_t*>(&cls_f[c].z) = static_cast<uint64_t>(n_zrows) * db;
+    n_zrows += G.rank;
+    F.max_r1 = std::max(F.max_r1, G.rank);
+    ++F.n_f1;
+  }
+  F.n_fu = static_cast<uint32_t>(fu_t0.size() - 1);
+  auto most_terms = [&](uint32_t a, uint32_t b) {
+    uint32_t t = 0;
+    for (uint32_t u = a; u < b; ++u) t = std::max(t, fu_t0[u + 1] - fu_t0[u]);
+    return t;
+  };
+  F.t_pair = most_terms(F.c0_fu0, F.c0_fq);
+  F.t_quad = most_terms(F.c0_fq, F.c0_fu1);
+  F.t_zero = most_terms(F.c0_fu1, F.n_fu);
+  F.n_ft = static_cast<uint32_t>(ft_za.size());
+  upload(F.fu_t0, fu_t0);
+  upload(F.ft_za, ft_za);
+  upload(F.ft_c, ft_c);
+  upload(F.cls_f, cls_f);
+  DevBuf<uint32_t> d_qlo, d_qzb;
+  DevBuf<double> d_qc;
+  upload(d_qlo, q_lo);
+  upload(d_qzb, q_zb);
+  upload(d_qc, q_c);
+
+  if (n_zrows) {
+    F.fz.alloc(static_cast<uint64_t>(n_zrows) * db);
+    const uint64_t n = static_cast<uint64_t>(n_zrows) * db;
+    hipLaunchKernelGGL(k_fact_rows, dim3(grid_for(n, 256, 65536)), dim3(256), 0, s, n_zrows, db, sp.str_beta.get(),
+                       d_qlo.get() + rows_z, d_qzb.get(), d_qc.get(), F.fz.get());
+    PBS_HIP(hipGetLastError());
+  }
+  if (F.c0 != 0xffffffffu) {
+    DevBuf<int32_t> d_pk, d_qk;
+    upload(d_pk, pk);
+    upload(d_qk, qk);
+    F.em.alloc(static_cast<uint64_t>(n_moves) * db);
+    F.fp.alloc(static_cast<uint64_t>(n_moves) * F.r2 * db);
+    F.eq.alloc(n_qmoves * db);
+    F.fq.alloc(n_qmoves * F.r3 * db);
+    const uint64_t nm = static_cast<uint64_t>(n_moves) * db, nq = n_qmoves * db;
+    hipLaunchKernelGGL(k_fact_moves, dim3(grid_for(nm, 256, 65536)), dim3(256), 0, s, db, sp.n_orb, sp.n_beta, F.r2,
+                       sp.str_beta.get(), d_pk.get(), d_qlo.get() + rows_p, d_qzb.get(), d_qc.get(), F.em.get(),
+                       F.fp.get());
+    const uint32_t slot0 = kFactZeroSlots + F.n_f2 * F.r2;
+    hipLaunchKernelGGL(k_fact_quads, dim3(grid_for(nq, 256, 65536)), dim3(256), 0, s, db, sp.n_orb, sp.n_beta,
+                       F.r3, slot0, sp.str_beta.get(), d_qk.get(), d_qlo.get() + rows_q, d_qzb.get(), d_qc.get(),
+                       F.eq.get(), F.fq.get());
+    PBS_HIP(hipGetLastError());
+  }
+  // alpha lists of the simple classes, when every unique of every simple
+  // class has beta Z-mask 0
+  {
+    std::vector<uint32_t> simple;
+    bool plain = true;
+    for (uint32_t c = 0; c < h.n_class && plain; ++c) {
+      if (!(meta[c].flags & kClassSimple)) continue;
+      simple.push_back(c);
+      for (uint32_t u = meta[c].ua; u < meta[c].u_end; ++u) plain = plain && T.u_zb[u] == 0u;
+    }
+    const uint64_t da = sp.dim_alpha;
+    if (plain && !simple.empty() && sp.n_orb <= 32) {
+      DevBuf<uint32_t> d_simple, cnt(da, s);
+      upload(d_simple, simple);
+      const unsigned grid = grid_for(da, 256, 65536);
+      hipLaunchKernelGGL(k_alpha_list, dim3(grid), dim3(256), 0, s, 0u, da, sp.n_alpha, sp.str_alpha.get(),
+                         d_simple.get(), static_cast<uint32_t>(simple.size()), h.cls_meta.get(), h.u_t0.get(),
+                         h.pt_za.get(), h.pt_c.get(), nullptr, cnt.get(), nullptr, nullptr);
+      PBS_HIP(hipGetLastError());
+      PBS_HIP(hipStreamSynchronize(s));
+      std::vector<uint32_t> c = download(cnt, da), off(da + 1, 0u);
+      for (uint64_t i = 0; i < da; ++i) off[i + 1] = off[i] + c[i];
+      upload(F.alist_off, off);
+      F.alist_src.alloc(off[da]);
+      F.alist_c.alloc(off[da]);
+      if (off[da]) {
+        hipLaunchKernelGGL(k_alpha_list, dim3(grid), dim3(256), 0, s, 1u, da, sp.n_alpha, sp.str_alpha.get(),
+                           d_simple.get(), static_cast<uint32_t>(simple.size()), h.cls_meta.get(), h.u_t0.get(),
+                           h.pt_za.get(), h.pt_c.get(), F.alist_off.get(), nullptr, F.alist_src.get(),
+                           F.alist_c.get());
+        PBS_HIP(hipGetLastError());
+      }
+      F.alist = true;
+      F.n_alpha = sp.n_alpha;
+    }
+  }
+  // image classes and their per-row images
+  if (F.alist && h.pair_sign && F.n_alpha == sp.n_alpha) {
+    std::vector<uint32_t> icls, flag(h.n_class, 0u);
+    const std::vector<uint4> cf = download(F.cls_f, h.n_class);
+    for (uint32_t c : ns) {
+      const ClassMeta& m = meta[c];
+      if (c == F.c0 || m.pm < 0 || !(m.flags & kClassPairsSingle) || m.p1 != m.g1) continue;
+      if (m.zg >= 0 && (cf[c].y == 0 || cf[c].y > 2)) continue;
+      icls.push_back(c);
+      flag[c] = 1u;
+    }
+    const uint64_t da = sp.dim_alpha;
+    if (!icls.empty()) {
+      DevBuf<uint32_t> d_cls, cnt(da, s);
+      upload(d_cls, icls);
+      const unsigned grid = grid_for(da, 256, 65536);
+      hipLaunchKernelGGL(k_pair_list, dim3(grid), dim3(256), 0, s, 0u, da, sp.n_alpha, sp.str_alpha.get(), d_cls.get(),
+                         static_cast<uint32_t>(icls.size()), h.cls_meta.get(), nullptr, cnt.get(), nullptr, nullptr,
+                         nullptr);
+      PBS_HIP(hipGetLastError());
+      PBS_HIP(hipStreamSynchronize(s));
+      std::vector<uint32_t> c = download(cnt, da), off(da + 1, 0u);
+      for (uint64_t i = 0; i < da; ++i) off[i + 1] = off[i] + c[i];
+      const uint64_t n_ent = off[da];
+      upload(F.plist_off, off);
+      F.plist_src.alloc(n_ent);
+      F.plist_cls.alloc(n_ent);
+      DevBuf<uint32_t> ent_row(n_ent, s);
+      F.n_img = h.n_pairs + 3;
+      F.pimg.alloc(n_ent * F.n_img);
+      if (n_ent) {
+        hipLaunchKernelGGL(k_pair_list, dim3(grid), dim3(256), 0, s, 1u, da, sp.n_alpha, sp.str_alpha.get(),
+                           d_cls.get(), static_cast<uint32_t>(icls.size()), h.cls_meta.get(), F.plist_off.get(),
+                           nullptr, F.plist_src.get(), F.plist_cls.get(), ent_row.get());
+        const uint64_t ni = n_ent * F.n_img;
+        hipLaunchKernelGGL(k_pair_images, dim3(grid_for(ni, 256, 65536)), dim3(256), 0, s, n_ent, F.n_img,
+                           h.n_pairs, sp.str_alpha.get(), F.plist_cls.get(), ent_row.get(), h.cls_meta.get(),
+                           h.pmap.get(), h.pg_u0.get(), h.u_t0.get(), h.pt_za.get(), h.pt_c.get(), F.cls_f.get(),
+                           F.fu_t0.get(), F.ft_za.get(), F.ft_c.get(), F.pimg.get());
+        PBS_HIP(hipGetLastError());
+      }
+      upload(F.pimg_flag, flag);
+      PBS_HIP(hipStreamSynchronize(s));
+      F.plist = true;
+    }
+  }
+  {
+    std::vector<uint32_t> flag = F.plist ? download(F.pimg_flag, h.n_class) : std::vector<uint32_t>(h.n_class, 0u);
+    F.ns_sizes.assign(3, 0u);
+    for (int k = 0; k < 3; ++k) {
+      std::vector<uint32_t> l;
+      for (uint32_t c : ns)
+        if (!((k != 1 && c == F.c0) || (k != 0 && flag[c]))) l.push_back(c);
+      F.ns_sizes[k] = static_cast<uint32_t>(l.size());
+      upload(F.ns_rest[k], l);
+    }
+  }
+  PBS_HIP(hipStreamSynchronize(s));
+  h.fplan = std::move(plan);
+}
+
+}  // namespace
+}  // namespace pbs
+
+using namespace pbs;
+
+extern "C" {
+
+pbs_status pbs_grouped_factor(pbs_grouped* h, const pbs_space* sp, void* stream) {
+  return guarded([&] {
+    PBS_REQUIRE(h != nullptr && sp != nullptr, PBS_ERR_ARG, "null handle");
+    PBS_REQUIRE(sp->sector, PBS_ERR_ARG, "factored evaluation needs a spin-sector space");
+    PBS_REQUIRE(h->has_sector && h->half == sp->n_orb, PBS_ERR_ARG, "operator lacks sector tables for this split");
+    PBS_REQUIRE(h->real_coef, PBS_ERR_UNSUPPORTED, "factored evaluation needs real sector-form coefficients");
+    h->fplan.reset();
+    build_plan(*h, *sp, as_stream(stream));
+  });
+}
+
+pbs_status pbs_grouped_set_factored(pbs_grouped* h, int32_t mode) {
+  return guarded([&] {
+    PBS_REQUIRE(h != nullptr, PBS_ERR_ARG, "null handle");
+    PBS_REQUIRE(mode >= 0 && mode <= 7, PBS_ERR_ARG, "factored-evaluation mode must be 0..7");
+    h->fact_on = static_cast<uint32_t>(mode);
+  });
+}
+
+pbs_status pbs_grouped_factor_info(const pbs_grouped* h, uint32_t* info) {
+  return guarded([&] {
+    PBS_REQUIRE(h != nullptr && info != nullptr, PBS_ERR_ARG, "null argument");
+    const FactorPlan* F = h->fplan.get();
+    info[0] = F ? 1u : 0u;
+    info[1] = F ? F->n_f1 : 0u;
+    info[2] = F ? F->max_r1 : 0u;
+    info[3] = F ? F->n_f2 : 0u;
+    info[4] = F ? F->r2 : 0u;
+    info[5] = F ? F->n_f3 : 0u;
+    info[6] = F ? F->r3 : 0u;
+    info[7] = F ? F->n_beta : 0u;
+    info[8] = F && F->alist ? 1u : 0u;
+    info[9] = F ? F->n_alpha : 0u;
+    info[10] = F && F->plist ? 1u : 0u;
+  });
+}
+
+}  // extern "C"

@@ -1,6 +1,8 @@
 // Device-side layout of the grouped operator and the configuration spaces.
 #pragma once
 
+#include <memory>
+
 #include "pbs_internal.h"
 
 // Operator grouped by X-mask (Eq. topological_group) plus the tables of the
@@ -62,6 +64,77 @@ constexpr uint32_t kClassSimple = 1u;       // only an X_beta = 0 group, few uni
 constexpr uint32_t kClassPairsSingle = 2u;  // every pair group has exactly one unique
 constexpr uint32_t kSimpleCap = 64;         // uniques of a "simple" class
 constexpr uint32_t kMaxQuads = 2048;        // largest C(h, 4) given a quad map (h <= 16)
+
+// Spin-factorized phase evaluation of one beta sector (Section 2.4,
+// Eqs. svd_weights, precomp_alpha, precomp_beta, svd_sreverse_sum and
+// dot_product; Algorithm grouped_hvec).  A group's coefficients in sector
+// form make a matrix M[mu][nu] over its distinct alpha Z-masks (rows) and
+// its uniques (columns, beta Z-masks); with a rank-R factorization M = P Q
+// its phase sum at target (t_a, t_b) is sum_r A_r(t_a) F_r(t_b), where
+//   A_r = sum_mu P[mu][r] (-1)^popcount(Za_mu & t_a)   ("factor uniques",
+//         folded per workgroup like the unfactored uniques), and
+//   F_r = sum_nu Q[r][nu] (-1)^popcount(Zb_nu & t_b)   (precomputed here for
+//         every beta string of the sector).
+// Factored groups: the X_beta = 0 group of every non-simple class (tables
+// fz, one per class and rank, indexed by beta column), and the pair and quad
+// groups of the class with X_alpha = 0 (tables indexed by the target's move:
+// em/fp for its single moves, eq/fq for its double moves).  Real
+// coefficients only.
+struct FactorPlan {
+  uint32_t n_orb = 0, n_beta = 0;  // the beta sector the tables are for
+  uint64_t dim_beta = 0;
+  uint32_t n_fu = 0, n_ft = 0;     // factor uniques and their terms
+  DevBuf<uint32_t> fu_t0;          // [n_fu + 1]
+  DevBuf<uint32_t> ft_za;          // [n_ft] alpha Z-mask (sector form)
+  DevBuf<double> ft_c;             // [n_ft] P[mu][r]
+  // per class: first factor unique of its X_beta = 0 group, rank (0 = not
+  // factored), offset of its fz rows (in doubles), 0
+  DevBuf<uint4> cls_f;
+  DevBuf<double> fz;
+  uint32_t max_r1 = 0;
+  // the X_alpha = 0 class (c0 < n_class when its pair and quad groups are factored)
+  uint32_t c0 = 0xffffffffu;
+  uint32_t c0_fu0 = 0, c0_fq = 0, c0_fu1 = 0;  // its pair-group, then quad-group factor uniques
+  uint32_t t_zero = 0, t_pair = 0, t_quad = 0;  // most terms of one factor unique, per kind
+  uint32_t r2 = 0, r3 = 0;          // rank of every factored pair / quad group (padded with zeros)
+  uint32_t n_moves = 0, n_qmoves = 0;
+  DevBuf<uint32_t> em;   // [n_moves][dim_beta]: source column | (4 + factor offset, or 0) << 16
+  DevBuf<double> fp;     // [n_moves][r2][dim_beta]
+  DevBuf<uint32_t> eq;   // [n_qmoves][dim_beta]: source column | (4 + factor offset, or 0) << 16
+  DevBuf<double> fq;     // [n_qmoves][r3][dim_beta]
+  // ranks found (for reporting): groups factored per kind and the largest rank
+  uint32_t n_f1 = 0, n_f2 = 0, n_f3 = 0;
+  // Alpha side of the alpha sector N_alpha (Eq. precomp_alpha) for the
+  // simple classes (one X_beta = 0 group whose uniques all have beta Z-mask
+  // 0, so a target's phase sum for the class depends on t_alpha alone):
+  // for alpha row i, entries alist_off[i] .. alist_off[i + 1] - 1 hold, in
+  // class order, the source row rank of every simple class whose source
+  // lies in the sector and the class's folded coefficient at t_alpha.
+  uint32_t n_alpha = 0;
+  bool alist = false;
+  DevBuf<uint32_t> alist_off;  // [dim_alpha + 1]
+  DevBuf<uint32_t> alist_src;
+  DevBuf<double> alist_c;
+  // Alpha side of the "image" classes (X_beta = 0 group factored with rank
+  // <= 2 or absent, every other group a single-unique pair group): for alpha
+  // row i, entries plist_off[i] .. plist_off[i + 1] - 1 list, in class order,
+  // the image classes whose source lies in the sector (source row rank,
+  // class), and entry e's image pimg[e * n_img ..] holds the folded
+  // coefficient of the class's pair group for each orbital pair (0 when
+  // absent), a 0 for padding moves, then the X_beta = 0 group's folded
+  // factors A_0, A_1.
+  bool plist = false;
+  uint32_t n_img = 0;
+  DevBuf<uint32_t> plist_off, plist_src, plist_cls;
+  DevBuf<double> pimg;
+  DevBuf<uint32_t> pimg_flag;  // [n_class]: 1 for image classes
+  // the operator's non-simple classes without the X_alpha = 0 class (when
+  // its tables exist), without the image classes, and without both
+  std::vector<uint32_t> ns_sizes;  // [3]
+  DevBuf<uint32_t> ns_rest[3];
+};
+constexpr uint32_t kMaxR1 = 32;       // largest factored rank of an X_beta = 0 group
+constexpr uint32_t kFactZeroSlots = 4;  // zero factors at the start of the class-0 fold
 }  // namespace pbs
 
 struct pbs_grouped {
@@ -100,6 +173,10 @@ struct pbs_grouped {
   pbs::DevBuf<uint32_t> pt_za;
   pbs::DevBuf<double> pt_c;
   bool real_coef = false;  // every sector-form coefficient has a zero imaginary part
+  // spin-factorized evaluation of one beta sector (pbs_grouped_factor) and
+  // whether applies use it
+  std::unique_ptr<pbs::FactorPlan> fplan;
+  uint32_t fact_on = 7u;  // which factored parts applies use (pbs_grouped_set_factored)
 };
 
 // Full space (D = 2^n) or spin sector.

@@ -72,9 +72,41 @@ __device__ inline double signed_by(double v, uint32_t p) {
   return __hiloint2double(__double2hiint(v) ^ static_cast<int>((p & 1u) << 31), __double2loint(v));
 }
 
+// v * (-1)^(bit 31 of e), one bitwise op on the high word (b ^ (a & c)).
+__device__ inline double signed_by_bit31(double v, uint32_t e) {
+  return __hiloint2double(
+      static_cast<int>(__builtin_amdgcn_bitop3_b32(e, static_cast<uint32_t>(__double2hiint(v)), 0x80000000u, 0x6c)),
+      __double2loint(v));
+}
+
 // Read-only load through the constant address space: uniform addresses
 // become scalar loads (the tables are never written by the kernels).
 __device__ inline uint32_t ldc(const uint32_t* p) { return *((const __attribute__((address_space(4))) uint32_t*)(p)); }
+__device__ inline double ldc(const double* p) { return *((const __attribute__((address_space(4))) double*)(p)); }
+
+// LDS load at an absolute byte address.  The kernels declare no static LDS,
+// so the dynamic allocation starts at address 0 and an address computed in a
+// register needs no base added.
+template <class U>
+struct LdsLoad {
+  __device__ static __forceinline__ U at(uint32_t byte) {
+    typedef __attribute__((address_space(3))) const U* LdsPtr;
+    return *(LdsPtr)(static_cast<uintptr_t>(byte));
+  }
+};
+template <class E>
+struct LdsLoad<HIP_vector_type<E, 2>> {  // two components (adjacent loads merge)
+  __device__ static __forceinline__ HIP_vector_type<E, 2> at(uint32_t byte) {
+    HIP_vector_type<E, 2> v;
+    v.x = LdsLoad<E>::at(byte);
+    v.y = LdsLoad<E>::at(byte + sizeof(E));
+    return v;
+  }
+};
+template <class U>
+__device__ __forceinline__ U lds_ld(uint32_t byte) {
+  return LdsLoad<U>::at(byte);
+}
 
 __device__ inline ClassMeta ld_meta(const ClassMeta* p) {
   static_assert(sizeof(ClassMeta) == 16 * sizeof(uint32_t), "ClassMeta layout");
@@ -137,6 +169,9 @@ struct Coef<false> {
     acc.y += signed_by(c.y, par);
   }
   __device__ static inline V sign(V c, uint32_t par) { return make_double2(signed_by(c.x, par), signed_by(c.y, par)); }
+  __device__ static inline V sign31(V c, uint32_t e) {
+    return make_double2(signed_by_bit31(c.x, e), signed_by_bit31(c.y, e));
+  }
   __device__ static inline V zeroed_unless(V f, bool keep) { return keep ? f : zero(); }
   // acc += f * a
   __device__ static inline void mac(V f, double ar, double ai, double& acc_r, double& acc_i) {
@@ -151,6 +186,7 @@ struct Coef<true> {
   __device__ static inline V term(const double2* c, uint32_t t) { return c[t].x; }
   __device__ static inline void add_signed(V& acc, V c, uint32_t par) { acc += signed_by(c, par); }
   __device__ static inline V sign(V c, uint32_t par) { return signed_by(c, par); }
+  __device__ static inline V sign31(V c, uint32_t e) { return signed_by_bit31(c, e); }
   __device__ static inline V zeroed_unless(V f, bool keep) { return keep ? f : 0.0; }
   __device__ static inline void mac(V f, double ar, double ai, double& acc_r, double& acc_i) {
     acc_r = fma(ar, f, acc_r);
@@ -169,13 +205,17 @@ constexpr uint32_t kRank16Lds = 10u * 256u;
 constexpr int kGather = 16;  // simple-class row loads in flight per lane
 // Fixed LDS placement (the kernel declares no static LDS, so these are
 // absolute addresses): workgroup scratch at byte 0, the pair map at kPuOff
-// (one word per orbital pair, at most C(32, 2) + 1 entries) and the staged
+// (an 8-byte slot per orbital pair, at most C(32, 2) + 1 entries) and the staged
 // row at kRowOff, so per-move addresses need no base register.
 constexpr uint32_t kMiscBytes = 256;  // ballot counts and the energy reduction
 constexpr uint32_t kPuOff = kMiscBytes;
-constexpr uint32_t kPuBytes = 2048;
+constexpr uint32_t kPuBytes = 4096;
 constexpr uint32_t kRowOff = kPuOff + kPuBytes;
 constexpr uint32_t kZeroSlots = 4;  // zero entries after the folded uniques (absent groups, padding)
+
+constexpr uint32_t kFactZero = 1u;  // X_beta = 0 groups through their F rows
+constexpr uint32_t kFactMoves = 2u;  // the X_alpha = 0 class through the move tables
+constexpr uint32_t kFactAlpha = 4u;  // simple classes through the alpha lists
 
 struct SectorArgs {
   uint32_t n_orb, n_alpha, n_beta, n_chunks;
@@ -205,6 +245,35 @@ struct SectorArgs {
   const uint32_t* u_t0;
   const uint32_t* pt_za;
   const double2* pt_c;
+  // spin-factorized evaluation (FactorPlan; real coefficients): fact holds
+  // kFactZero when X_beta = 0 groups use their F rows (0 when unused); f_c0
+  // = the X_alpha = 0 class whose pair and quad groups are evaluated through
+  // the move tables, or ~0
+  uint32_t fact, f_c0, f_r2, f_r3, f_c0_fu0, f_c0_fu1, f_n_qmoves, off_a;
+  // longest factor unique (terms) among: the X_beta = 0 groups', the class-0
+  // pair groups' (factor uniques f_c0_fu0 .. f_c0_fq - 1) and quad groups'
+  uint32_t f_tz, f_tp, f_tq, f_c0_fq;
+  // alpha lists of the simple classes (FactorPlan::alist_*), or null: pass A
+  // then reads each row's valid simple classes and coefficients directly
+  const uint32_t* alist_off;
+  const uint32_t* alist_src;
+  const double* alist_c;
+  // alpha images of the image classes (FactorPlan::plist, pimg), or null
+  const uint32_t* plist_off;
+  const uint32_t* plist_src;
+  const uint32_t* plist_cls;
+  const double* pimg;
+  const uint32_t* pimg_flag;
+  uint32_t n_img, pad_img;
+  const uint32_t* fu_t0;
+  const uint32_t* ft_za;
+  const double* ft_c;
+  const uint4* cls_f;
+  const double* fz;
+  const uint32_t* em;
+  const double* fp;
+  const uint32_t* eq;
+  const double* fq;
 };
 
 // Combinatorial rank of a spin string: uint16 tables in LDS (n_orb <= 16,
@@ -237,6 +306,40 @@ __device__ inline void fold_uniques(const SectorArgs& P, uint32_t ua, uint32_t u
     F[u - ua] = f;
     Fz[u - ua] = P.u_zb[u];
   }
+}
+
+// A_r = sum over the factor unique's terms of P[mu][r] (-1)^popcount(za & ta)
+// for factor uniques fa .. fb-1, written to A[0 ..).  L consecutive lanes
+// share a factor unique (lane j of the set takes terms j, j + L, ...) and
+// add their parts in a fixed butterfly, so the loads of a unique's terms are
+// issued together and the result does not depend on timing.
+template <int L>
+__device__ inline void fold_factors_l(const SectorArgs& P, uint32_t fa, uint32_t fb, uint32_t ta, double* A,
+                                      uint32_t lane0, uint32_t stride) {
+  const uint32_t j = lane0 % L;
+  for (uint32_t u0 = fa; u0 < fb; u0 += stride / L) {
+    const uint32_t u = u0 + lane0 / L;
+    double f = 0.0;
+    if (u < fb) {
+      const uint32_t t1 = P.fu_t0[u + 1];
+      for (uint32_t t = P.fu_t0[u] + j; t < t1; t += L) f += signed_by(P.ft_c[t], __popc(P.ft_za[t] & ta));
+    }
+#pragma unroll
+    for (int d = L / 2; d > 0; d /= 2) f += __shfl_xor(f, d, 64);
+    if (u < fb && j == 0) A[u - fa] = f;
+  }
+}
+
+// lanes per factor unique for a range whose longest factor unique has
+// `terms` terms
+__device__ inline void fold_factors(const SectorArgs& P, uint32_t fa, uint32_t fb, uint32_t terms, uint32_t ta,
+                                    double* A, uint32_t lane0, uint32_t stride) {
+  if (terms <= 1)
+    fold_factors_l<1>(P, fa, fb, ta, A, lane0, stride);
+  else if (terms <= 16)
+    fold_factors_l<16>(P, fa, fb, ta, A, lane0, stride);
+  else
+    fold_factors_l<64>(P, fa, fb, ta, A, lane0, stride);
 }
 
 template <bool REALC>
@@ -374,6 +477,71 @@ __device__ __forceinline__ void quad_moves(const SectorArgs& P, uint32_t tb, con
   }
 }
 
+// Factored groups of the X_alpha = 0 class through a move table (single or
+// double moves of this lane's beta string, n per string): entry = source
+// column | (first folded factor of the move's group, or a zero slot) << 16,
+// and F_r of that group at this lane's beta string.  Software-pipelined
+// over three register buffers of 8 / R moves: while one buffer is
+// evaluated, the table loads of the next two are in flight.
+template <int R, class T, bool ROWLDS>
+struct MoveTable {
+  static constexpr int kU = 8 / R;
+  uint32_t e[kU];
+  double F[kU][R];
+  __device__ __forceinline__ void load(const uint32_t* ent, const double* fv, uint64_t db, uint32_t col, uint32_t q0,
+                                       uint32_t n) {
+#pragma unroll
+    for (int i = 0; i < kU; ++i) {
+      const uint32_t m = min(q0 + i, n - 1u);  // past the end: reload the last move (unused)
+      e[i] = ent[static_cast<uint64_t>(m) * db + col];
+#pragma unroll
+      for (int r = 0; r < R; ++r) F[i][r] = fv[(static_cast<uint64_t>(m) * R + r) * db + col];
+    }
+  }
+  __device__ __forceinline__ void eval(const unsigned char* smem, const double* s_A, const T* rowg, uint32_t q0,
+                                       uint32_t n, double (&ar4)[4], double (&ai4)[4]) const {
+    double a_r[kU], a_i[kU];
+#pragma unroll
+    for (int i = 0; i < kU; ++i) {
+      if (ROWLDS)
+        Amp<T>::load(reinterpret_cast<const T*>(smem + kRowOff), e[i] & 0xffffu, a_r[i], a_i[i]);
+      else
+        Amp<T>::load(rowg, e[i] & 0xffffu, a_r[i], a_i[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < kU; ++i) {
+      double f = 0.0;
+#pragma unroll
+      for (int r = 0; r < R; ++r) f = fma(s_A[(e[i] >> 16) + r], F[i][r], f);
+      f = q0 + i < n ? f : 0.0;  // moves past the end (uniform)
+      Coef<true>::mac(f, a_r[i], a_i[i], ar4[i & 3], ai4[i & 3]);
+    }
+  }
+};
+
+template <int R, class T, bool ROWLDS>
+__device__ __forceinline__ void fact_table_moves(const unsigned char* smem, const double* s_A, const T* rowg,
+                                                 uint32_t n, const uint32_t* ent, const double* fv, uint64_t db,
+                                                 uint32_t col, double (&ar4)[4], double (&ai4)[4]) {
+  using MT = MoveTable<R, T, ROWLDS>;
+  constexpr uint32_t U = MT::kU;
+  if (n == 0) return;
+  MT b0, b1, b2;
+  b0.load(ent, fv, db, col, 0, n);
+  b1.load(ent, fv, db, col, U, n);
+  for (uint32_t q0 = 0;; q0 += 3 * U) {
+    b2.load(ent, fv, db, col, q0 + 2 * U, n);
+    b0.eval(smem, s_A, rowg, q0, n, ar4, ai4);
+    if (q0 + U >= n) break;
+    b0.load(ent, fv, db, col, q0 + 3 * U, n);
+    b1.eval(smem, s_A, rowg, q0 + U, n, ar4, ai4);
+    if (q0 + 2 * U >= n) break;
+    b1.load(ent, fv, db, col, q0 + 4 * U, n);
+    b2.eval(smem, s_A, rowg, q0 + 2 * U, n, ar4, ai4);
+    if (q0 + 3 * U >= n) break;
+  }
+}
+
 // Appends to the list, in class order, the simple classes c0 .. c1-1 whose
 // source alpha string ta ^ X_alpha lies in the sector: entry = (source row
 // rank, first folded unique | unique count << 16), where a class's uniques
@@ -392,7 +560,13 @@ __device__ uint32_t append_valid_rows(const SectorArgs& P, uint32_t c0, uint32_t
       const ClassMeta* m = P.meta + cc;
       const uint32_t sa = ta ^ m->xa;
       v = static_cast<uint32_t>(__popc(sa)) == P.n_alpha;
-      if (v) entry = make_uint2(rank_of<R16>(sa, P, s_rank), (m->ua - ubase) | ((m->u_end - m->ua) << 16));
+      if (v) {
+        // bit 31: the class's single unique has beta Z-mask 0 (its phase sum
+        // is the folded coefficient itself, as for same-spin alpha doubles)
+        const uint32_t cnt = m->u_end - m->ua;
+        const uint32_t plain = (cnt == 1 && P.u_zb[m->ua] == 0u) ? 0x80000000u : 0u;
+        entry = make_uint2(rank_of<R16>(sa, P, s_rank), (m->ua - ubase) | (cnt << 16) | plain);
+      }
     }
     const uint64_t bal = __ballot(v);
     if (lane == 0) s_wcnt[wave] = static_cast<uint32_t>(__popcll(bal));
@@ -465,6 +639,10 @@ __device__ __forceinline__ void sector_body(const SectorArgs& P, const T* __rest
       if (w < kWords) s_rank32[w] = v[k];
     }
   }
+  // beta Z-masks of the pair moves, for the move cache below (the pair-map
+  // region is free until pass B)
+  if (P.enum_ok && P.pair_sign && threadIdx.x <= P.n_pairs)
+    reinterpret_cast<uint32_t*>(smem + kPuOff)[threadIdx.x] = P.zpair[threadIdx.x];
   if (threadIdx.x < kZeroSlots) {  // zero slots for absent groups and padding entries
     s_F[f_cap + threadIdx.x] = C::zero();
     s_Fz[f_cap + threadIdx.x] = 0u;
@@ -481,13 +659,62 @@ __device__ __forceinline__ void sector_body(const SectorArgs& P, const T* __rest
 
   double ar4[4] = {0.0, 0.0, 0.0, 0.0}, ai4[4] = {0.0, 0.0, 0.0, 0.0};
 
+  // pass A through the alpha list: the row's valid simple classes in class
+  // order, each a source row rank and a coefficient uniform across the
+  // workgroup.  The row's list is copied into LDS (the staged-row region is
+  // free here) in pieces; each gather then reads its entry as a broadcast
+  // LDS load, and two buffers of kGather / 2 rows keep the next gathers in
+  // flight while the current ones are summed.
+  if (P.alist_off != nullptr) {
+    const uint32_t a0 = ldc(P.alist_off + ia), a1 = ldc(P.alist_off + ia + 1);
+    constexpr uint32_t G = kGather / 2;
+    const uint32_t cap = (P.list_cap * 8u / 12u) & ~(2u * G - 1u);  // entries per piece (4 + 8 bytes each)
+    const uint32_t* s_src = reinterpret_cast<const uint32_t*>(smem + kRowOff);
+    const double* s_c = reinterpret_cast<const double*>(smem + kRowOff + 4u * cap);
+    const T* psi_col = psi + colc;
+    struct Buf {
+      double c[G];
+      T a[G];
+    } b0, b1;
+    for (uint32_t p0 = a0; p0 < a1; p0 += cap) {
+      const uint32_t n = min(cap, a1 - p0);
+      __syncthreads();
+      for (uint32_t j = threadIdx.x; j < n; j += kSB) {
+        reinterpret_cast<uint32_t*>(smem + kRowOff)[j] = P.alist_src[p0 + j];
+        reinterpret_cast<double*>(smem + kRowOff + 4u * cap)[j] = P.alist_c[p0 + j];
+      }
+      __syncthreads();
+      auto load = [&](uint32_t e0, Buf& b) {
+#pragma unroll
+        for (uint32_t i = 0; i < G; ++i) {
+          const uint32_t m = min(e0 + i, n - 1u);
+          b.c[i] = e0 + i < n ? s_c[m] : 0.0;
+          b.a[i] = psi_col[static_cast<uint64_t>(s_src[m]) * db];
+        }
+      };
+      auto eval = [&](const Buf& b) {
+#pragma unroll
+        for (uint32_t i = 0; i < G; ++i)
+          Coef<true>::mac(b.c[i], static_cast<double>(b.a[i].x), static_cast<double>(b.a[i].y), ar4[i & 3],
+                          ai4[i & 3]);
+      };
+      load(0, b0);
+      for (uint32_t e0 = 0; e0 < n; e0 += 2 * G) {
+        if (e0 + G < n) load(e0 + G, b1);
+        eval(b0);
+        if (e0 + G >= n) break;
+        if (e0 + 2 * G < n) load(e0 + 2 * G, b0);
+        eval(b1);
+      }
+    }
+  }
   // pass A: the simple classes (runs of consecutive ones).  A batch takes
   // whole runs, or pieces of a long run, while their uniques fit in LDS and
   // their classes in the list; each piece is folded at a running offset, the
   // valid source rows of the batch are listed (in class order) and gathered
   // kGather at a time, so the row loads overlap.  This pass runs before the
   // move cache below exists, leaving registers for the loads in flight.
-  {
+  if (P.alist_off == nullptr) {
     uint32_t r = 0;
     uint32_t c = P.n_runs ? P.runs[0] : 0u;
     while (r < P.n_runs) {
@@ -514,7 +741,7 @@ __device__ __forceinline__ void sector_body(const SectorArgs& P, const T* __rest
       }
       // pad to a multiple of kGather with entries that read row 0 against a zero slot
       const uint32_t padded = (n_list + kGather - 1u) / kGather * kGather;
-      if (threadIdx.x < padded - n_list) s_list[n_list + threadIdx.x] = make_uint2(0u, f_cap | (1u << 16));
+      if (threadIdx.x < padded - n_list) s_list[n_list + threadIdx.x] = make_uint2(0u, f_cap | (1u << 16) | 0x80000000u);
       __syncthreads();
       for (uint32_t e0 = 0; e0 < padded; e0 += kGather) {
         uint32_t rk[kGather], w[kGather];
@@ -526,24 +753,102 @@ __device__ __forceinline__ void sector_body(const SectorArgs& P, const T* __rest
           w[i] = __builtin_amdgcn_readfirstlane(L.y);
         }
 #pragma unroll
-        for (int i = 0; i < kGather; ++i) ld_amp<T>(psi, static_cast<uint64_t>(rk[i]) * db + colc, a_r[i], a_i[i]);
+        for (int i = 0; i < kGather; ++i) ld_amp<T>(psi + static_cast<uint64_t>(rk[i]) * db, colc, a_r[i], a_i[i]);
 #pragma unroll
         for (int i = 0; i < kGather; ++i) {
           V f = C::zero();
-          phase_sum_lds<REALC>(s_F, s_Fz, w[i] & 0xffffu, w[i] >> 16, tb, f);
+          if (w[i] >> 31)
+            f = s_F[w[i] & 0xffffu];
+          else
+            phase_sum_lds<REALC>(s_F, s_Fz, w[i] & 0xffffu, (w[i] >> 16) & 0x7fffu, tb, f);
           C::mac(f, a_r[i], a_i[i], ar4[i & 3], ai4[i & 3]);
         }
       }
     }
   }
 
+  // pass Q: with factor tables, the whole X_alpha = 0 class (first of the
+  // other classes; its source row is the target row): row staged, factors
+  // folded, then its X_beta = 0 group through its F rows and its pair and
+  // quad groups through the single- and double-move tables.  It runs before
+  // the move cache below takes its registers, and pass B skips the class.
+  if constexpr (REALC && ROWLDS) {
+    if (P.fact && P.f_c0 != 0xffffffffu) {  // the class is then absent from ns_list
+      const ClassMeta M = ld_meta(P.meta + P.f_c0);
+      const T* rowg = psi + ia * db;
+      const bool stage = P.row_lds != 0;
+      const uint32_t* cf = reinterpret_cast<const uint32_t*>(P.cls_f + P.f_c0);
+      const uint32_t fz_fu0 = ldc(cf), fz_r = (P.fact & kFactZero) ? ldc(cf + 1) : 0u;
+      const uint64_t fz_off = ldc(cf + 2) | (static_cast<uint64_t>(ldc(cf + 3)) << 32);
+      double* s_Fd = reinterpret_cast<double*>(smem + P.off_f);
+      double* s_A = reinterpret_cast<double*>(smem + P.off_a);
+      constexpr uint32_t kZv = 16;  // F rows of the X_beta = 0 group loaded before the folds
+      double zv[kZv];
+#pragma unroll
+      for (uint32_t r = 0; r < kZv; ++r) zv[r] = r < fz_r ? P.fz[fz_off + r * db + colc] : 0.0;
+      __syncthreads();  // pass A's list and folds are consumed
+      const bool stager = stage && threadIdx.x < kSB / 2;
+      const uint32_t lane0 = stage ? threadIdx.x % (kSB / 2) : threadIdx.x;
+      const uint32_t stride = stage ? kSB / 2 : kSB;
+      if (stager) {
+        stage_row<T>(s_row, rowg, db, lane0, stride);
+      } else {
+        if (lane0 < kFactZeroSlots) s_Fd[lane0] = 0.0;
+        fold_factors(P, P.f_c0_fu0, P.f_c0_fq, P.f_tp, ta, s_Fd + kFactZeroSlots, lane0, stride);
+        fold_factors(P, P.f_c0_fq, P.f_c0_fu1, P.f_tq, ta, s_Fd + kFactZeroSlots + (P.f_c0_fq - P.f_c0_fu0), lane0,
+                     stride);
+        if (fz_r) fold_factors(P, fz_fu0, fz_fu0 + fz_r, P.f_tz, ta, s_A, lane0, stride);
+      }
+      __syncthreads();
+      if (M.zg >= 0) {
+        double f = 0.0;
+        if (fz_r) {
+#pragma unroll
+          for (uint32_t r = 0; r < kZv; ++r) f = fma(s_A[r < fz_r ? r : 0], zv[r], f);  // zv[r] = 0 past fz_r
+          const double* fr = P.fz + fz_off + colc;
+          for (uint32_t r = kZv; r < fz_r; ++r) f = fma(s_A[r], fr[r * db], f);
+        } else {
+          phase_sum_direct<true>(P, static_cast<uint32_t>(M.zg), ta, tb, f);
+        }
+        double a_r, a_i;
+        if (ROWLDS)
+          ld_amp<T>(s_row, colc, a_r, a_i);
+        else
+          ld_amp<T>(rowg, colc, a_r, a_i);
+        Coef<true>::mac(f, a_r, a_i, ar4[0], ai4[0]);
+      }
+      if (P.f_r2 == 1)
+        fact_table_moves<1, T, ROWLDS>(smem, s_Fd, rowg, P.n_moves, P.em, P.fp, db, colc, ar4, ai4);
+      else
+        fact_table_moves<2, T, ROWLDS>(smem, s_Fd, rowg, P.n_moves, P.em, P.fp, db, colc, ar4, ai4);
+      if (P.f_r3 == 1)
+        fact_table_moves<1, T, ROWLDS>(smem, s_Fd, rowg, P.f_n_qmoves, P.eq, P.fq, db, colc, ar4, ai4);
+      else
+        fact_table_moves<2, T, ROWLDS>(smem, s_Fd, rowg, P.f_n_qmoves, P.eq, P.fq, db, colc, ar4, ai4);
+      // groups beyond the quads (none for two-body operators) are scanned
+      uint32_t gs = M.q1;
+      while (gs < M.g1) {
+        const uint32_t xb = P.pg_xb[gs];
+        const bool valid = live && 2u * __popc(tb & xb) == static_cast<uint32_t>(__popc(xb));
+        if (valid) {
+          double f = 0.0;
+          phase_sum_direct<true>(P, gs, ta, tb, f);
+          double a_r, a_i;
+          ld_amp<T>(rowg, rank_of<R16>(tb ^ xb, P, s_rank), a_r, a_i);
+          Coef<true>::mac(f, a_r, a_i, ar4[1], ai4[1]);
+        }
+        ++gs;
+      }
+    }
+  }
+
   // Pair moves of this lane's target (occupied p -> empty q), occupied-major,
   // packed as: bits 0-15 the source column (its LDS byte offset in the staged
-  // row when rows are staged), bits 16-26 the pair-map byte offset 4 pair(p, q),
+  // row when rows are staged), bits 16-27 the pair-map byte offset 8 pair(p, q),
   // bit 31 the move's beta parity popcount(zpair & t_b) when cached.
   uint32_t mv[kMaxMoves];
   // padding moves point at map entry n_pairs (a zero slot) and column 0
-  const uint32_t pad_move = (4u * P.n_pairs) << 16;
+  const uint32_t pad_move = (8u * P.n_pairs) << 16;
   if (P.enum_ok) {
     const uint32_t full = (n_orb == 32) ? 0xffffffffu : ((1u << n_orb) - 1u);
     const uint32_t emp = ~tb & full;
@@ -559,8 +864,9 @@ __device__ __forceinline__ void sector_body(const SectorArgs& P, const T* __rest
         const uint32_t lo = p < q ? p : q, hi = p < q ? q : p;
         const uint32_t pair = hi * (hi - 1) / 2 + lo;
         const uint32_t src = rank_of<R16>(tb ^ (1u << p) ^ (1u << q), P, s_rank);
-        const uint32_t par = P.pair_sign ? (static_cast<uint32_t>(__popc(P.zpair[pair] & tb)) & 1u) : 0u;
-        mv[k] = (ROWLDS ? src * static_cast<uint32_t>(sizeof(T)) : src) | ((4u * pair) << 16) | (par << 31);
+        const uint32_t par =
+            P.pair_sign ? (static_cast<uint32_t>(__popc(lds_ld<uint32_t>(kPuOff + 4u * pair) & tb)) & 1u) : 0u;
+        mv[k] = (ROWLDS ? src * static_cast<uint32_t>(sizeof(T)) : src) | ((8u * pair) << 16) | (par << 31);
         if (++j == ne) {
           j = 0;
           pm_emp = emp;
@@ -571,9 +877,84 @@ __device__ __forceinline__ void sector_body(const SectorArgs& P, const T* __rest
     }
   }
 
+  // pass B through the alpha images: for each image class of this row (in
+  // class order) the source row is staged while the other half of the
+  // workgroup copies the class's precomputed image -- the folded pair-group
+  // coefficient per orbital pair and the X_beta = 0 group's factors -- into
+  // the pair-map region, so each cached move reads its coefficient directly
+  // (staged rows only)
+  if constexpr (REALC && ROWLDS) {
+    if (P.plist_off != nullptr) {
+      const uint32_t b0 = ldc(P.plist_off + ia), b1 = ldc(P.plist_off + ia + 1);
+      uint32_t n_moves = __builtin_amdgcn_readfirstlane(P.n_moves);
+      const uint32_t n_img = P.n_img, n_pairs = P.n_pairs;
+      const double* s_Af = reinterpret_cast<const double*>(smem + P.off_a);
+      const bool stage = P.row_lds != 0;
+      const bool stager = stage && threadIdx.x < kSB / 2;
+      const uint32_t lane0 = stage ? threadIdx.x % (kSB / 2) : threadIdx.x;
+      const uint32_t stride = stage ? kSB / 2 : kSB;
+      // each copying lane holds its image element of the next class, loaded
+      // while the current class is evaluated
+      double imv = (b1 > b0 && !stager && lane0 < n_img) ? P.pimg[static_cast<uint64_t>(b0) * n_img + lane0] : 0.0;
+      for (uint32_t k = b0; k < b1; ++k) {
+        const uint32_t src = ldc(P.plist_src + k), cid = ldc(P.plist_cls + k);
+        const uint32_t* cf = reinterpret_cast<const uint32_t*>(P.cls_f + cid);
+        const uint32_t fz_r = ldc(cf + 1);
+        const uint64_t fz_off = ldc(cf + 2) | (static_cast<uint64_t>(ldc(cf + 3)) << 32);
+        const double zv0 = fz_r > 0 ? P.fz[fz_off + colc] : 0.0;
+        const double zv1 = fz_r > 1 ? P.fz[fz_off + db + colc] : 0.0;
+        const T* rowg = psi + static_cast<uint64_t>(src) * db;
+        __syncthreads();
+        if (stager) {
+          stage_row<T>(s_row, rowg, db, lane0, stride);
+        } else {
+          const double* im = P.pimg + static_cast<uint64_t>(k) * n_img;
+          for (uint32_t j = lane0; j < n_img; j += stride) {
+            const uint32_t at = j <= n_pairs ? kPuOff + 8u * j : P.off_a + 8u * (j - n_pairs - 1u);
+            *reinterpret_cast<double*>(smem + at) = j == lane0 ? imv : im[j];
+          }
+          if (k + 1 < b1 && lane0 < n_img) imv = im[n_img + lane0];
+        }
+        __syncthreads();
+        if (fz_r) {
+          const double f = fma(s_Af[0], zv0, s_Af[1] * zv1);
+          double a_r, a_i;
+          if (ROWLDS)
+            ld_amp<T>(s_row, colc, a_r, a_i);
+          else
+            ld_amp<T>(rowg, colc, a_r, a_i);
+          Coef<true>::mac(f, a_r, a_i, ar4[0], ai4[0]);
+        }
+        uint32_t o16 = 16u, o0 = 0u;
+        asm volatile("" : "+s"(o16), "+s"(o0));
+#pragma unroll
+        for (int k0 = 0; k0 < kMaxMoves; k0 += 4) {
+          if (static_cast<uint32_t>(k0) < n_moves) {
+            double f[4], a_r[4], a_i[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              f[i] = lds_ld<double>(kPuOff + __builtin_amdgcn_ubfe(mv[k0 + i], o16, 12));
+              if (ROWLDS) {
+                const T v = lds_ld<T>(kRowOff + __builtin_amdgcn_ubfe(mv[k0 + i], o0, 16));
+                a_r[i] = static_cast<double>(v.x);
+                a_i[i] = static_cast<double>(v.y);
+              } else {
+                move_amp<T, false>(smem, rowg, mv[k0 + i], a_r[i], a_i[i]);
+              }
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+              Coef<true>::mac(signed_by_bit31(f[i], mv[k0 + i]), a_r[i], a_i[i], ar4[i], ai4[i]);
+          }
+        }
+      }
+    }
+  }
+
   // pass B: every other class, in class order
   for (uint32_t ic = 0; ic < P.n_ns; ++ic) {
-    const ClassMeta M = ld_meta(P.meta + P.ns_list[ic]);
+    const uint32_t cid = P.ns_list[ic];
+    const ClassMeta M = ld_meta(P.meta + cid);
     const uint32_t sa = ta ^ M.xa;
     if (static_cast<uint32_t>(__popc(sa)) != P.n_alpha) continue;
     const uint64_t rowoff = static_cast<uint64_t>(rank_of<R16>(sa, P, s_rank)) * db;
@@ -597,9 +978,10 @@ __device__ __forceinline__ void sector_body(const SectorArgs& P, const T* __rest
       const bool stager = !split || threadIdx.x < kSB / 2;
       const uint32_t lane0 = split ? threadIdx.x % (kSB / 2) : threadIdx.x;
       const uint32_t stride = split ? kSB / 2 : kSB;
+      const bool folder = !split || !stager;
       if (stage && stager) stage_row<T>(s_row, rowg, db, lane0, stride);
-      if (fold_a && (!split || !stager)) fold_uniques<REALC>(P, M.ua, ub_a, ta, s_F, s_Fz, lane0, stride);
-      if (penum && (!split || !stager)) {
+      if (fold_a && folder) fold_uniques<REALC>(P, M.ua, ub_a, ta, s_F, s_Fz, lane0, stride);
+      if (penum && folder) {
         const int32_t* pm = P.pmap + static_cast<uint64_t>(M.pm) * P.n_pairs;
         for (uint32_t q = lane0; q <= P.n_pairs; q += stride) {
           const int32_t g = q < P.n_pairs ? pm[q] : -1;  // entry n_pairs serves the padding moves
@@ -608,7 +990,7 @@ __device__ __forceinline__ void sector_body(const SectorArgs& P, const T* __rest
             v = P.off_f + (g >= 0 ? P.pg_u0[g] - M.ua : f_cap) * static_cast<uint32_t>(sizeof(V));
           else
             v = g >= 0 ? ((P.pg_u0[g] - M.ua) | ((P.pg_u0[g + 1] - P.pg_u0[g]) << 16)) : 0u;
-          s_pu[q] = v;
+          s_pu[2 * q] = v;  // 8-byte slots: a move holds 8 pair(p, q) << 16
         }
       }
       __syncthreads();
@@ -633,25 +1015,32 @@ __device__ __forceinline__ void sector_body(const SectorArgs& P, const T* __rest
       if (single) {
         // straight-line groups of four moves: one unique per pair group; absent
         // groups and padding moves hit the zero slot, so loads issue together
+        // The field offsets are opaque scalars redefined per class, so the
+        // per-move bit-field extracts stay inside the class loop (hoisting
+        // them would need 2 registers per cached move) at one VALU each.
+        uint32_t o16 = 16u, o0 = 0u;
+        asm volatile("" : "+s"(o16), "+s"(o0));
 #pragma unroll
         for (int k0 = 0; k0 < kMaxMoves; k0 += 4) {
           if (static_cast<uint32_t>(k0) < n_moves) {
-            uint32_t fa[4], e[4];
+            uint32_t fa[4];
             V f[4];
             double a_r[4], a_i[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-              e[i] = mv[k0 + i];
-              asm volatile("" : "+v"(e[i]));  // keep per-move address arithmetic inside the class loop
-              fa[i] = *reinterpret_cast<const uint32_t*>(smem + kPuOff + ((e[i] >> 16) & 0x7ffu));
-            }
+            for (int i = 0; i < 4; ++i) fa[i] = lds_ld<uint32_t>(kPuOff + __builtin_amdgcn_ubfe(mv[k0 + i], o16, 12));
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-              f[i] = *reinterpret_cast<const V*>(smem + fa[i]);
-              move_amp<T, ROWLDS>(smem, rowg, e[i], a_r[i], a_i[i]);
+              f[i] = lds_ld<V>(fa[i]);
+              if (ROWLDS) {
+                const T v = lds_ld<T>(kRowOff + __builtin_amdgcn_ubfe(mv[k0 + i], o0, 16));
+                a_r[i] = static_cast<double>(v.x);
+                a_i[i] = static_cast<double>(v.y);
+              } else {
+                Amp<T>::load(rowg, __builtin_amdgcn_ubfe(mv[k0 + i], o0, 16), a_r[i], a_i[i]);
+              }
             }
 #pragma unroll
-            for (int i = 0; i < 4; ++i) C::mac(C::sign(f[i], e[i] >> 31), a_r[i], a_i[i], ar4[i], ai4[i]);
+            for (int i = 0; i < 4; ++i) C::mac(C::sign31(f[i], mv[k0 + i]), a_r[i], a_i[i], ar4[i], ai4[i]);
           }
         }
       } else {
@@ -660,7 +1049,7 @@ __device__ __forceinline__ void sector_body(const SectorArgs& P, const T* __rest
           if (static_cast<uint32_t>(k) < n_moves) {
             uint32_t e = mv[k];
             asm volatile("" : "+v"(e));
-            const uint32_t w = *reinterpret_cast<const uint32_t*>(smem + kPuOff + ((e >> 16) & 0x7ffu));
+            const uint32_t w = *reinterpret_cast<const uint32_t*>(smem + kPuOff + ((e >> 16) & 0xfffu));
             V f = C::zero();
             phase_sum_lds<REALC>(s_F, s_Fz, w & 0xffffu, w >> 16, tb, f);
             double a_r, a_i;
@@ -673,8 +1062,8 @@ __device__ __forceinline__ void sector_body(const SectorArgs& P, const T* __rest
 
     // phase Q: groups whose X_beta flips four orbitals, by enumerating the
     // lane's valid double moves against a per-class quad map
-    const bool qenum =
-        penum && P.qenum_ok && M.qm >= 0 && M.u_q - M.u_p <= f_cap && 2 * (M.q1 - M.p1) >= P.n_qmoves;
+    const bool qenum = penum && P.qenum_ok && M.qm >= 0 && M.u_q - M.u_p <= f_cap &&
+                       2 * (M.q1 - M.p1) >= P.n_qmoves;
     if (qenum) {
       __syncthreads();
       fold_uniques<REALC>(P, M.u_p, M.u_q, ta, s_F, s_Fz);

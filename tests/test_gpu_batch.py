@@ -25,13 +25,15 @@ JOBS = [(4, 2, 2, 11, 21), (5, 2, 3, 12, 22), (6, 3, 3, 13, 23), (7, 3, 2, 14, 2
         (7, 4, 3, 16, 26), (3, 1, 1, 17, 27), (8, 4, 4, 18, 28)]
 
 
-def _build(dev, dtype):
+def _build(dev, dtype, factor=False):
     api = _api()
     jobs, refs = [], []
     for n_o, na, nb, hs, ps in JOBS:
         h1, h2 = synth.molecular_spin_integrals(n_o, hs)
         G = api.jw_transform(torch.from_numpy(h1).to(dev), torch.from_numpy(h2).to(dev)).group()
         sp = api.Space.sector(n_o, na, nb)
+        if factor:
+            G.factor(sp)  # spin-factorized tables for this job's beta sector
         psi_np = synth.random_state(sp.dim, ps)
         if dtype == torch.complex64:
             psi_np = psi_np.astype(np.complex64).astype(np.complex128)
@@ -127,13 +129,13 @@ def _oracle_refs(refs):
 @pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
 def test_every_schedule_matches_oracle(dev, dtype):
     api = _api()
-    jobs, refs = _build(dev, dtype)
+    jobs, refs = _build(dev, dtype, factor=True)
     want = _oracle_refs(refs)
     batch = api.Batch(jobs)
     tol = 1e-12 if dtype == torch.complex128 else 1e-6
     energies = torch.zeros(3 * len(jobs), dtype=torch.float64, device=dev)
     first = {}  # flags -> outputs under the first workgroup order tried
-    for config in range(64):
+    for config in range(128):
         batch.set_config(config)
         assert batch.info()[0] == config and batch.info()[1] == -1.0
         for _, _, _, out in jobs:
@@ -146,7 +148,7 @@ def test_every_schedule_matches_oracle(dev, dtype):
             assert abs(e[k, 0] - e_ref) < 1e-11 * max(1.0, abs(e_ref)), (config, k)
         # the workgroup order moves work between workgroups, never within a target
         outs = [torch.view_as_real(j[3]).clone() for j in jobs]
-        flags = config & 15
+        flags = config & (15 | 64)
         if flags in first:
             assert all(torch.equal(a, b) for a, b in zip(outs, first[flags])), config
         else:
@@ -160,7 +162,7 @@ def test_tuner_keeps_the_fastest_schedule(dev):
     batch = api.Batch(jobs)
     wg0 = batch.info()[2]
     config, ms = batch.tune(reps=2)
-    assert 0 <= config < 64 and ms > 0.0
+    assert 0 <= config < 128 and ms > 0.0
     assert batch.info() == (config, ms, wg0)  # the workgroup count does not depend on the schedule
     for _, _, _, out in jobs:
         out.zero_()
@@ -169,7 +171,7 @@ def test_tuner_keeps_the_fastest_schedule(dev):
     for (_, _, _, out), (ref, _) in zip(jobs, want):
         assert rel_err(out.cpu().numpy(), ref) < 1e-6
     with pytest.raises(Exception, match="schedule"):
-        batch.set_config(64)
+        batch.set_config(128)
 
 
 def test_config3_batch_of_64_uneven_sectors(dev):

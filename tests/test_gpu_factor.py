@@ -1,0 +1,114 @@
+"""Spin-factorized phase evaluation (Section 2.4: Eqs. svd_weights,
+precomp_alpha, precomp_beta, svd_sreverse_sum, dot_product; Algorithm
+grouped_hvec) against the oracle's plain scatter and against the
+unfactored evaluation of the same kernel.
+
+The factored path changes only the order and grouping of floating-point
+operations (each phase sum becomes a rank-R dot product of folded alpha
+factors and precomputed beta factors), so it must meet the same bars as the
+plain path: 1e-12 relative 2-norm in float64, 1e-6 for complex64 storage on
+the same FP32-rounded input, and energies to float64 accumulation error.
+The ranks the plan finds pin the structure of Table svd_rank_dist: the
+diagonal group has rank n_o + 2, same-spin hopping groups rank 2 and
+double-excitation groups rank 1."""
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import apply as oapply
+from oracle import jw as ojw
+from oracle import space as ospace
+from tests.conftest import rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+def _api():
+    from paper_2606_28952_amd import api
+
+    return api
+
+
+CASES = [(6, 3, 3, 1001), (8, 3, 5, 41), (7, 2, 4, 42), (10, 5, 5, 43), (9, 5, 4, 44)]
+
+
+@pytest.mark.parametrize("n_o,na,nb,seed", CASES)
+def test_factored_matches_oracle_and_plain(dev, n_o, na, nb, seed):
+    api = _api()
+    h1, h2 = synth.molecular_spin_integrals(n_o, seed)
+    G = api.jw_transform(torch.from_numpy(h1).to(dev), torch.from_numpy(h2).to(dev)).group()
+    sp = api.Space.sector(n_o, na, nb)
+    psi_np = synth.random_state(sp.dim, seed + 7)
+    ref = oapply.apply_scatter(ojw.jw_sum(h1, h2), ospace.SectorSpace(n_o, na, nb), psi_np)
+    psi = torch.from_numpy(psi_np).to(dev)
+    plain = api.apply_pauli_sum(G, sp, psi)
+    assert G.factor_info()["present"] == 0
+    G.factor(sp)
+    info = G.factor_info()
+    assert info["present"] == 1 and info["n_beta"] == nb
+    assert info["alpha_lists"] == 1 and info["n_alpha"] == na and info["alpha_images"] == 1
+    assert info["zero_max_rank"] == n_o + 2, info
+    # every non-simple class: X_alpha = 0 (diagonal, rank n_o + 2) and the
+    # C(n_o, 2) same-spin alpha hops (rank 2)
+    assert info["zero_groups"] == 1 + n_o * (n_o - 1) // 2, info
+    assert info["pair_groups"] == n_o * (n_o - 1) // 2 and info["pair_rank"] == 2, info
+    assert info["quad_groups"] == n_o * (n_o - 1) * (n_o - 2) * (n_o - 3) // 24 and info["quad_rank"] == 1, info
+    # each part alone (mode 1: X_beta = 0 groups; 2: the X_alpha = 0 class's
+    # move tables; 4: the simple classes' alpha lists), then all
+    errs = {}
+    for mode in (1, 2, 4, 7):
+        G.set_factored(mode)
+        errs[mode] = rel_err(api.apply_pauli_sum(G, sp, psi).cpu().numpy(), ref)
+    assert max(errs.values()) < 1e-12, errs
+    fact = api.apply_pauli_sum(G, sp, psi)
+    out = fact.cpu().numpy()
+    assert rel_err(out, plain.cpu().numpy()) < 1e-12
+    # fused energy on the factored path
+    e = api.expval(G, sp, psi).cpu().numpy()
+    e_ref = np.vdot(psi_np, ref)
+    assert abs(e[0] - e_ref.real) < 1e-12 * max(1.0, abs(e_ref))
+    # complex64 storage against the oracle on the same FP32-rounded input
+    psi32_np = psi_np.astype(np.complex64)
+    ref32 = oapply.apply_scatter(ojw.jw_sum(h1, h2), ospace.SectorSpace(n_o, na, nb), psi32_np.astype(np.complex128))
+    out32 = api.apply_pauli_sum(G, sp, torch.from_numpy(psi32_np).to(dev)).cpu().numpy()
+    assert rel_err(out32, ref32) < 1e-6
+    # switched off: the unfactored evaluation, bit for bit as before
+    G.set_factored(0)
+    again = api.apply_pauli_sum(G, sp, psi)
+    assert torch.equal(torch.view_as_real(again), torch.view_as_real(plain))
+    G.set_factored(7)
+    assert torch.equal(torch.view_as_real(api.apply_pauli_sum(G, sp, psi)), torch.view_as_real(fact))
+
+
+def test_factor_tables_follow_their_beta_sector(dev):
+    # tables built for N_beta = 3 serve (2, 3) but not (3, 2), which falls
+    # back to the unfactored evaluation; both stay correct
+    api = _api()
+    n_o, seed = 6, 51
+    h1, h2 = synth.molecular_spin_integrals(n_o, seed)
+    G = api.jw_transform(torch.from_numpy(h1).to(dev), torch.from_numpy(h2).to(dev)).group()
+    op = ojw.jw_sum(h1, h2)
+    G.factor(api.Space.sector(n_o, 3, 3))
+    for na, nb in [(2, 3), (3, 2), (4, 3)]:
+        sp = api.Space.sector(n_o, na, nb)
+        psi_np = synth.random_state(sp.dim, 60 + na + nb)
+        ref = oapply.apply_scatter(op, ospace.SectorSpace(n_o, na, nb), psi_np)
+        out = api.apply_pauli_sum(G, sp, torch.from_numpy(psi_np).to(dev)).cpu().numpy()
+        assert rel_err(out, ref) < 1e-12, (na, nb)
+
+
+def test_factor_refuses_complex_and_full_space(dev):
+    api = _api()
+    from paper_2606_28952_amd._abi import PbsError
+
+    h1, h2 = synth.molecular_spin_integrals(4, 3)
+    G = api.jw_transform(torch.from_numpy(h1).to(dev), torch.from_numpy(h2).to(dev)).group()
+    with pytest.raises(PbsError, match="spin-sector"):
+        G.factor(api.Space.full(8))
+    x = np.array([0b11], np.uint64)
+    z = np.array([0b01], np.uint64)
+    Gc = api.PauliSum.create(8, x, z, np.array([0.5 + 0.25j])).canonicalize().group()
+    with pytest.raises(PbsError, match="real"):
+        Gc.factor(api.Space.sector(4, 2, 2))
