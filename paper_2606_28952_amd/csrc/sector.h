@@ -889,13 +889,11 @@ __device__ __forceinline__ void sector_body(const SectorArgs& P, const T* __rest
       uint32_t n_moves = __builtin_amdgcn_readfirstlane(P.n_moves);
       const uint32_t n_img = P.n_img, n_pairs = P.n_pairs;
       const double* s_Af = reinterpret_cast<const double*>(smem + P.off_a);
-      const bool stage = P.row_lds != 0;
-      const bool stager = stage && threadIdx.x < kSB / 2;
-      const uint32_t lane0 = stage ? threadIdx.x % (kSB / 2) : threadIdx.x;
-      const uint32_t stride = stage ? kSB / 2 : kSB;
-      // each copying lane holds its image element of the next class, loaded
-      // while the current class is evaluated
-      double imv = (b1 > b0 && !stager && lane0 < n_img) ? P.pimg[static_cast<uint64_t>(b0) * n_img + lane0] : 0.0;
+      // every lane stages part of the row; lane j < n_img also holds image
+      // element j of the next class, loaded while the current class is
+      // evaluated
+      const uint32_t lane0 = threadIdx.x;
+      double imv = (b1 > b0 && lane0 < n_img) ? P.pimg[static_cast<uint64_t>(b0) * n_img + lane0] : 0.0;
       for (uint32_t k = b0; k < b1; ++k) {
         const uint32_t src = ldc(P.plist_src + k), cid = ldc(P.plist_cls + k);
         const uint32_t* cf = reinterpret_cast<const uint32_t*>(P.cls_f + cid);
@@ -905,11 +903,10 @@ __device__ __forceinline__ void sector_body(const SectorArgs& P, const T* __rest
         const double zv1 = fz_r > 1 ? P.fz[fz_off + db + colc] : 0.0;
         const T* rowg = psi + static_cast<uint64_t>(src) * db;
         __syncthreads();
-        if (stager) {
-          stage_row<T>(s_row, rowg, db, lane0, stride);
-        } else {
+        stage_row<T>(s_row, rowg, db, lane0, kSB);
+        {
           const double* im = P.pimg + static_cast<uint64_t>(k) * n_img;
-          for (uint32_t j = lane0; j < n_img; j += stride) {
+          for (uint32_t j = lane0; j < n_img; j += kSB) {
             const uint32_t at = j <= n_pairs ? kPuOff + 8u * j : P.off_a + 8u * (j - n_pairs - 1u);
             *reinterpret_cast<double*>(smem + at) = j == lane0 ? imv : im[j];
           }
