@@ -18,7 +18,6 @@
 // exact ranks on these matrices with the same rounding-level residual.
 #include <algorithm>
 #include <cmath>
-#include <map>
 #include <vector>
 
 #include "handles.h"
@@ -131,55 +130,81 @@ __global__ void k_fact_quads(uint64_t db, uint32_t n_orb, uint32_t n_beta, uint3
   }
 }
 
-// Alpha lists (Eq. precomp_alpha for the simple classes): one thread per
-// alpha row walks the simple classes in class order; pass 0 counts the
-// classes whose source row lies in the sector, pass 1 writes their source
-// rank and folded coefficient sum_t c_t (-1)^popcount(za_t & t_alpha).
-__global__ void k_alpha_list(uint32_t pass, uint64_t da, uint32_t n_alpha, const uint32_t* str_a,
-                             const uint32_t* simple, uint32_t n_simple, const ClassMeta* meta, const uint32_t* u_t0,
-                             const uint32_t* pt_za, const double* pt_c, const uint32_t* off, uint32_t* count,
-                             uint32_t* src, double* coef) {
-  for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < da;
-       i += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+// Position of this thread's flag among the workgroup's set flags (in thread
+// order) and their total; 256 threads.
+__device__ inline void block_compact(bool flag, uint32_t* s_cnt, uint32_t& pos, uint32_t& total) {
+  const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+  const uint64_t bal = __ballot(flag);
+  if (lane == 0) s_cnt[wave] = static_cast<uint32_t>(__popcll(bal));
+  __syncthreads();
+  pos = static_cast<uint32_t>(__popcll(bal & ((1ull << lane) - 1ull)));
+  total = 0;
+  for (uint32_t w = 0; w < 4; ++w) {
+    pos += w < wave ? s_cnt[w] : 0u;
+    total += s_cnt[w];
+  }
+  __syncthreads();
+}
+
+// Alpha lists (Eq. precomp_alpha for the simple classes): one workgroup per
+// alpha row, its threads over the simple classes in class order; pass 0
+// counts the classes whose source row lies in the sector, pass 1 writes
+// their source rank and folded coefficient sum_t c_t (-1)^popcount(za_t & t_alpha)
+// in class order.
+__global__ __launch_bounds__(256) void k_alpha_list(uint32_t pass, uint64_t da, uint32_t n_alpha,
+                                                    const uint32_t* str_a, const uint32_t* simple, uint32_t n_simple,
+                                                    const ClassMeta* meta, const uint32_t* u_t0,
+                                                    const uint32_t* pt_za, const double* pt_c, const uint32_t* off,
+                                                    uint32_t* count, uint32_t* src, double* coef) {
+  __shared__ uint32_t s_cnt[4];
+  for (uint64_t i = blockIdx.x; i < da; i += gridDim.x) {
     const uint32_t ta = str_a[i];
-    uint32_t n = 0, o = pass ? off[i] : 0u;
-    for (uint32_t k = 0; k < n_simple; ++k) {
-      const ClassMeta& m = meta[simple[k]];
-      const uint32_t sa = ta ^ m.xa;
-      if (static_cast<uint32_t>(__popc(sa)) != n_alpha) continue;
-      if (pass) {
+    uint32_t n = pass ? off[i] : 0u;
+    for (uint32_t k0 = 0; k0 < n_simple; k0 += 256) {
+      const uint32_t k = k0 + threadIdx.x;
+      const ClassMeta* m = k < n_simple ? meta + simple[k] : nullptr;
+      const uint32_t sa = m ? ta ^ m->xa : 0u;
+      const bool v = m && static_cast<uint32_t>(__popc(sa)) == n_alpha;
+      uint32_t pos, total;
+      block_compact(v, s_cnt, pos, total);
+      if (pass && v) {
         double f = 0.0;
-        for (uint32_t t = u_t0[m.ua]; t < u_t0[m.u_end]; ++t)
+        for (uint32_t t = u_t0[m->ua]; t < u_t0[m->u_end]; ++t)
           f += (__popc(pt_za[t] & ta) & 1u) ? -pt_c[2 * t] : pt_c[2 * t];
-        src[o + n] = colex_rank(sa);
-        coef[o + n] = f;
+        src[n + pos] = colex_rank(sa);
+        coef[n + pos] = f;
       }
-      ++n;
+      n += total;
     }
-    if (!pass) count[i] = n;
+    if (!pass && threadIdx.x == 0) count[i] = n;
   }
 }
 
-// Image-class lists: pass 0 counts per alpha row the image classes whose
-// source row lies in the sector, pass 1 writes (source rank, class, row).
-__global__ void k_pair_list(uint32_t pass, uint64_t da, uint32_t n_alpha, const uint32_t* str_a, const uint32_t* cls,
-                            uint32_t n_cls, const ClassMeta* meta, const uint32_t* off, uint32_t* count,
-                            uint32_t* src, uint32_t* ent_cls, uint32_t* ent_row) {
-  for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < da;
-       i += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+// Image-class lists: one workgroup per alpha row; pass 0 counts the image
+// classes whose source row lies in the sector, pass 1 writes (source rank,
+// class, row) in class order.
+__global__ __launch_bounds__(256) void k_pair_list(uint32_t pass, uint64_t da, uint32_t n_alpha,
+                                                   const uint32_t* str_a, const uint32_t* cls, uint32_t n_cls,
+                                                   const ClassMeta* meta, const uint32_t* off, uint32_t* count,
+                                                   uint32_t* src, uint32_t* ent_cls, uint32_t* ent_row) {
+  __shared__ uint32_t s_cnt[4];
+  for (uint64_t i = blockIdx.x; i < da; i += gridDim.x) {
     const uint32_t ta = str_a[i];
-    uint32_t n = 0, o = pass ? off[i] : 0u;
-    for (uint32_t k = 0; k < n_cls; ++k) {
-      const uint32_t sa = ta ^ meta[cls[k]].xa;
-      if (static_cast<uint32_t>(__popc(sa)) != n_alpha) continue;
-      if (pass) {
-        src[o + n] = colex_rank(sa);
-        ent_cls[o + n] = cls[k];
-        ent_row[o + n] = static_cast<uint32_t>(i);
+    uint32_t n = pass ? off[i] : 0u;
+    for (uint32_t k0 = 0; k0 < n_cls; k0 += 256) {
+      const uint32_t k = k0 + threadIdx.x;
+      const uint32_t sa = k < n_cls ? ta ^ meta[cls[k]].xa : 0u;
+      const bool v = k < n_cls && static_cast<uint32_t>(__popc(sa)) == n_alpha;
+      uint32_t pos, total;
+      block_compact(v, s_cnt, pos, total);
+      if (pass && v) {
+        src[n + pos] = colex_rank(sa);
+        ent_cls[n + pos] = cls[k];
+        ent_row[n + pos] = static_cast<uint32_t>(i);
       }
-      ++n;
+      n += total;
     }
-    if (!pass) count[i] = n;
+    if (!pass && threadIdx.x == 0) count[i] = n;
   }
 }
 
@@ -286,20 +311,19 @@ GroupFactors factor_group(const HostTables& T, uint32_t g) {
   GroupFactors F;
   const uint32_t u0 = T.pg_u0[g], u1 = T.pg_u0[g + 1];
   F.n_uniques = u1 - u0;
-  std::map<uint32_t, uint32_t> rows;
-  for (uint32_t t = T.u_t0[u0]; t < T.u_t0[u1]; ++t) rows.emplace(T.pt_za[t], 0u);
-  uint32_t i = 0;
-  std::vector<uint32_t> za(rows.size());
-  for (auto& kv : rows) {
-    kv.second = i;
-    za[i++] = kv.first;
-  }
-  const uint32_t nr = static_cast<uint32_t>(rows.size()), nc = u1 - u0;
+  // rows: the distinct alpha Z-masks, ascending
+  std::vector<uint32_t> za(T.pt_za.begin() + T.u_t0[u0], T.pt_za.begin() + T.u_t0[u1]);
+  std::sort(za.begin(), za.end());
+  za.erase(std::unique(za.begin(), za.end()), za.end());
+  auto row_of = [&](uint32_t z) {
+    return static_cast<uint32_t>(std::lower_bound(za.begin(), za.end(), z) - za.begin());
+  };
+  const uint32_t nr = static_cast<uint32_t>(za.size()), nc = u1 - u0;
   std::vector<double> M(static_cast<size_t>(nr) * nc, 0.0);
   for (uint32_t u = u0; u < u1; ++u)
     // terms whose beta Z-masks differ by X_beta share one unique in sector
     // form and may share an alpha Z-mask too: their coefficients add
-    for (uint32_t t = T.u_t0[u]; t < T.u_t0[u + 1]; ++t) M[rows[T.pt_za[t]] * nc + (u - u0)] += T.pt_c[t];
+    for (uint32_t t = T.u_t0[u]; t < T.u_t0[u + 1]; ++t) M[row_of(T.pt_za[t]) * nc + (u - u0)] += T.pt_c[t];
   std::vector<double> Q;
   F.rank = factor_rows(M, nr, nc, 1e-14, Q);
   F.a.resize(F.rank);
@@ -523,7 +547,7 @@ void build_plan(pbs_grouped& h, const pbs_space& sp, hipStream_t s) {
     if (plain && !simple.empty() && sp.n_orb <= 32) {
       DevBuf<uint32_t> d_simple, cnt(da, s);
       upload(d_simple, simple);
-      const unsigned grid = grid_for(da, 256, 65536);
+      const unsigned grid = static_cast<unsigned>(std::min<uint64_t>(da, 65536));
       hipLaunchKernelGGL(k_alpha_list, dim3(grid), dim3(256), 0, s, 0u, da, sp.n_alpha, sp.str_alpha.get(),
                          d_simple.get(), static_cast<uint32_t>(simple.size()), h.cls_meta.get(), h.u_t0.get(),
                          h.pt_za.get(), h.pt_c.get(), nullptr, cnt.get(), nullptr, nullptr);
@@ -560,7 +584,7 @@ void build_plan(pbs_grouped& h, const pbs_space& sp, hipStream_t s) {
     if (!icls.empty()) {
       DevBuf<uint32_t> d_cls, cnt(da, s);
       upload(d_cls, icls);
-      const unsigned grid = grid_for(da, 256, 65536);
+      const unsigned grid = static_cast<unsigned>(std::min<uint64_t>(da, 65536));
       hipLaunchKernelGGL(k_pair_list, dim3(grid), dim3(256), 0, s, 0u, da, sp.n_alpha, sp.str_alpha.get(), d_cls.get(),
                          static_cast<uint32_t>(icls.size()), h.cls_meta.get(), nullptr, cnt.get(), nullptr, nullptr,
                          nullptr);
