@@ -312,8 +312,37 @@ void validate(const pbs_grouped* h, const pbs_space* sp, pbs_dtype dt) {
   }
 }
 
+// Layout of the rows kernel when it applies (see k_apply_rows): factored
+// alpha lists, rows not staged, every non-simple class in LDS.
+bool plan_rows(const pbs_grouped& h, const SectorArgs& a, bool r16, RowsLayout* Lr, size_t* lds) {
+  const FactorPlan* F = h.fplan.get();
+  if (!r16 || a.row_lds || a.alist_off == nullptr || F == nullptr || a.ns_list != h.ns_list.get()) return false;
+  if (F->ns_uniques >= 65536u || F->ns_uniques + F->ns_groups == 0) return false;
+  RowsLayout L{};
+  uint32_t off = kMiscBytes;
+  L.off_rank = off;
+  off += align16(kRank16Lds * 2u);
+  L.off_lsrc = off;
+  off += align16(F->alist_max * 4u);
+  L.off_lc = off;
+  off += align16(F->alist_max * 8u);
+  L.off_cls = off;
+  off += align16(a.n_ns * 16u);
+  L.off_grp = off;
+  off += align16(F->ns_groups * 8u);
+  L.off_f = off;
+  off += align16(F->ns_uniques * 8u);
+  L.off_fz = off;
+  off += align16(F->ns_uniques * 4u);
+  if (off > 48u * 1024u) return false;
+  *Lr = L;
+  *lds = off;
+  return true;
+}
+
 template <class T, bool EXPVAL>
-void launch(const pbs_grouped& h, const pbs_space& sp, const void* psi, void* out, double* partial, hipStream_t s) {
+uint64_t launch(const pbs_grouped& h, const pbs_space& sp, const void* psi, void* out, double* partial,
+                hipStream_t s) {
   const T* p = static_cast<const T*>(psi);
   T* o = static_cast<T*>(out);
   if (!sp.sector) {
@@ -326,13 +355,25 @@ void launch(const pbs_grouped& h, const pbs_space& sp, const void* psi, void* ou
     bool r16 = false;
     const Launch L = plan_sector(h, sp, sizeof(T), true, h.real_coef, &a, &r16);
     const pbs_dtype dt = sizeof(T) == 16 ? PBS_C128 : PBS_C64;
+    RowsLayout Lr;
+    size_t lds_rows = 0;
+    if (h.real_coef && plan_rows(h, a, r16, &Lr, &lds_rows)) {
+      // one workgroup per alpha row, sweeping all of its columns
+      hipLaunchKernelGGL((k_apply_rows<T, EXPVAL>), dim3(static_cast<unsigned>(sp.dim_alpha)), dim3(kSB), lds_rows, s,
+                         a, Lr, p, o, partial);
+      PBS_HIP(hipGetLastError());
+      return sp.dim_alpha;
+    }
     void* kern = sector_kernel(dt, EXPVAL, false, r16, a.row_lds != 0, h.real_coef);
     if (L.lds > 64 * 1024)
       PBS_HIP(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(L.lds)));
     void* args[] = {&a, &p, &o, &partial};
     PBS_HIP(hipLaunchKernel(kern, L.grid, L.block, args, L.lds, s));
+    PBS_HIP(hipGetLastError());
+    return L.parts;
   }
   PBS_HIP(hipGetLastError());
+  return partial_count(sp);
 }
 
 }  // namespace
@@ -390,11 +431,9 @@ pbs_status pbs_expval(const pbs_grouped* h, const pbs_space* sp, pbs_dtype dt, c
                 "workspace of " + std::to_string(work_bytes) + " bytes, need " + std::to_string(need));
     hipStream_t s = as_stream(stream);
     double* partial = static_cast<double*>(work);
-    if (dt == PBS_C128)
-      launch<double2, true>(*h, *sp, psi, out, partial, s);
-    else
-      launch<float2, true>(*h, *sp, psi, out, partial, s);
-    hipLaunchKernelGGL(k_expval_finish, dim3(1), dim3(kBlock), 0, s, partial, partial_count(*sp), result);
+    const uint64_t parts = dt == PBS_C128 ? launch<double2, true>(*h, *sp, psi, out, partial, s)
+                                          : launch<float2, true>(*h, *sp, psi, out, partial, s);
+    hipLaunchKernelGGL(k_expval_finish, dim3(1), dim3(kBlock), 0, s, partial, parts, result);
     PBS_HIP(hipGetLastError());
   });
 }
@@ -415,11 +454,9 @@ pbs_status pbs_expval_noalloc(const pbs_grouped* h, const pbs_space* sp, pbs_dty
                     std::to_string(static_cast<uint64_t>(PBS_EXPVAL_NOALLOC_MAX_BYTES)));
     double* partial = noalloc_scratch();
     hipStream_t s = as_stream(stream);
-    if (dt == PBS_C128)
-      launch<double2, true>(*h, *sp, psi, out, partial, s);
-    else
-      launch<float2, true>(*h, *sp, psi, out, partial, s);
-    hipLaunchKernelGGL(k_expval_finish, dim3(1), dim3(kBlock), 0, s, partial, partial_count(*sp), result);
+    const uint64_t parts = dt == PBS_C128 ? launch<double2, true>(*h, *sp, psi, out, partial, s)
+                                          : launch<float2, true>(*h, *sp, psi, out, partial, s);
+    hipLaunchKernelGGL(k_expval_finish, dim3(1), dim3(kBlock), 0, s, partial, parts, result);
     PBS_HIP(hipGetLastError());
   });
 }

@@ -554,7 +554,10 @@ void build_plan(pbs_grouped& h, const pbs_space& sp, hipStream_t s) {
       PBS_HIP(hipGetLastError());
       PBS_HIP(hipStreamSynchronize(s));
       std::vector<uint32_t> c = download(cnt, da), off(da + 1, 0u);
-      for (uint64_t i = 0; i < da; ++i) off[i + 1] = off[i] + c[i];
+      for (uint64_t i = 0; i < da; ++i) {
+        off[i + 1] = off[i] + c[i];
+        F.alist_max = std::max(F.alist_max, c[i]);
+      }
       upload(F.alist_off, off);
       F.alist_src.alloc(off[da]);
       F.alist_c.alloc(off[da]);
@@ -617,6 +620,10 @@ void build_plan(pbs_grouped& h, const pbs_space& sp, hipStream_t s) {
   }
   {
     std::vector<uint32_t> flag = F.plist ? download(F.pimg_flag, h.n_class) : std::vector<uint32_t>(h.n_class, 0u);
+    for (uint32_t c : ns) {
+      F.ns_uniques += meta[c].u_end - meta[c].ua;
+      F.ns_groups += meta[c].g1 - meta[c].g0;
+    }
     F.ns_sizes.assign(3, 0u);
     for (int k = 0; k < 3; ++k) {
       std::vector<uint32_t> l;

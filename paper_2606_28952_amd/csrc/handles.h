@@ -132,6 +132,9 @@ struct FactorPlan {
   // its tables exist), without the image classes, and without both
   std::vector<uint32_t> ns_sizes;  // [3]
   DevBuf<uint32_t> ns_rest[3];
+  // sizes for the rows kernel: longest alpha list, and the uniques and
+  // groups of all non-simple classes
+  uint32_t alist_max = 0, ns_uniques = 0, ns_groups = 0;
 };
 constexpr uint32_t kMaxR1 = 32;       // largest factored rank of an X_beta = 0 group
 constexpr uint32_t kFactZeroSlots = 4;  // zero factors at the start of the class-0 fold

@@ -1164,6 +1164,154 @@ __device__ inline void row_chunk_of(uint32_t b, uint32_t rows, uint32_t chunks, 
   }
 }
 
+// Rows kernel: one workgroup per alpha row and all of its beta columns, for
+// operators whose simple classes come through alpha lists and whose other
+// classes' uniques and group records all fit in LDS (few groups, rows too
+// long to stage: the 32-qubit Hubbard sector).  Everything the row needs --
+// rank tables, the row's alpha list, every valid class's source row, folded
+// uniques and group records -- is loaded once; the row's columns are then
+// swept chunk by chunk with no barrier, so waves run independently.
+// LDS: [0, 256) scratch, then rank tables, the list (source ranks, then
+// coefficients), valid classes (source row rank, first and end group
+// record), group records (X_beta, first unique | count << 16), folded
+// uniques and their beta Z-masks; offsets in RowsLayout.
+struct RowsLayout {
+  uint32_t off_rank, off_lsrc, off_lc, off_cls, off_grp, off_f, off_fz;
+  uint32_t max_list, max_cls, max_grp, max_u;
+};
+
+template <class T, bool EXPVAL>
+__global__ __launch_bounds__(kSB) void k_apply_rows(SectorArgs P, RowsLayout Lr, const T* __restrict__ psi,
+                                                    T* __restrict__ out, double* __restrict__ partial) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const uint32_t ia = blockIdx.x;
+  const uint64_t db = P.dim_beta;
+  uint16_t* s_rank = reinterpret_cast<uint16_t*>(smem + Lr.off_rank);
+  uint32_t* s_lsrc = reinterpret_cast<uint32_t*>(smem + Lr.off_lsrc);
+  double* s_lc = reinterpret_cast<double*>(smem + Lr.off_lc);
+  uint4* s_cls = reinterpret_cast<uint4*>(smem + Lr.off_cls);
+  uint2* s_grp = reinterpret_cast<uint2*>(smem + Lr.off_grp);
+  double* s_F = reinterpret_cast<double*>(smem + Lr.off_f);
+  uint32_t* s_Fz = reinterpret_cast<uint32_t*>(smem + Lr.off_fz);
+  uint32_t* s_cnt = reinterpret_cast<uint32_t*>(smem);  // [0]: valid classes, [1]: groups, [2]: uniques
+  {  // rank tables (n_orb <= 16), as in the sector kernel
+    constexpr uint32_t kWords = kRank16Lds / 2u;
+    const uint32_t* r0 = reinterpret_cast<const uint32_t*>(P.rank16);
+    const uint32_t* r1 = reinterpret_cast<const uint32_t*>(P.rank16 + (P.n_orb + 1) * 256u);
+    uint32_t* s_rank32 = reinterpret_cast<uint32_t*>(s_rank);
+    for (uint32_t w = threadIdx.x; w < kWords; w += kSB)
+      s_rank32[w] = w < 128u ? r0[w] : (P.n_chunks > 1 ? r1[w - 128u] : 0u);
+  }
+  const uint32_t ta = P.str_a[ia];
+  const uint32_t a0 = ldc(P.alist_off + ia), a1 = ldc(P.alist_off + ia + 1);
+  for (uint32_t j = threadIdx.x; j < a1 - a0; j += kSB) {
+    s_lsrc[j] = P.alist_src[a0 + j];
+    s_lc[j] = P.alist_c[a0 + j];
+  }
+  // valid classes and their group records (thread 0 walks the classes; few)
+  if (threadIdx.x == 0) {
+    uint32_t nc = 0, ng = 0, nu = 0;
+    for (uint32_t ic = 0; ic < P.n_ns; ++ic) {
+      const ClassMeta* m = P.meta + P.ns_list[ic];
+      const uint32_t sa = ta ^ m->xa;
+      if (static_cast<uint32_t>(__popc(sa)) != P.n_alpha) continue;
+      uint32_t r = 0, below = 0;  // rank of the source alpha string
+      for (uint32_t c = 0; c < P.n_chunks; ++c) {
+        const uint32_t byte = (sa >> (8 * c)) & 255u;
+        r += P.rank16[(c * (P.n_orb + 1) + below) * 256 + byte];
+        below += __popc(byte);
+      }
+      s_cls[nc++] = make_uint4(r, ng, ng + (m->g1 - m->g0), nu);
+      for (uint32_t g = m->g0; g < m->g1; ++g) {
+        const uint32_t u0 = P.pg_u0[g], u1 = P.pg_u0[g + 1];
+        s_grp[ng++] = make_uint2(P.pg_xb[g], (nu + (u0 - m->ua)) | ((u1 - u0) << 16));
+      }
+      nu += m->u_end - m->ua;
+    }
+    s_cnt[0] = nc;
+    s_cnt[1] = ng;
+    s_cnt[2] = nu;
+  }
+  __syncthreads();
+  const uint32_t n_cls = s_cnt[0];
+  {  // fold every valid class's uniques at the class's offset
+    uint32_t nu = 0;
+    for (uint32_t ic = 0; ic < P.n_ns; ++ic) {
+      const ClassMeta M = ld_meta(P.meta + P.ns_list[ic]);
+      if (static_cast<uint32_t>(__popc(ta ^ M.xa)) != P.n_alpha) continue;
+      fold_uniques<true>(P, M.ua, M.u_end, ta, s_F + nu, s_Fz + nu);
+      nu += M.u_end - M.ua;
+    }
+  }
+  __syncthreads();
+
+  const uint32_t chunks = static_cast<uint32_t>((db + kSB - 1) / kSB);
+  const uint32_t n_list = a1 - a0;
+  double e_re = 0.0, e_im = 0.0, nrm = 0.0;
+  for (uint32_t ch = 0; ch < chunks; ++ch) {
+    const uint32_t col = ch * kSB + threadIdx.x;
+    const bool live = col < db;
+    const uint32_t colc = live ? col : 0u;
+    const uint32_t tb = P.str_b[colc];
+    double ar4[4] = {0.0, 0.0, 0.0, 0.0}, ai4[4] = {0.0, 0.0, 0.0, 0.0};
+    const T* psi_col = psi + colc;
+    // simple classes: the row's list, eight gathers in flight
+    for (uint32_t e0 = 0; e0 < n_list; e0 += 8) {
+      double c[8];
+      T a[8];
+#pragma unroll
+      for (uint32_t i = 0; i < 8; ++i) {
+        const uint32_t m = min(e0 + i, n_list - 1u);
+        c[i] = e0 + i < n_list ? s_lc[m] : 0.0;
+        a[i] = psi_col[static_cast<uint64_t>(s_lsrc[m]) * db];
+      }
+#pragma unroll
+      for (uint32_t i = 0; i < 8; ++i)
+        Coef<true>::mac(c[i], static_cast<double>(a[i].x), static_cast<double>(a[i].y), ar4[i & 3], ai4[i & 3]);
+    }
+    // other classes: every group, four gathers in flight
+    for (uint32_t c = 0; c < n_cls; ++c) {
+      const uint4 C = s_cls[c];
+      const T* rowp = psi + static_cast<uint64_t>(C.x) * db;
+      for (uint32_t g0 = C.y; g0 < C.z; g0 += 4) {
+        uint32_t jb[4];
+        double f[4], a_r[4], a_i[4];
+#pragma unroll
+        for (uint32_t i = 0; i < 4; ++i) {
+          const uint32_t g = min(g0 + i, C.z - 1u);
+          const uint2 R = s_grp[g];
+          const uint32_t xb = R.x;
+          const bool valid = g0 + i < C.z && 2u * __popc(tb & xb) == static_cast<uint32_t>(__popc(xb));
+          jb[i] = valid ? rank_of<true>(tb ^ xb, P, s_rank) : 0u;
+          double h = 0.0;
+          phase_sum_lds<true>(s_F, s_Fz, R.y & 0xffffu, R.y >> 16, tb, h);
+          f[i] = valid ? h : 0.0;
+        }
+#pragma unroll
+        for (uint32_t i = 0; i < 4; ++i) ld_amp<T>(rowp, jb[i], a_r[i], a_i[i]);
+#pragma unroll
+        for (uint32_t i = 0; i < 4; ++i) Coef<true>::mac(f[i], a_r[i], a_i[i], ar4[i], ai4[i]);
+      }
+    }
+    const double acc_r = (ar4[0] + ar4[1]) + (ar4[2] + ar4[3]);
+    const double acc_i = (ai4[0] + ai4[1]) + (ai4[2] + ai4[3]);
+    if (live) {
+      const uint64_t t = static_cast<uint64_t>(ia) * db + col;
+      if (EXPVAL) {
+        double pr, pi;
+        Amp<T>::load(psi, t, pr, pi);
+        e_re = fma(pr, acc_r, fma(pi, acc_i, e_re));
+        e_im = fma(pr, acc_i, fma(-pi, acc_r, e_im));
+        nrm = fma(pr, pr, fma(pi, pi, nrm));
+        if (out) Amp<T>::store(out, t, acc_r, acc_i);
+      } else {
+        Amp<T>::store(out, t, acc_r, acc_i);
+      }
+    }
+  }
+  if (EXPVAL) block_reduce3_store<kSB>(e_re, e_im, nrm, partial + 3ull * blockIdx.x, reinterpret_cast<double(*)[kSB / 64]>(smem + 64));
+}
+
 // One-dimensional grid of dim_alpha * chunks workgroups.
 template <class T, bool EXPVAL, bool R16, bool ROWLDS, bool REALC>
 __global__ __launch_bounds__(kSB) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_apply_sector(

@@ -112,3 +112,29 @@ def test_factor_refuses_complex_and_full_space(dev):
     Gc = api.PauliSum.create(8, x, z, np.array([0.5 + 0.25j])).canonicalize().group()
     with pytest.raises(PbsError, match="real"):
         Gc.factor(api.Space.sector(4, 2, 2))
+
+
+def test_rows_kernel_hubbard_long_rows(dev):
+    """Rows too long to stage (complex128, 6,435 beta strings) with alpha
+    lists: the barrier-free rows kernel, against the oracle and against the
+    unfactored evaluation, apply and fused energy."""
+    api = _api()
+    h1, h2 = synth.hubbard_spin_integrals(3, 5)
+    n_o, na, nb = 15, 2, 7
+    G = api.jw_transform(torch.from_numpy(h1).to(dev), torch.from_numpy(h2).to(dev)).group()
+    sp = api.Space.sector(n_o, na, nb)
+    psi_np = synth.random_state(sp.dim, 71)
+    ref = oapply.apply_scatter(ojw.jw_sum(h1, h2), ospace.SectorSpace(n_o, na, nb), psi_np)
+    psi = torch.from_numpy(psi_np).to(dev)
+    plain = api.apply_pauli_sum(G, sp, psi).cpu().numpy()
+    G.factor(sp)
+    assert G.factor_info()["alpha_lists"] == 1
+    out = torch.empty_like(psi)
+    e = api.expval(G, sp, psi, out=out).cpu().numpy()
+    got = out.cpu().numpy()
+    assert rel_err(got, ref) < 1e-12
+    assert rel_err(got, plain) < 1e-12
+    e_ref = np.vdot(psi_np, ref)
+    assert abs(e[0] - e_ref.real) < 1e-12 * max(1.0, abs(e_ref))
+    assert abs(e[2] - 1.0) < 1e-13
+    assert torch.equal(torch.view_as_real(api.apply_pauli_sum(G, sp, psi)), torch.view_as_real(out))

@@ -49,12 +49,17 @@ def _pick_rows(dim_alpha, k, seed):
     return np.sort(np.concatenate([[0, dim_alpha - 1], inner]))
 
 
-@pytest.fixture(scope="module")
-def mol28(dev):
+# each full-size workload runs with the unfactored evaluation and with the
+# spin-factorized tables (factor tables, alpha lists, images; for the
+# Hubbard sector the rows kernel), the configuration the benchmark times
+@pytest.fixture(scope="module", params=[False, True], ids=["plain", "factored"])
+def mol28(dev, request):
     api = _api()
     h1, h2 = synth.molecular_spin_integrals(14, seed=2001)
     G = api.jw_transform(torch.from_numpy(h1).to(dev), torch.from_numpy(h2).to(dev)).group()
     sp = api.Space.sector(14, 7, 7)
+    if request.param:
+        G.factor(sp)
     osp = ospace.SectorSpace(14, 7, 7)
     op = ojw.jw_sum(h1, h2)
     assert sp.dim == 11_778_624 and op.n_terms == 55_371
@@ -138,12 +143,14 @@ def test_28q_hermiticity_dense_states(dev, mol28):
     assert abs(lhs - rhs) < 1e-11 * max(1.0, abs(lhs))
 
 
-@pytest.fixture(scope="module")
-def hub32(dev):
+@pytest.fixture(scope="module", params=[False, True], ids=["plain", "factored"])
+def hub32(dev, request):
     api = _api()
     h1, h2 = synth.hubbard_spin_integrals(4, 4)
     G = api.jw_transform(torch.from_numpy(h1).to(dev), torch.from_numpy(h2).to(dev)).group()
     sp = api.Space.sector(16, 8, 8)
+    if request.param:
+        G.factor(sp)
     osp = ospace.SectorSpace(16, 8, 8)
     op = ojw.jw_sum(h1, h2)
     assert sp.dim == 165_636_900
