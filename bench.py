@@ -184,6 +184,8 @@ def bench_batched(args):
         H = api.jw_transform(torch.from_numpy(h1).to(dev), torch.from_numpy(h2).to(dev))
         G = H.group()
         sp = api.Space.sector(n_orb, na, nb)
+        if not args.no_factor:
+            G.factor(sp)  # spin-factorized tables for the job's own sector
         psi = torch.from_numpy(synth.random_state(sp.dim, ps)).to(dev)
         p32 = psi.to(torch.complex64)
         jobs32.append((G, sp, p32, torch.empty_like(p32)))
@@ -204,20 +206,31 @@ def bench_batched(args):
         return (time.perf_counter() - t0) / args.steps
 
     t_default = time_batch()
+    batch.set_config(128)  # persistent launch, default schedule otherwise
+    t_persistent = time_batch()
     tuned_config, tuned_ms = batch.tune(reps=3)
     t_batch = time_batch()
 
     def per_job():
         for G, sp, psi, out in jobs64:
             api.apply_pauli_sum(G, sp, psi, out=out)
-    for _ in range(args.warmup):
-        per_job()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        per_job()
-    torch.cuda.synchronize()
-    t_single = (time.perf_counter() - t0) / args.steps
+
+    def time_per_job():
+        for _ in range(args.warmup):
+            per_job()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            per_job()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / args.steps
+
+    t_single = time_per_job()
+    for G, _, _, _ in jobs64:
+        G.set_factored(0)
+    t_single_plain = time_per_job()
+    for G, _, _, _ in jobs64:
+        G.set_factored(0 if args.no_factor else 7)
     # accuracy of the batched complex64 results against FP64 on the same input
     worst = 0.0
     for (G, sp, p32, o32) in jobs32:
@@ -228,13 +241,15 @@ def bench_batched(args):
         "metric": "batched H|psi> amplitude*terms/s (64 jobs, complex64 storage, float64 accumulation)",
         "value": work / t_batch, "unit": "amplitude*terms/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": t_batch * 1e3, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "vs_baseline": None, "dtype": "complex64 storage, f64 accumulation", "data": "synthetic",
         "config": {"workload": "batched-64", "jobs": len(jobs32), "amplitude_terms": work,
-                   "dims": [j[1].dim for j in jobs32]},
-        "ms_default_schedule": t_default * 1e3, "tuned_schedule": tuned_config,
-        "tuner_ms_per_run": tuned_ms, "workgroups": batch.info()[2],
+                   "dims": [j[1].dim for j in jobs32], "factored": not args.no_factor},
+        "ms_default_schedule": t_default * 1e3, "ms_persistent_schedule": t_persistent * 1e3,
+        "tuned_schedule": tuned_config, "tuner_ms_per_run": tuned_ms, "work_items": batch.info()[2],
         "ms_per_job_fp64_launches": t_single * 1e3,
+        "ms_per_job_fp64_launches_unfactored": t_single_plain * 1e3,
         "speedup_batched_c64_vs_per_job_fp64": t_single / t_batch,
+        "speedup_batched_c64_vs_per_job_fp64_unfactored": t_single_plain / t_batch,
         "max_rel_err_c64_vs_fp64_same_input": worst,
     }
     print(json.dumps(line))

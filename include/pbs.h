@@ -309,6 +309,8 @@ pbs_status pbs_batch_run(const pbs_batch* b, double* energies, void* stream);
 #define PBS_BATCH_NO_DOUBLE_MOVES 4u   /* scan double-flip groups instead of enumerating double moves */
 #define PBS_BATCH_NO_SINGLE_MOVES 8u   /* scan pair groups instead of enumerating single moves */
 #define PBS_BATCH_NO_FACTORED 64u      /* ignore the operators' factor tables (pbs_grouped_factor) */
+#define PBS_BATCH_PERSISTENT 128u      /* persistent launch: as many workgroups as are resident at once,
+                                          each walking the (largest-first) work list with a fixed stride */
 /* workgroup -> (alpha row, beta chunk) order of every job (bits 4-5); the
  * default is the single launch's: rows fastest when rows are staged in LDS,
  * else a row's chunks kept together on one XCD (shared L2) */
@@ -317,13 +319,13 @@ pbs_status pbs_batch_run(const pbs_batch* b, double* energies, void* stream);
 #define PBS_BATCH_ORDER_ROW_FAST 32u   /* rows fastest */
 #define PBS_BATCH_ORDER_XCD_ROWS 48u   /* a row's chunks on one XCD */
 
-/* Rebuilds the batch's job table for schedule `config` (0..127).  Synchronizes. */
+/* Rebuilds the batch's job table for schedule `config` (0..255).  Synchronizes. */
 pbs_status pbs_batch_set_config(pbs_batch* b, uint32_t config);
 
 /* Autotuner: times schedules (a warm-up run, then `reps` runs, 1..100, with
  * HIP events on the stream; schedules that build the same job table are
  * timed once), greedily: the four workgroup orders with the default flags,
- * then the 32 flag combinations with the best order.  Keeps the fastest and
+ * then the 64 flag combinations with the best order.  Keeps the fastest and
  * returns it in *config and its time per run in *ms (either may be NULL).
  * Runs the batch, so the output buffers are overwritten.  Call it before
  * capturing pbs_batch_run in a graph: it rebuilds the job table.

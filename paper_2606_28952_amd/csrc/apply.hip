@@ -465,7 +465,8 @@ pbs_status pbs_expval_noalloc(const pbs_grouped* h, const pbs_space* sp, pbs_dty
 
 struct pbs_batch {
   uint32_t n_jobs = 0;
-  uint32_t total_blocks = 0;
+  uint32_t total_blocks = 0;  // work items (alpha row, column chunk) over all jobs
+  uint32_t grid = 0;          // workgroups launched (fewer than the items when persistent)
   pbs_dtype dt = PBS_C64;
   bool r16 = false, row_lds = false, realc = false;
   size_t lds = 0;
@@ -482,7 +483,7 @@ struct pbs_batch {
 namespace pbs {
 namespace {
 
-constexpr uint32_t kBatchConfigs = 128;  // five PBS_BATCH_* flags and the 2-bit workgroup order
+constexpr uint32_t kBatchConfigs = 256;  // six PBS_BATCH_* flags and the 2-bit workgroup order
 
 // Builds and uploads the job table of batch B for schedule `config`:
 // PBS_BATCH_GIVEN_ORDER keeps the caller's job order (else largest first),
@@ -560,6 +561,18 @@ void fill_batch(pbs_batch& B, uint32_t config) {
   B.row_lds = rowlds;
   B.realc = realc;
   B.lds = lds;
+  B.grid = B.total_blocks;
+  if (config & PBS_BATCH_PERSISTENT) {
+    // as many workgroups as are resident at once (both kernel forms share
+    // their resources); each walks the item list with a fixed stride
+    int dev = 0, cus = 0, per_cu = 0;
+    PBS_HIP(hipGetDevice(&dev));
+    PBS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    PBS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, sector_kernel(B.dt, false, true, r16, rowlds, realc),
+                                                         kSB, lds));
+    const uint64_t resident = static_cast<uint64_t>(std::max(cus, 1)) * static_cast<uint64_t>(std::max(per_cu, 1));
+    B.grid = static_cast<uint32_t>(std::min<uint64_t>(B.total_blocks, resident));
+  }
   B.config = config;
 }
 
@@ -567,10 +580,10 @@ void launch_batch(const pbs_batch& b, double* energies, hipStream_t s) {
   const bool ev = energies != nullptr;
   void* kern = sector_kernel(b.dt, ev, true, b.r16, b.row_lds, b.realc);
   const BatchJob* jobs = b.jobs.get();
-  uint32_t n = b.n_jobs;
+  uint32_t n = b.n_jobs, items = b.total_blocks;
   double* partial = b.partial.get();
-  void* args[] = {&jobs, &n, &partial};
-  PBS_HIP(hipLaunchKernel(kern, dim3(b.total_blocks), dim3(kSB), args, b.lds, s));
+  void* args[] = {&jobs, &n, &items, &partial};
+  PBS_HIP(hipLaunchKernel(kern, dim3(b.grid), dim3(kSB), args, b.lds, s));
   if (ev) {
     hipLaunchKernelGGL(k_batch_finish, dim3(n), dim3(kBlock), 0, s, jobs, n, b.total_blocks, partial, energies);
     PBS_HIP(hipGetLastError());

@@ -1336,29 +1336,37 @@ struct BatchJob {
 };
 constexpr uint32_t kOrderPlain = 0, kOrderRowFast = 1, kOrderXcdRows = 2;
 
-// All jobs of a batch in one launch: workgroup b belongs to the job with the
-// largest block_base <= b (jobs are stored in block order).
+// All jobs of a batch in one launch: work item w (one alpha row and column
+// chunk of one job) belongs to the job with the largest block_base <= w
+// (jobs are stored in block order, largest first by default).  With a grid
+// of one workgroup per item each workgroup takes one item; a persistent
+// launch has as many workgroups as fit on the device at once, and
+// workgroup i walks items i, i + grid, i + 2 grid, ... of that static list
+// (no atomics: the schedule is fixed by the grid size).
 template <class T, bool EXPVAL, bool R16, bool ROWLDS, bool REALC>
 __global__ __launch_bounds__(kSB) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_apply_sector_batch(
-    const BatchJob* __restrict__ jobs, uint32_t n_jobs, double* __restrict__ partial) {
-  uint32_t lo = 0, hi = n_jobs;
-  while (hi - lo > 1) {
-    const uint32_t mid = (lo + hi) / 2;
-    if (ldc(&jobs[mid].block_base) <= blockIdx.x)
-      lo = mid;
-    else
-      hi = mid;
+    const BatchJob* __restrict__ jobs, uint32_t n_jobs, uint32_t n_items, double* __restrict__ partial) {
+  for (uint32_t w = blockIdx.x; w < n_items; w += gridDim.x) {
+    if (w != blockIdx.x) __syncthreads();  // the previous item is done with LDS
+    uint32_t lo = 0, hi = n_jobs;
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) / 2;
+      if (ldc(&jobs[mid].block_base) <= w)
+        lo = mid;
+      else
+        hi = mid;
+    }
+    // fields are read from the (read-only) job table where they are used, so
+    // the record is not held in registers for the whole kernel
+    const BatchJob& J = jobs[lo];
+    const uint32_t b = w - J.block_base;
+    // a row's chunks share b mod 8 under kOrderXcdRows, hence one XCD whatever
+    // the job's first workgroup
+    uint32_t row = b / J.chunks, chunk = b % J.chunks;
+    if (J.order != kOrderPlain) row_chunk_of(b, J.rows, J.chunks, J.order == kOrderRowFast, row, chunk);
+    sector_body<T, EXPVAL, R16, ROWLDS, REALC>(J.args, static_cast<const T*>(J.psi), static_cast<T*>(J.out),
+                                               partial + 3ull * w, row, chunk);
   }
-  // fields are read from the (read-only) job table where they are used, so
-  // the record is not held in registers for the whole kernel
-  const BatchJob& J = jobs[lo];
-  const uint32_t b = blockIdx.x - J.block_base;
-  // a row's chunks share b mod 8 under kOrderXcdRows, hence one XCD whatever
-  // the job's first workgroup
-  uint32_t row = b / J.chunks, chunk = b % J.chunks;
-  if (J.order != kOrderPlain) row_chunk_of(b, J.rows, J.chunks, J.order == kOrderRowFast, row, chunk);
-  sector_body<T, EXPVAL, R16, ROWLDS, REALC>(J.args, static_cast<const T*>(J.psi), static_cast<T*>(J.out),
-                                             partial + 3ull * blockIdx.x, row, chunk);
 }
 
 // Address of one sector kernel variant (single launch or batch).

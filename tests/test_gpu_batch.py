@@ -70,10 +70,12 @@ def test_batch_matches_single_launches_and_oracle(dev, dtype):
         assert abs(ev_single[0] - e[k, 0]) < 1e-12 * max(1.0, abs(e_ref))
 
 
-def test_batch_graph_replay(dev):
+@pytest.mark.parametrize("config", [0, 128], ids=["grid", "persistent"])
+def test_batch_graph_replay(dev, config):
     api = _api()
     jobs, _ = _build(dev, torch.complex64)
     batch = api.Batch(jobs)
+    batch.set_config(config)
     energies = torch.zeros(3 * len(jobs), dtype=torch.float64, device=dev)
     batch.run(energies)
     torch.cuda.synchronize()
@@ -135,7 +137,7 @@ def test_every_schedule_matches_oracle(dev, dtype):
     tol = 1e-12 if dtype == torch.complex128 else 1e-6
     energies = torch.zeros(3 * len(jobs), dtype=torch.float64, device=dev)
     first = {}  # flags -> outputs under the first workgroup order tried
-    for config in range(128):
+    for config in range(256):
         batch.set_config(config)
         assert batch.info()[0] == config and batch.info()[1] == -1.0
         for _, _, _, out in jobs:
@@ -148,6 +150,7 @@ def test_every_schedule_matches_oracle(dev, dtype):
             assert abs(e[k, 0] - e_ref) < 1e-11 * max(1.0, abs(e_ref)), (config, k)
         # the workgroup order moves work between workgroups, never within a target
         outs = [torch.view_as_real(j[3]).clone() for j in jobs]
+        # a persistent launch (128) moves items between workgroups too
         flags = config & (15 | 64)
         if flags in first:
             assert all(torch.equal(a, b) for a, b in zip(outs, first[flags])), config
@@ -162,7 +165,7 @@ def test_tuner_keeps_the_fastest_schedule(dev):
     batch = api.Batch(jobs)
     wg0 = batch.info()[2]
     config, ms = batch.tune(reps=2)
-    assert 0 <= config < 128 and ms > 0.0
+    assert 0 <= config < 256 and ms > 0.0
     assert batch.info() == (config, ms, wg0)  # the workgroup count does not depend on the schedule
     for _, _, _, out in jobs:
         out.zero_()
@@ -171,7 +174,7 @@ def test_tuner_keeps_the_fastest_schedule(dev):
     for (_, _, _, out), (ref, _) in zip(jobs, want):
         assert rel_err(out.cpu().numpy(), ref) < 1e-6
     with pytest.raises(Exception, match="schedule"):
-        batch.set_config(128)
+        batch.set_config(256)
 
 
 def test_config3_batch_of_64_uneven_sectors(dev):
