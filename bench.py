@@ -4,12 +4,15 @@ One step is one pass of the whole path on the 28-qubit molecular workload
 (14 spatial orbitals, (7, 7) spin sector, D = 11,778,624): Jordan-Wigner
 construction from device-resident integrals (string products + canonical
 reduction), grouping by X-mask with the sector tables, the sector's rank
-tables, H|psi> with complex64 storage and float64 accumulation, and the fused
+tables, the spin-factorized phase tables of the sector (group factors, beta
+factors and move tables, alpha lists and images; --no-factor leaves them
+out), H|psi> with complex64 storage and float64 accumulation, and the fused
 float64 energy <psi|H|psi>.  The metric is amplitude*terms per second,
 D * M / t_step with M the number of canonical Pauli strings.
 
-The dominant kernel (the sector apply) is timed with HIP events on the
-stream it runs on.  On the molecular sector it is bound by vector-ALU issue:
+The dominant kernel (the sector apply; for the Hubbard sector the rows
+kernel) is timed with HIP events on the stream it runs on.  On the molecular
+sector it is bound by vector-ALU issue:
 its roofline is its VALU wave-instructions per launch (from the committed
 rocprofv3 counters of the same kernel source) per second against 614.4 G/s,
 with the measured HBM traffic and the method's algorithmic gather bytes,
@@ -43,13 +46,16 @@ WORKLOADS = {
                                                bound="alu")),
     "molecular-12q-sector": ("molecular", dict(n_orb=6, n_alpha=3, n_beta=3, h_seed=1001, psi_seed=1102,
                                                bound="alu")),
-    "hubbard-32q-sector": ("hubbard", dict(rows=4, cols=4, n_alpha=8, n_beta=8, psi_seed=4101, bound="hbm")),
+    # the Hubbard sector's rows (103 KB) are too long to stage: with the
+    # factor tables its apply is the rows kernel
+    "hubbard-32q-sector": ("hubbard", dict(rows=4, cols=4, n_alpha=8, n_beta=8, psi_seed=4101, bound="hbm",
+                                           kernel="rows")),
 }
 
 
 # sources that decide what the sector apply kernel does per launch: its
 # device code, its launch planner and the tables grouping builds for it
-APPLY_SOURCES = ("apply.hip", "factor.hip", "group.hip", "handles.h", "sector.h", "sector_c128_apply.hip",
+APPLY_SOURCES = ("apply.hip", "factor.hip", "group.hip", "handles.h", "host_plan.h", "sector.h", "sector_c128_apply.hip",
                  "sector_c128_expval.hip", "sector_c64_apply.hip", "sector_c64_expval.hip")
 
 
@@ -267,6 +273,8 @@ def bench_krylov(args):
     h1, h2 = synth.hubbard_spin_integrals(4, 4, t=1.0, u=4.0)
     G = api.jw_transform(torch.from_numpy(h1).to(dev), torch.from_numpy(h2).to(dev)).group()
     sp = api.Space.sector(16, 8, 8)
+    if not args.no_factor:
+        G.factor(sp)  # spin-factorized tables: the applies run the rows kernel
     na, nb = synth.neel_occupations(4, 4)
     start = sp.rank(torch.tensor([na | (nb << 16)], dtype=torch.int64, device=dev)).item()
     res = {}
@@ -294,7 +302,7 @@ def bench_krylov(args):
     for r in res.values():
         r.pop("psi")
     print(json.dumps({"workload": "hubbard-32q-krylov", "steps": args.krylov_steps, "dt": 0.05, "vectors": 12,
-                      "dim": sp.dim, "c64": res["c64"], "c128": res["c128"],
+                      "dim": sp.dim, "factored": not args.no_factor, "c64": res["c64"], "c128": res["c128"],
                       "final_state_rel_diff_c64_vs_c128": diff}))
 
 
@@ -313,7 +321,7 @@ def bench_pes(args):
 
     n_orb, na, nb, n_rot = 12, 6, 6, 200
     dev = torch.device("cuda:0")
-    gens = synth.excitation_generators(n_orb, na, nb, n_rot)
+    x, z = synth.excitation_masks(n_orb, na, nb, n_rot)
     ref = ((1 << na) - 1) | (((1 << nb) - 1) << n_orb)
     radii = np.linspace(0.0, 1.0, args.geometries)
     # cost of one energy + gradient evaluation at the middle of the scan
@@ -327,7 +335,6 @@ def bench_pes(args):
 
     gathers = sum(comb(n_orb, a) * comb(n_orb, b) * (1.0 + _connected_groups(xg, n_orb, a, b))
                   for a in range(n_orb + 1) for b in range(n_orb + 1))
-    x, z = pes.letters_to_masks(gens)
     evals = {}
     for name, dtype in (("c128", torch.complex128), ("c64", torch.complex64)):
         v = api.VQE(G, n_orb, x, z, ref, dtype=dtype)
@@ -350,7 +357,7 @@ def bench_pes(args):
               file=sys.stderr, flush=True)
 
     t0 = time.perf_counter()
-    recs = pes.scan(lambda r: synth.pes_integrals(n_orb, r), radii, n_orb, gens, ref, dtype=torch.complex128,
+    recs = pes.scan(lambda r: synth.pes_integrals(n_orb, r), radii, n_orb, x, z, ref, dtype=torch.complex128,
                     hidden=256, mlp_params=synth.mlp_init(256, n_rot, seed=2), train_steps=600, lr=1e-3,
                     g_tol=1e-5, log=log)
     wall = time.perf_counter() - t0
@@ -358,6 +365,12 @@ def bench_pes(args):
     out = {"workload": "pes-scan-24q", "n_qubits": 2 * n_orb, "dim": 1 << (2 * n_orb), "rotations": n_rot,
            "geometries": len(radii), "pauli_strings_R0.5": n_terms, "groups_R0.5": n_groups,
            "apply_gather_amplitudes_R0.5": gathers,
+           "integrals": {"form": "h(R) = h0 + s (R h1 + R^2 h2), g(R) likewise", "s": 0.3, "basis": "eigenbasis of h0",
+                         "seeds": [5001, 5002, 5003],
+                         "change": "differs from plain h0 + R h1 + R^2 h2 in the draws' own basis: the R terms "
+                                   "are scaled by s = 0.3 and every term is expressed in h0's eigenbasis, so the "
+                                   "(6, 6) reference is h0's one-body ground state (as Hartree-Fock orbitals make "
+                                   "it) and the scan starts near a mean-field solution"},
            "network": "1-256-256-200 bf16/fp32", "dtype": "c128 (fp64 energies)",
            "g_tol": 1e-5, "wall_s": wall, "evaluation": evals, **summ,
            "sec_cold": sum(r["sec_cold"] for r in recs), "sec_warm": sum(r["sec_warm"] for r in recs),
@@ -520,7 +533,7 @@ def main():
     # reported beside it: most of them are served from LDS and caches.
     bytes_per_launch = D * 8 * (1.0 + g_conn)
     gather_gbs = bytes_per_launch / (apply_ms * 1e-3) / 1e9
-    kernel_tag = f"apply_sector_c64_{args.workload}"
+    kernel_tag = f"apply_{prm.get('kernel', 'sector') if not args.no_factor else 'sector'}_c64_{args.workload}"
     ctr = _counters(kernel_tag)
     traffic = ctr.get("hbm_bytes_per_launch") if ctr else None
     valu = ctr.get("valu_wave_insts_per_launch") if ctr else None

@@ -49,8 +49,6 @@ __global__ __launch_bounds__(kBlock) void k_apply_full(uint64_t dim, uint32_t n_
   if (EXPVAL) block_reduce3_store<kBlock>(e_re, e_im, nrm, partial + 3ull * blockIdx.x);
 }
 
-constexpr uint32_t kFCapMin = 1024;  // folded uniques: smallest LDS capacity planned for
-constexpr uint32_t kFCapMax = 4096;  // and the largest (offsets are packed in 16 bits)
 
 // Per-job sums of workgroup partials (one workgroup per job, fixed order).
 __global__ __launch_bounds__(kBlock) void k_batch_finish(const BatchJob* jobs, uint32_t n_jobs, uint32_t total_blocks,
@@ -86,8 +84,6 @@ struct Launch {
   uint64_t parts = 0;
   size_t lds = 0;
 };
-
-inline uint32_t align16(uint32_t v) { return (v + 15u) & ~15u; }
 
 int device_lds_limit() {
   int dev = 0, v = 0;
@@ -137,39 +133,6 @@ Launch plan_sector(const pbs_grouped& h, const pbs_space& sp, size_t elem_bytes,
   a.pt_za = h.pt_za.get();
   a.pt_c = reinterpret_cast<const double2*>(h.pt_c.get());
 
-  const uint32_t limit = static_cast<uint32_t>(device_lds_limit()) - 1024u;  // static shared arrays
-  const uint32_t half = limit / 2u - 512u;
-  *r16 = sp.n_orb <= 16;
-  const uint32_t rank_bytes = *r16 ? align16(kRank16Lds * 2u) : 0u;
-  const uint32_t per_unique = (realc ? 8u : 16u) + 4u;
-  const uint32_t f_min = (kFCapMin + kZeroSlots) * per_unique + 64u;
-  a.enum_ok = (allow_enum && h.n_pmap > 0 && a.n_moves <= static_cast<uint32_t>(kMaxMoves) && sp.dim_beta < 65536 &&
-               h.n_pairs < 65536)
-                  ? 1u
-                  : 0u;
-  const uint32_t pu_bytes = kMiscBytes + kPuBytes;  // fixed: scratch and pair map (n_pairs + 1 <= 512 slots)
-  PBS_REQUIRE(h.n_pairs + 1 <= kPuBytes / 8, PBS_ERR_RANGE, "too many orbital pairs for the pair map");
-  const uint64_t n_ep = host_binom(sp.n_orb - sp.n_beta, 2), n_op = host_binom(sp.n_beta, 2);
-  a.qenum_ok = (allow_qenum && *r16 && a.enum_ok && h.n_qmap > 0 && h.n_quads > 0 && n_op * n_ep > 0) ? 1u : 0u;
-  a.n_quads = h.n_quads;
-  a.n_qmoves = static_cast<uint32_t>(n_op * n_ep);
-  const uint64_t row_bytes = sp.dim_beta * elem_bytes;
-  const uint64_t row_space = row_bytes > kListMinBytes ? row_bytes : kListMinBytes;
-  a.row_lds = (allow_row && row_bytes <= kRowCapBytes && rank_bytes + f_min + pu_bytes + row_space <= limit) ? 1u : 0u;
-  const uint32_t row_region = align16(static_cast<uint32_t>(a.row_lds ? row_space : kListMinBytes));
-  a.list_cap = row_region / 8u;
-  // The double-move phase needs its quad map and every quad unique of a
-  // class in LDS at once; it is kept only if that still lets two workgroups
-  // share a compute unit (or if two never fit anyway).
-  const uint32_t base_fixed = rank_bytes + row_region + pu_bytes;
-  const uint32_t qu_need = align16(h.n_quads * 4);
-  const uint32_t q_need = (h.max_quad_uniques + kZeroSlots) * per_unique + 64u;
-  if (a.qenum_ok) {
-    const bool two_without = base_fixed + f_min <= half;
-    const uint32_t cap = two_without ? half : limit;
-    if (base_fixed + qu_need + std::max(q_need, f_min) > cap || h.max_quad_uniques >= kFCapMax) a.qenum_ok = 0u;
-  }
-  const uint32_t qu_bytes = a.qenum_ok ? qu_need : 0u;
   // spin-factorized evaluation when the operator carries tables for this
   // beta sector (real coefficients)
   const FactorPlan* F = h.fplan.get();
@@ -177,28 +140,37 @@ Launch plan_sector(const pbs_grouped& h, const pbs_space& sp, size_t elem_bytes,
   const bool fact = fact_ok && (h.fact_on & (kFactZero | kFactMoves)) && F->n_beta == sp.n_beta &&
                     F->dim_beta == sp.dim_beta;
   const bool fact_a = fact_ok && (h.fact_on & kFactAlpha) && F->alist && F->n_alpha == sp.n_alpha;
-  // the folded factors of an X_beta = 0 group sit after the pair map when
-  // its fixed region has room (n_orb <= 16), else in a region of their own
-  const uint32_t a_in_pu = align16((h.n_pairs + 1u) * 8u);
-  const bool a_fits_pu = a_in_pu + kMaxR1 * 8u <= kPuBytes;
-  const uint32_t a_bytes = ((fact || fact_a) && !a_fits_pu) ? align16(kMaxR1 * 8u) : 0u;
-  const uint32_t fixed = base_fixed + qu_bytes + a_bytes;
-  const uint32_t budget = fixed + f_min <= half ? half : limit;
-  a.f_cap = std::min(kFCapMax, (budget - fixed - 64u) / per_unique - kZeroSlots);
-  // layout: scratch [0, kMiscBytes), pair map at kPuOff, row or row list at
-  // kRowOff, then the rank tables, the folded uniques, their Z-masks and the
-  // quad map
-  uint32_t off = kRowOff + row_region;
-  a.off_rank = off;
-  off += rank_bytes;
-  a.off_f = off;
-  off += align16((a.f_cap + kZeroSlots) * (per_unique - 4u));
-  a.off_fz = off;
-  off += align16((a.f_cap + kZeroSlots) * 4u);
-  a.off_qu = off;
-  off += qu_bytes;
-  a.off_a = a_fits_pu ? kPuOff + a_in_pu : off;
-  off += a_bytes;
+  SectorLayoutIn in;
+  in.lds_limit = static_cast<uint32_t>(device_lds_limit()) - 1024u;  // static shared arrays
+  in.n_orb = sp.n_orb;
+  in.n_beta = sp.n_beta;
+  in.dim_beta = sp.dim_beta;
+  in.elem_bytes = static_cast<uint32_t>(elem_bytes);
+  in.realc = realc;
+  in.allow_row = allow_row;
+  in.allow_enum = allow_enum;
+  in.allow_qenum = allow_qenum;
+  in.n_pmap = h.n_pmap;
+  in.n_qmap = h.n_qmap;
+  in.n_pairs = h.n_pairs;
+  in.n_quads = h.n_quads;
+  in.max_quad_uniques = h.max_quad_uniques;
+  in.a_region = fact || fact_a;
+  SectorLayout Y;
+  PBS_REQUIRE(sector_layout(in, &Y), PBS_ERR_RANGE, "too many orbital pairs for the pair map");
+  *r16 = Y.r16;
+  a.enum_ok = Y.enum_ok ? 1u : 0u;
+  a.qenum_ok = Y.qenum_ok ? 1u : 0u;
+  a.n_quads = h.n_quads;
+  a.n_qmoves = Y.n_qmoves;
+  a.row_lds = Y.row_lds ? 1u : 0u;
+  a.list_cap = Y.list_cap;
+  a.f_cap = Y.f_cap;
+  a.off_rank = Y.off_rank;
+  a.off_f = Y.off_f;
+  a.off_fz = Y.off_fz;
+  a.off_qu = Y.off_qu;
+  a.off_a = Y.off_a;
   a.fact = fact ? (h.fact_on & kFactZero) : 0u;
   a.f_c0 = 0xffffffffu;
   if (fact_a) {
@@ -262,7 +234,7 @@ Launch plan_sector(const pbs_grouped& h, const pbs_space& sp, size_t elem_bytes,
   L.chunks = static_cast<uint32_t>(chunks);
   L.block = dim3(kSB);
   L.parts = sp.dim_alpha * chunks;
-  L.lds = off;
+  L.lds = Y.lds;
   return L;
 }
 
@@ -314,7 +286,7 @@ void validate(const pbs_grouped* h, const pbs_space* sp, pbs_dtype dt) {
 
 // Layout of the rows kernel when it applies (see k_apply_rows): factored
 // alpha lists, rows not staged, every non-simple class in LDS.
-bool plan_rows(const pbs_grouped& h, const SectorArgs& a, bool r16, RowsLayout* Lr, size_t* lds) {
+bool plan_rows(const pbs_grouped& h, const SectorArgs& a, bool r16, bool expval, RowsLayout* Lr, size_t* lds) {
   const FactorPlan* F = h.fplan.get();
   if (!r16 || a.row_lds || a.alist_off == nullptr || F == nullptr || a.ns_list != h.ns_list.get()) return false;
   if (F->ns_uniques >= 65536u || F->ns_uniques + F->ns_groups == 0) return false;
@@ -334,7 +306,9 @@ bool plan_rows(const pbs_grouped& h, const SectorArgs& a, bool r16, RowsLayout* 
   off += align16(F->ns_uniques * 8u);
   L.off_fz = off;
   off += align16(F->ns_uniques * 4u);
-  if (off > 48u * 1024u) return false;
+  L.off_e = off;  // per-thread energy sums (the fused energy pass only)
+  if (expval) off += 3u * kSB * 8u;
+  if (off > 60u * 1024u) return false;
   *Lr = L;
   *lds = off;
   return true;
@@ -357,7 +331,7 @@ uint64_t launch(const pbs_grouped& h, const pbs_space& sp, const void* psi, void
     const pbs_dtype dt = sizeof(T) == 16 ? PBS_C128 : PBS_C64;
     RowsLayout Lr;
     size_t lds_rows = 0;
-    if (h.real_coef && plan_rows(h, a, r16, &Lr, &lds_rows)) {
+    if (h.real_coef && plan_rows(h, a, r16, EXPVAL, &Lr, &lds_rows)) {
       // one workgroup per alpha row, sweeping all of its columns
       hipLaunchKernelGGL((k_apply_rows<T, EXPVAL>), dim3(static_cast<unsigned>(sp.dim_alpha)), dim3(kSB), lds_rows, s,
                          a, Lr, p, o, partial);
@@ -503,7 +477,7 @@ void fill_batch(pbs_batch& B, uint32_t config) {
   const bool factd = !(config & PBS_BATCH_NO_FACTORED);
   std::vector<BatchJob> jobs(n);
   std::vector<double> cost(n);
-  std::vector<uint32_t> order(n);
+  std::vector<uint64_t> items(n);
   // one launch shares one kernel variant: rows staged only if every job's
   // row fits, LDS rank tables only if every job has n_orb <= 16
   bool r16 = true, rowlds = allow_row, realc = true;
@@ -529,25 +503,23 @@ void fill_batch(pbs_batch& B, uint32_t config) {
     jobs[i].pad = 0;
     lds = std::max(lds, L.lds);
     cost[i] = static_cast<double>(B.sp[i]->dim) * static_cast<double>(B.h[i]->n_pterm + 1);
-    order[i] = i;
+    items[i] = static_cast<uint64_t>(B.sp[i]->dim_alpha) * L.chunks;
   }
   // largest jobs first, so the launch does not end on a long straggler
-  if (!given) std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return cost[a] > cost[b]; });
+  const BatchPlan plan = batch_plan(cost, items, given);
   const uint32_t order_field = config & PBS_BATCH_ORDER_MASK;
   const uint32_t grid_order = order_field == PBS_BATCH_ORDER_PLAIN     ? kOrderPlain
                               : order_field == PBS_BATCH_ORDER_ROW_FAST ? kOrderRowFast
                               : order_field == PBS_BATCH_ORDER_XCD_ROWS ? kOrderXcdRows
                               : (rowlds ? kOrderRowFast : kOrderXcdRows);
   for (uint32_t i = 0; i < n; ++i) jobs[i].order = grid_order;
+  PBS_REQUIRE(plan.total < (1ull << 31), PBS_ERR_RANGE, "batch needs more than 2^31 workgroups");
   std::vector<BatchJob> sorted(n);
-  uint64_t base = 0;
   for (uint32_t k = 0; k < n; ++k) {
-    BatchJob J = jobs[order[k]];
-    J.block_base = static_cast<uint32_t>(base);
-    base += static_cast<uint64_t>(B.sp[order[k]]->dim_alpha) * J.chunks;
-    sorted[k] = J;
+    sorted[k] = jobs[plan.order[k]];
+    sorted[k].block_base = static_cast<uint32_t>(plan.base[k]);
   }
-  PBS_REQUIRE(base < (1ull << 31), PBS_ERR_RANGE, "batch needs more than 2^31 workgroups");
+  const uint64_t base = plan.total;
   if (lds > 64 * 1024) {
     for (bool ev : {false, true})
       PBS_HIP(hipFuncSetAttribute(sector_kernel(B.dt, ev, true, r16, rowlds, realc),

@@ -242,104 +242,6 @@ __global__ void k_pair_images(uint64_t n_ent, uint32_t n_img, uint32_t n_pairs, 
 
 // ---------------------------------------------------------------- host side
 
-// One group's factors: for each r, the alpha terms (Za, P[mu][r]) and the
-// beta list (Zb, Q[r][nu]); exact zeros are left out.
-struct GroupFactors {
-  uint32_t rank = 0;
-  uint32_t n_uniques = 0;
-  std::vector<std::vector<std::pair<uint32_t, double>>> a, b;
-};
-
-// M = P Q by pivoted Gram-Schmidt on the rows of M (rows x cols, row-major):
-// the next basis vector is the remaining row of largest norm, orthogonalised
-// twice against the basis; stops when every remaining row is below
-// rtol * (largest row norm of M).
-uint32_t factor_rows(const std::vector<double>& M, uint32_t rows, uint32_t cols, double rtol,
-                     std::vector<double>& Q) {
-  std::vector<double> res = M;
-  Q.clear();
-  double scale = 0.0;
-  for (uint32_t i = 0; i < rows; ++i) {
-    double s = 0.0;
-    for (uint32_t j = 0; j < cols; ++j) s += M[i * cols + j] * M[i * cols + j];
-    scale = std::max(scale, std::sqrt(s));
-  }
-  if (scale == 0.0) return 0;
-  uint32_t r = 0;
-  std::vector<double> q(cols);
-  while (r < rows && r < cols) {
-    uint32_t best = 0;
-    double bn = -1.0;
-    for (uint32_t i = 0; i < rows; ++i) {
-      double s = 0.0;
-      for (uint32_t j = 0; j < cols; ++j) s += res[i * cols + j] * res[i * cols + j];
-      if (s > bn) {
-        bn = s;
-        best = i;
-      }
-    }
-    if (std::sqrt(bn) <= rtol * scale) break;
-    for (uint32_t j = 0; j < cols; ++j) q[j] = res[best * cols + j];
-    for (int pass = 0; pass < 2; ++pass) {
-      for (uint32_t k = 0; k < r; ++k) {
-        double d = 0.0;
-        for (uint32_t j = 0; j < cols; ++j) d += q[j] * Q[k * cols + j];
-        for (uint32_t j = 0; j < cols; ++j) q[j] -= d * Q[k * cols + j];
-      }
-      double nn = 0.0;
-      for (uint32_t j = 0; j < cols; ++j) nn += q[j] * q[j];
-      nn = std::sqrt(nn);
-      for (uint32_t j = 0; j < cols; ++j) q[j] /= nn;
-    }
-    Q.insert(Q.end(), q.begin(), q.end());
-    ++r;
-    for (uint32_t i = 0; i < rows; ++i) {
-      double d = 0.0;
-      for (uint32_t j = 0; j < cols; ++j) d += res[i * cols + j] * q[j];
-      for (uint32_t j = 0; j < cols; ++j) res[i * cols + j] -= d * q[j];
-    }
-  }
-  return r;
-}
-
-struct HostTables {
-  std::vector<uint32_t> pg_u0, u_zb, u_t0, pt_za, pg_xb;
-  std::vector<double> pt_c;  // real parts
-};
-
-GroupFactors factor_group(const HostTables& T, uint32_t g) {
-  GroupFactors F;
-  const uint32_t u0 = T.pg_u0[g], u1 = T.pg_u0[g + 1];
-  F.n_uniques = u1 - u0;
-  // rows: the distinct alpha Z-masks, ascending
-  std::vector<uint32_t> za(T.pt_za.begin() + T.u_t0[u0], T.pt_za.begin() + T.u_t0[u1]);
-  std::sort(za.begin(), za.end());
-  za.erase(std::unique(za.begin(), za.end()), za.end());
-  auto row_of = [&](uint32_t z) {
-    return static_cast<uint32_t>(std::lower_bound(za.begin(), za.end(), z) - za.begin());
-  };
-  const uint32_t nr = static_cast<uint32_t>(za.size()), nc = u1 - u0;
-  std::vector<double> M(static_cast<size_t>(nr) * nc, 0.0);
-  for (uint32_t u = u0; u < u1; ++u)
-    // terms whose beta Z-masks differ by X_beta share one unique in sector
-    // form and may share an alpha Z-mask too: their coefficients add
-    for (uint32_t t = T.u_t0[u]; t < T.u_t0[u + 1]; ++t) M[row_of(T.pt_za[t]) * nc + (u - u0)] += T.pt_c[t];
-  std::vector<double> Q;
-  F.rank = factor_rows(M, nr, nc, 1e-14, Q);
-  F.a.resize(F.rank);
-  F.b.resize(F.rank);
-  for (uint32_t r = 0; r < F.rank; ++r) {
-    for (uint32_t mu = 0; mu < nr; ++mu) {
-      double p = 0.0;
-      for (uint32_t nu = 0; nu < nc; ++nu) p += M[mu * nc + nu] * Q[r * nc + nu];
-      if (p != 0.0) F.a[r].emplace_back(za[mu], p);
-    }
-    for (uint32_t nu = 0; nu < nc; ++nu)
-      if (Q[r * nc + nu] != 0.0) F.b[r].emplace_back(T.u_zb[u0 + nu], Q[r * nc + nu]);
-  }
-  return F;
-}
-
 template <class T>
 void upload(DevBuf<T>& d, const std::vector<T>& h) {
   d.alloc(h.size());

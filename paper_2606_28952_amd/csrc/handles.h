@@ -3,6 +3,7 @@
 
 #include <memory>
 
+#include "host_plan.h"
 #include "pbs_internal.h"
 
 // Operator grouped by X-mask (Eq. topological_group) plus the tables of the
@@ -136,8 +137,6 @@ struct FactorPlan {
   // groups of all non-simple classes
   uint32_t alist_max = 0, ns_uniques = 0, ns_groups = 0;
 };
-constexpr uint32_t kMaxR1 = 32;       // largest factored rank of an X_beta = 0 group
-constexpr uint32_t kFactZeroSlots = 4;  // zero factors at the start of the class-0 fold
 }  // namespace pbs
 
 struct pbs_grouped {

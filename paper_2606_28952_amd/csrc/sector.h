@@ -196,22 +196,8 @@ struct Coef<true> {
 
 // ---------------------------------------------------------------- spin sector
 constexpr int kSB = 512;              // lanes per sector workgroup = beta columns per workgroup
-constexpr int kMaxMoves = 56;         // pair moves cached per lane (N_beta (n_orb - N_beta) <= 56)
-constexpr uint32_t kRowCapBytes = 64u * 1024u;
-constexpr uint32_t kListMinBytes = 4096u;  // simple-class row list when no row is staged
-// LDS copy of the uint16 rank tables (n_orb <= 16): chunk 0 with no ones
-// below it, then chunk 1 for 0..8 ones below it (zeros when n_orb <= 8)
-constexpr uint32_t kRank16Lds = 10u * 256u;
 constexpr int kGather = 16;  // simple-class row loads in flight per lane
-// Fixed LDS placement (the kernel declares no static LDS, so these are
-// absolute addresses): workgroup scratch at byte 0, the pair map at kPuOff
-// (an 8-byte slot per orbital pair, at most C(32, 2) + 1 entries) and the staged
-// row at kRowOff, so per-move addresses need no base register.
-constexpr uint32_t kMiscBytes = 256;  // ballot counts and the energy reduction
-constexpr uint32_t kPuOff = kMiscBytes;
-constexpr uint32_t kPuBytes = 4096;
-constexpr uint32_t kRowOff = kPuOff + kPuBytes;
-constexpr uint32_t kZeroSlots = 4;  // zero entries after the folded uniques (absent groups, padding)
+// the LDS placement constants (kPuOff, kRowOff, ...) are in host_plan.h
 
 constexpr uint32_t kFactZero = 1u;  // X_beta = 0 groups through their F rows
 constexpr uint32_t kFactMoves = 2u;  // the X_alpha = 0 class through the move tables
@@ -1176,12 +1162,12 @@ __device__ inline void row_chunk_of(uint32_t b, uint32_t rows, uint32_t chunks, 
 // record), group records (X_beta, first unique | count << 16), folded
 // uniques and their beta Z-masks; offsets in RowsLayout.
 struct RowsLayout {
-  uint32_t off_rank, off_lsrc, off_lc, off_cls, off_grp, off_f, off_fz;
+  uint32_t off_rank, off_lsrc, off_lc, off_cls, off_grp, off_f, off_fz, off_e;
   uint32_t max_list, max_cls, max_grp, max_u;
 };
 
 template <class T, bool EXPVAL>
-__global__ __launch_bounds__(kSB) void k_apply_rows(SectorArgs P, RowsLayout Lr, const T* __restrict__ psi,
+__global__ __launch_bounds__(kSB) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 8 : 1, 8))) void k_apply_rows(SectorArgs P, RowsLayout Lr, const T* __restrict__ psi,
                                                     T* __restrict__ out, double* __restrict__ partial) {
   extern __shared__ __align__(16) unsigned char smem[];
   const uint32_t ia = blockIdx.x;
@@ -1247,7 +1233,15 @@ __global__ __launch_bounds__(kSB) void k_apply_rows(SectorArgs P, RowsLayout Lr,
 
   const uint32_t chunks = static_cast<uint32_t>((db + kSB - 1) / kSB);
   const uint32_t n_list = a1 - a0;
-  double e_re = 0.0, e_im = 0.0, nrm = 0.0;
+  // the energy sums live in LDS (one slot per thread, volatile so they are
+  // not promoted back to registers): three doubles held across the sweep
+  // would push the kernel past 64 VGPRs and cost a quarter of its waves
+  volatile double* s_e = reinterpret_cast<volatile double*>(smem + Lr.off_e);
+  if (EXPVAL) {
+    s_e[threadIdx.x] = 0.0;
+    s_e[kSB + threadIdx.x] = 0.0;
+    s_e[2 * kSB + threadIdx.x] = 0.0;
+  }
   for (uint32_t ch = 0; ch < chunks; ++ch) {
     const uint32_t col = ch * kSB + threadIdx.x;
     const bool live = col < db;
@@ -1300,16 +1294,18 @@ __global__ __launch_bounds__(kSB) void k_apply_rows(SectorArgs P, RowsLayout Lr,
       if (EXPVAL) {
         double pr, pi;
         Amp<T>::load(psi, t, pr, pi);
-        e_re = fma(pr, acc_r, fma(pi, acc_i, e_re));
-        e_im = fma(pr, acc_i, fma(-pi, acc_r, e_im));
-        nrm = fma(pr, pr, fma(pi, pi, nrm));
+        s_e[threadIdx.x] = fma(pr, acc_r, fma(pi, acc_i, s_e[threadIdx.x]));
+        s_e[kSB + threadIdx.x] = fma(pr, acc_i, fma(-pi, acc_r, s_e[kSB + threadIdx.x]));
+        s_e[2 * kSB + threadIdx.x] = fma(pr, pr, fma(pi, pi, s_e[2 * kSB + threadIdx.x]));
         if (out) Amp<T>::store(out, t, acc_r, acc_i);
       } else {
         Amp<T>::store(out, t, acc_r, acc_i);
       }
     }
   }
-  if (EXPVAL) block_reduce3_store<kSB>(e_re, e_im, nrm, partial + 3ull * blockIdx.x, reinterpret_cast<double(*)[kSB / 64]>(smem + 64));
+  if (EXPVAL)
+    block_reduce3_store<kSB>(s_e[threadIdx.x], s_e[kSB + threadIdx.x], s_e[2 * kSB + threadIdx.x],
+                             partial + 3ull * blockIdx.x, reinterpret_cast<double(*)[kSB / 64]>(smem + 64));
 }
 
 // One-dimensional grid of dim_alpha * chunks workgroups.
