@@ -22,34 +22,23 @@ import torch
 
 from . import api
 
-LETTER_X, LETTER_Y, LETTER_Z = 1, 2, 3
 
-
-def letters_to_masks(letters):
-    """Letter rows (0=I, 1=X, 2=Y, 3=Z; qubit k = column k, at most 64
-    qubits) -> (x, z) uint64 masks, one word per row."""
-    letters = np.atleast_2d(np.asarray(letters, dtype=np.uint8))
-    if letters.shape[1] > 64:
-        raise ValueError("at most 64 qubits per rotation")
-    weights = np.uint64(1) << np.arange(letters.shape[1], dtype=np.uint64)
-    xbit = (letters == LETTER_X) | (letters == LETTER_Y)
-    zbit = (letters == LETTER_Y) | (letters == LETTER_Z)
-    x = (xbit.astype(np.uint64) * weights).sum(axis=1, dtype=np.uint64)
-    z = (zbit.astype(np.uint64) * weights).sum(axis=1, dtype=np.uint64)
-    return x, z
-
-
-def scan(integrals, radii, n_orb, generators, ref, *, dtype=torch.complex128, hidden=256, mlp_params=None,
+def scan(integrals, radii, n_orb, gen_x, gen_z, ref, *, dtype=torch.complex128, hidden=256, mlp_params=None,
          train_steps=600, lr=1e-3, min_train=1, max_iter=500, g_tol=1e-5, f_tol=0.0, run_cold=True, log=None):
     """Runs the scan.
 
     integrals(R) -> (h1, h2) spin-orbital arrays (float64, host);
-    generators: letter rows of the rotation generators (applied in order);
+    gen_x, gen_z: uint64 X and Z masks of the Hermitian rotation generators
+    P_k (bit q = qubit q, phase 0, applied in order), as ``api.VQE`` takes
+    them;
     ref: reference basis state; mlp_params: packed float32 initial network
     parameters (``api.MLP`` layout) for hidden width ``hidden``.
     Returns a list of per-geometry records (dicts)."""
     dev = torch.device("cuda")
-    x, z = letters_to_masks(generators)
+    x = np.ascontiguousarray(gen_x, dtype=np.uint64)
+    z = np.ascontiguousarray(gen_z, dtype=np.uint64)
+    if x.shape != z.shape or x.ndim != 1:
+        raise ValueError("gen_x and gen_z must be 1-D arrays of one mask per rotation")
     n_rot = len(x)
     net = api.MLP(hidden, n_rot, max(1, len(radii)), mlp_params) if mlp_params is not None else None
     seen_r, seen_theta = [], []

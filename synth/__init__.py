@@ -34,6 +34,7 @@ __all__ = [
     "neel_occupations",
     "pes_integrals",
     "excitation_generators",
+    "excitation_masks",
     "mlp_init",
 ]
 
@@ -227,6 +228,26 @@ def pes_integrals(n_orb, r, seed=5001, r_scale=0.3):
     return spin_orbital_integrals(h, g)
 
 
+def _excitation_qubits(n_orb, n_alpha, n_beta, count, seed):
+    """Sorted qubit tuples of the ansatz's excitations, in ansatz order: every
+    spin-conserving single (i -> a), then every spin-conserving double
+    (i j -> a b) in a seeded random order, cut to ``count``."""
+    occ = [p for p in range(n_alpha)] + [n_orb + p for p in range(n_beta)]
+    vir = [p for p in range(n_alpha, n_orb)] + [n_orb + p for p in range(n_beta, n_orb)]
+    spin = lambda q: q // n_orb
+    singles = [(i, a) for i in occ for a in vir if spin(i) == spin(a)]
+    doubles = []
+    for ii, i in enumerate(occ):
+        for j in occ[ii + 1:]:
+            for aa, a in enumerate(vir):
+                for b in vir[aa + 1:]:
+                    if sorted((spin(i), spin(j))) == sorted((spin(a), spin(b))):
+                        doubles.append((i, j, a, b))
+    rng = np.random.default_rng(seed)
+    doubles = [doubles[k] for k in rng.permutation(len(doubles))]
+    return [tuple(sorted(q)) for q in (singles + doubles)[:count]]
+
+
 def excitation_generators(n_orb, n_alpha, n_beta, count, seed=7):
     """Letter strings (uint8 rows over 2 n_orb qubits, 0=I 1=X 2=Y 3=Z) that
     generate the rotations of a synthetic excitation ansatz on the reference
@@ -237,33 +258,37 @@ def excitation_generators(n_orb, n_alpha, n_beta, count, seed=7):
     qubit, X on its other qubits, and Z on the qubits strictly inside each
     consecutive pair of its sorted qubits (first-second, third-fourth).  The
     list holds all singles, then the doubles in a seeded random order, cut
-    to ``count`` strings."""
+    to ``count`` strings.  ``excitation_masks`` gives the same strings as
+    X/Z bit masks."""
     n = 2 * n_orb
-    occ = [p for p in range(n_alpha)] + [n_orb + p for p in range(n_beta)]
-    vir = [p for p in range(n_alpha, n_orb)] + [n_orb + p for p in range(n_beta, n_orb)]
-    spin = lambda q: q // n_orb
-
-    def string(qubits):
-        qs = sorted(qubits)
+    rows = []
+    for qs in _excitation_qubits(n_orb, n_alpha, n_beta, count, seed):
         s = np.zeros(n, np.uint8)
         for a, b in zip(qs[0::2], qs[1::2]):
             s[a + 1:b] = 3
-        s[qs] = 1
+        s[list(qs)] = 1
         s[qs[0]] = 2
-        return s
-
-    singles = [string((i, a)) for i in occ for a in vir if spin(i) == spin(a)]
-    doubles = []
-    for ii, i in enumerate(occ):
-        for j in occ[ii + 1:]:
-            for aa, a in enumerate(vir):
-                for b in vir[aa + 1:]:
-                    if sorted((spin(i), spin(j))) == sorted((spin(a), spin(b))):
-                        doubles.append(string((i, j, a, b)))
-    rng = np.random.default_rng(seed)
-    doubles = [doubles[k] for k in rng.permutation(len(doubles))]
-    rows = (singles + doubles)[:count]
+        rows.append(s)
     return np.array(rows, dtype=np.uint8).reshape(len(rows), n)
+
+
+def excitation_masks(n_orb, n_alpha, n_beta, count, seed=7):
+    """The strings of ``excitation_generators`` as (x, z) uint64 masks (bit k
+    = qubit k), the form the library's rotation ansatz takes: x has every
+    qubit of the excitation, z the lowest one (the Y) and the qubits strictly
+    inside each consecutive pair."""
+    xs, zs = [], []
+    for qs in _excitation_qubits(n_orb, n_alpha, n_beta, count, seed):
+        xm = 0
+        for q in qs:
+            xm |= 1 << q
+        zm = 1 << qs[0]
+        for a, b in zip(qs[0::2], qs[1::2]):
+            zm |= ((1 << b) - 1) & ~((1 << (a + 1)) - 1)
+        xs.append(xm)
+        zs.append(zm)
+    x = np.array(xs, dtype=np.uint64)
+    return x, np.array(zs, dtype=np.uint64)
 
 
 def mlp_init(hidden, n_out, seed):

@@ -33,7 +33,7 @@ def test_minimize_reaches_a_confirmed_stationary_point(dev, dtype):
     h1, h2 = synth.pes_integrals(n_orb, 0.4)
     G = api.jw_transform(torch.from_numpy(h1).to(dev), torch.from_numpy(h2).to(dev)).group()
     gens = synth.excitation_generators(n_orb, na, nb, 40)
-    x, z = pes.letters_to_masks(gens)
+    x, z = synth.excitation_masks(n_orb, na, nb, 40)
     ref = _ref(n_orb, na, nb)
     v = api.VQE(G, n_orb, x, z, ref, dtype=dtype)
     g_tol = 1e-6 if dtype == torch.complex128 else 2e-3
@@ -51,9 +51,9 @@ def test_minimize_reaches_a_confirmed_stationary_point(dev, dtype):
 
 def _scan(dev, n_orb, na, nb, n_rot, n_geo, **kw):
     api, pes = _mods()
-    gens = synth.excitation_generators(n_orb, na, nb, n_rot)
-    return pes.scan(lambda r: synth.pes_integrals(n_orb, r), np.linspace(0, 1, n_geo), n_orb, gens,
-                    _ref(n_orb, na, nb), mlp_params=synth.mlp_init(256, len(gens), seed=2), **kw)
+    x, z = synth.excitation_masks(n_orb, na, nb, n_rot)
+    return pes.scan(lambda r: synth.pes_integrals(n_orb, r), np.linspace(0, 1, n_geo), n_orb, x, z,
+                    _ref(n_orb, na, nb), mlp_params=synth.mlp_init(256, len(x), seed=2), **kw)
 
 
 def test_warm_start_saves_iterations_at_equal_energy(dev):
@@ -80,10 +80,10 @@ def test_untrained_network_falls_back_to_cold_start(dev):
 def test_poor_prediction_falls_back_to_cold_start(dev):
     api, pes = _mods()
     n_orb, na, nb = 4, 2, 2
-    gens = synth.excitation_generators(n_orb, na, nb, 26)
-    p = synth.mlp_init(256, len(gens), seed=3)
-    p[-len(gens):] = 2.0  # output bias: every angle near 2 rad, far from the minimum
-    recs = pes.scan(lambda r: synth.pes_integrals(n_orb, r), [0.0, 0.5], n_orb, gens, _ref(n_orb, na, nb),
+    x, z = synth.excitation_masks(n_orb, na, nb, 26)
+    p = synth.mlp_init(256, len(x), seed=3)
+    p[-len(x):] = 2.0  # output bias: every angle near 2 rad, far from the minimum
+    recs = pes.scan(lambda r: synth.pes_integrals(n_orb, r), [0.0, 0.5], n_orb, x, z, _ref(n_orb, na, nb),
                     mlp_params=p, train_steps=0)
     assert recs[1]["start"] == "cold"
     assert recs[1]["E_warm"] == recs[1]["E_cold"]

@@ -141,14 +141,13 @@ def test_vqe_28_qubit_full_space_against_sparse_oracle(dev, dtype, molecular_28q
     # maximum size: 2^28 amplitudes per vector, all 225 sector blocks; three
     # rotations keep the exact state on at most 8 basis states, where the
     # oracle evaluates energy and gradient from matrix elements
-    from paper_2606_28952_amd import pes
-
     api = _api()
     h1, h2, op = molecular_28q
     n_orb = 14
     G = api.jw_transform(torch.from_numpy(h1).to(dev), torch.from_numpy(h2).to(dev)).group()
-    gens = synth.excitation_generators(n_orb, 7, 7, 400)[[3, 150, 390]]
-    x, z = pes.letters_to_masks(gens)
+    pick = [3, 150, 390]
+    gens = synth.excitation_generators(n_orb, 7, 7, 400)[pick]
+    x, z = (m[pick] for m in synth.excitation_masks(n_orb, 7, 7, 400))
     ref = 127 | (127 << n_orb)
     theta = np.array([0.3, -0.7, 1.1])
     v = api.VQE(G, n_orb, x, z, ref, dtype=dtype)
@@ -190,15 +189,13 @@ def test_vqe_schedule_tuning_keeps_results(dev):
 def test_vqe_fusion_depths_agree(dev, dtype):
     # every (forward, adjoint) fusion depth gives the oracle's energy and
     # gradient; in complex128 the state, hence the energy, is bit-identical
-    from paper_2606_28952_amd import pes
-
     api = _api()
     n_orb = 5
     h1, h2 = synth.molecular_spin_integrals(n_orb, seed=81)
     G = api.jw_transform(torch.from_numpy(h1).to(dev), torch.from_numpy(h2).to(dev)).group()
     op = ojw.jw_sum(h1, h2)
     gens = synth.excitation_generators(n_orb, 3, 2, 17)
-    x, z = pes.letters_to_masks(gens)
+    x, z = synth.excitation_masks(n_orb, 3, 2, 17)
     ref = 0b00111 | (0b00011 << n_orb)
     theta = np.random.default_rng(82).normal(size=len(gens)) * 0.4
     want_e = ovqe.energy(op, gens, theta, ref)

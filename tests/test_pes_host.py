@@ -1,5 +1,6 @@
-"""Host logic of the scan driver (no GPU): letter strings to X/Z masks
-against the oracle's independent conversion, and the scan summary."""
+"""Host logic of the scan driver (no GPU): the rotation generators' X/Z
+masks against the oracle's independent conversion of their letter form, and
+the scan summary."""
 
 import numpy as np
 import pytest
@@ -9,16 +10,14 @@ from oracle import pauli as opauli
 from paper_2606_28952_amd import pes
 
 
-def test_letters_to_masks_matches_oracle():
-    rng = np.random.default_rng(0)
-    for n in (1, 7, 24, 64):
-        letters = rng.integers(0, 4, size=(50, n)).astype(np.uint8)
-        x, z = pes.letters_to_masks(letters)
-        xo, zo = opauli.letters_to_xz(letters)
-        np.testing.assert_array_equal(x, xo[:, 0])
-        np.testing.assert_array_equal(z, zo[:, 0])
-    with pytest.raises(ValueError):
-        pes.letters_to_masks(np.zeros((1, 65), np.uint8))
+@pytest.mark.parametrize("n_orb,na,nb,count", [(6, 3, 3, 200), (3, 2, 1, 40), (12, 6, 6, 200), (14, 7, 7, 400)])
+def test_excitation_masks_match_letters(n_orb, na, nb, count):
+    letters = synth.excitation_generators(n_orb, na, nb, count)
+    x, z = synth.excitation_masks(n_orb, na, nb, count)
+    xo, zo = opauli.letters_to_xz(letters)
+    assert x.dtype == np.uint64 and z.dtype == np.uint64
+    np.testing.assert_array_equal(x, xo[:, 0])
+    np.testing.assert_array_equal(z, zo[:, 0])
 
 
 def test_excitation_generators_are_hermitian_imaginary_strings():
@@ -26,8 +25,14 @@ def test_excitation_generators_are_hermitian_imaginary_strings():
     gens = synth.excitation_generators(6, 3, 3, 200)
     assert len(gens) == 9 + 9 + 9 + 9 + 81  # singles, then same-spin and opposite-spin doubles
     assert all(int((g == 2).sum()) == 1 for g in gens)
-    x, _ = pes.letters_to_masks(gens)
+    x, z = synth.excitation_masks(6, 3, 3, 200)
     assert len(set(x.tolist())) == len(x)  # distinct qubit sets
+    assert all(bin(int(a) & int(b)).count("1") == 1 for a, b in zip(x, z))  # one Y each
+
+
+def test_scan_rejects_mismatched_masks():
+    with pytest.raises(ValueError):
+        pes.scan(None, [], 2, np.zeros(3, np.uint64), np.zeros(2, np.uint64), 0)
 
 
 def test_summary_totals():
