@@ -180,10 +180,13 @@ def test_tuner_keeps_the_fastest_schedule(dev):
 def test_config3_batch_of_64_uneven_sectors(dev):
     """The 64-job batch at its full sizes (n_orb 10 to 13, 20 to 26 qubits,
     D from 30,240 to 2,944,656, each job its own operator), complex64
-    storage, in one launch with energies.  Every job equals its single
-    launch bit for bit; six 13-orbital jobs (every electron count and both
-    S_z values among them) are checked on 8 whole rows against the oracle's
-    C twin, and four 10-orbital jobs on the whole vector and the energy."""
+    storage, in one launch with energies: unfactored with the default
+    schedule, then with the spin-factorized tables of every job in a
+    persistent launch (the configuration the benchmark times).  Every job
+    equals its single launch bit for bit; six 13-orbital jobs (every electron
+    count and both S_z values among them) are checked on 8 whole rows against
+    the oracle's C twin, and four 10-orbital jobs on the whole vector and the
+    energy."""
     from oracle import native
 
     api = _api()
@@ -198,28 +201,41 @@ def test_config3_batch_of_64_uneven_sectors(dev):
         jobs.append((G, sp, t, torch.empty_like(t)))
         inputs.append((h1, h2, psi32))
     print(f"[batch64] {len(jobs)} jobs, {sum(j[1].dim for j in jobs)} amplitudes", flush=True)
-    batch = api.Batch(jobs)
-    energies = torch.zeros(3 * len(jobs), dtype=torch.float64, device=dev)
-    batch.run(energies)
-    torch.cuda.synchronize()
-    e = energies.cpu().numpy().reshape(-1, 3)
-    for k, (G, sp, t, out) in enumerate(jobs):
-        single = api.apply_pauli_sum(G, sp, t)
-        assert torch.equal(torch.view_as_real(single), torch.view_as_real(out)), f"job {k}"
+    row_refs, vec_refs = {}, {}
     for k in (3, 7, 11, 15, 19, 63):          # n_orb = 13
         n_o, na, nb, _, _ = specs[k]
         h1, h2, psi32 = inputs[k]
         osp = ospace.SectorSpace(n_o, na, nb)
         rows = np.random.default_rng(k).choice(osp.dim_alpha, 8, replace=False)
         tgt = (rows[:, None] * osp.dim_beta + np.arange(osp.dim_beta)[None, :]).reshape(-1)
-        ref, _ = native.apply_targets(ojw.jw_sum(h1, h2), osp, psi32, tgt)
-        got = jobs[k][3][torch.from_numpy(tgt).to(dev)].cpu().numpy().astype(np.complex128)
-        assert rel_err(got, ref) < 1e-6, f"job {k}"
+        row_refs[k] = (torch.from_numpy(tgt).to(dev), native.apply_targets(ojw.jw_sum(h1, h2), osp, psi32, tgt)[0])
     for k in (0, 20, 40, 60):                 # n_orb = 10
         n_o, na, nb, _, _ = specs[k]
         h1, h2, psi32 = inputs[k]
-        osp = ospace.SectorSpace(n_o, na, nb)
-        ref, _ = native.apply_scatter(ojw.jw_sum(h1, h2), osp, psi32)
-        assert rel_err(jobs[k][3].cpu().numpy().astype(np.complex128), ref) < 1e-6, f"job {k}"
-        e_ref = np.vdot(psi32.astype(np.complex128), ref)
-        assert abs(e[k, 0] - e_ref.real) < 1e-8, f"job {k}"
+        ref, _ = native.apply_scatter(ojw.jw_sum(h1, h2), ospace.SectorSpace(n_o, na, nb), psi32)
+        vec_refs[k] = (ref, np.vdot(psi32.astype(np.complex128), ref).real)
+
+    def check(batch, label):
+        energies = torch.zeros(3 * len(jobs), dtype=torch.float64, device=dev)
+        for _, _, _, out in jobs:
+            out.zero_()
+        batch.run(energies)
+        torch.cuda.synchronize()
+        e = energies.cpu().numpy().reshape(-1, 3)
+        for k, (G, sp, t, out) in enumerate(jobs):
+            single = api.apply_pauli_sum(G, sp, t)
+            assert torch.equal(torch.view_as_real(single), torch.view_as_real(out)), f"{label} job {k}"
+        for k, (tsel, ref) in row_refs.items():
+            got = jobs[k][3][tsel].cpu().numpy().astype(np.complex128)
+            assert rel_err(got, ref) < 1e-6, f"{label} job {k}"
+        for k, (ref, e_ref) in vec_refs.items():
+            assert rel_err(jobs[k][3].cpu().numpy().astype(np.complex128), ref) < 1e-6, f"{label} job {k}"
+            assert abs(e[k, 0] - e_ref) < 1e-8, f"{label} job {k}"
+
+    check(api.Batch(jobs), "unfactored")
+    print("[batch64] factored, persistent", flush=True)
+    for G, sp, _, _ in jobs:
+        G.factor(sp)
+    batch = api.Batch(jobs)
+    batch.set_config(128)  # PBS_BATCH_PERSISTENT
+    check(batch, "factored persistent")
