@@ -217,6 +217,35 @@ def bench_batched(args):
     tuned_config, tuned_ms = batch.tune(reps=3)
     t_batch = time_batch()
 
+    def time_graph(config):
+        # the batch (under `config`) captured once in a HIP graph and replayed;
+        # the replay must reproduce the eager outputs and energies exactly
+        batch.set_config(config)
+        batch.run(energies)
+        torch.cuda.synchronize()
+        eager = [torch.view_as_real(j[3]).clone() for j in jobs32] + [energies.clone()]
+        graph, stream = torch.cuda.CUDAGraph(), torch.cuda.Stream()
+        with torch.cuda.stream(stream):
+            with torch.cuda.graph(graph, stream=stream):
+                batch.run(energies)
+        torch.cuda.synchronize()
+        for _ in range(args.warmup):
+            graph.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            graph.replay()
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / args.steps
+        same = all(torch.equal(torch.view_as_real(j[3]), e) for j, e in zip(jobs32, eager)) and \
+            torch.equal(energies, eager[-1])
+        del graph
+        return t, same
+
+    t_graph, graph_same = time_graph(tuned_config)
+    t_graph_persistent, graph_same_p = time_graph(128)
+    batch.set_config(tuned_config)
+
     def per_job():
         for G, sp, psi, out in jobs64:
             api.apply_pauli_sum(G, sp, psi, out=out)
@@ -252,6 +281,8 @@ def bench_batched(args):
                    "dims": [j[1].dim for j in jobs32], "factored": not args.no_factor},
         "ms_default_schedule": t_default * 1e3, "ms_persistent_schedule": t_persistent * 1e3,
         "tuned_schedule": tuned_config, "tuner_ms_per_run": tuned_ms, "work_items": batch.info()[2],
+        "ms_graph_replay_tuned": t_graph * 1e3, "ms_graph_replay_persistent": t_graph_persistent * 1e3,
+        "graph_replay_equals_eager": bool(graph_same and graph_same_p),
         "ms_per_job_fp64_launches": t_single * 1e3,
         "ms_per_job_fp64_launches_unfactored": t_single_plain * 1e3,
         "speedup_batched_c64_vs_per_job_fp64": t_single / t_batch,

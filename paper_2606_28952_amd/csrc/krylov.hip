@@ -5,8 +5,8 @@
 //
 // Device work per Lanczos vector: one operator-state product (the sector or
 // full-space apply), two passes of classical Gram-Schmidt against all
-// previous vectors as fused multi-dot / multi-axpy kernels, a norm and a
-// scale.  Inner products accumulate in float64 with a fixed-order two-stage
+// previous vectors (a multi-dot, then two multi-axpy sweeps that also return
+// the next pass's projections and the norm), and a scale.  Inner products accumulate in float64 with a fixed-order two-stage
 // reduction (deterministic).  The k x k tridiagonal matrix (k <= 16) is
 // diagonalised on the host by cyclic Jacobi rotations and exp(-i T dt) e_1
 // combines the basis vectors on the device.
@@ -30,6 +30,8 @@ template <>
 struct KAmp<double2> {
   __device__ static inline double2 ld(const double2* p, uint64_t i) { return p[i]; }
   __device__ static inline void st(double2* p, uint64_t i, double r, double m) { p[i] = make_double2(r, m); }
+  // the value st() stores, read back as float64
+  __device__ static inline double2 stored(double r, double m) { return make_double2(r, m); }
 };
 template <>
 struct KAmp<float2> {
@@ -39,6 +41,9 @@ struct KAmp<float2> {
   }
   __device__ static inline void st(float2* p, uint64_t i, double r, double m) {
     p[i] = make_float2(static_cast<float>(r), static_cast<float>(m));
+  }
+  __device__ static inline double2 stored(double r, double m) {
+    return make_double2(static_cast<float>(r), static_cast<float>(m));
   }
 };
 
@@ -131,6 +136,73 @@ __global__ __launch_bounds__(kKB) void k_multiaxpy(uint64_t n, int nv, const T* 
   }
 }
 
+// Fused Gram-Schmidt pass: y <- y + sum_i c_i x_i, and from the same sweep
+// over the elements the block partials that k_multidot would write for the
+// updated y as stored: with NORM = false the inner products conj(x_i) y of
+// the same x_i (the next pass's projections), with NORM = true |y|^2 (as
+// k_multidot(y, y)).  Each thread visits the same elements in the same order
+// as in k_multidot, so the partials, hence the reduced values, are those of
+// the unfused sequence bit for bit; the x_i are read once instead of twice.
+template <class T, bool NORM>
+__global__ __launch_bounds__(kKB) void k_multiaxpy_dot(uint64_t n, int nv, const T* __restrict__ xbase, uint64_t stride,
+                                                       Coeffs c, T* __restrict__ y, double* __restrict__ partial) {
+  constexpr int kD = NORM ? 1 : kMaxK;
+  double ar[kD], ai[kD];
+#pragma unroll
+  for (int i = 0; i < kD; ++i) ar[i] = ai[i] = 0.0;
+  for (uint64_t t = blockIdx.x * static_cast<uint64_t>(kKB) + threadIdx.x; t < n;
+       t += static_cast<uint64_t>(gridDim.x) * kKB) {
+    const double2 w0 = KAmp<T>::ld(y, t);
+    double r = w0.x, m = w0.y;
+    double2 v[kMaxK];
+#pragma unroll
+    for (int i = 0; i < kMaxK; ++i) {
+      if (i < nv) {
+        v[i] = KAmp<T>::ld(xbase + i * stride, t);
+        r = fma(c.re[i], v[i].x, fma(-c.im[i], v[i].y, r));
+        m = fma(c.re[i], v[i].y, fma(c.im[i], v[i].x, m));
+      }
+    }
+    KAmp<T>::st(y, t, r, m);
+    const double2 w = KAmp<T>::stored(r, m);
+    if (NORM) {
+      ar[0] = fma(w.x, w.x, fma(w.y, w.y, ar[0]));
+      ai[0] = fma(w.x, w.y, fma(-w.y, w.x, ai[0]));
+    } else {
+#pragma unroll
+      for (int i = 0; i < kD; ++i) {
+        if (i < nv) {
+          ar[i] = fma(v[i].x, w.x, fma(v[i].y, w.y, ar[i]));
+          ai[i] = fma(v[i].x, w.y, fma(-v[i].y, w.x, ai[i]));
+        }
+      }
+    }
+  }
+  const int nd = NORM ? 1 : nv;
+  __shared__ double red[2 * kMaxK][kKB / 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < kD; ++i) {
+    if (i < nd) {
+      double a = ar[i], b = ai[i];
+      for (int d = 32; d > 0; d >>= 1) {
+        a += __shfl_xor(a, d, 64);
+        b += __shfl_xor(b, d, 64);
+      }
+      if (lane == 0) {
+        red[2 * i][wave] = a;
+        red[2 * i + 1][wave] = b;
+      }
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < 2 * nd) {
+    double sum = 0.0;
+    for (int w = 0; w < kKB / 64; ++w) sum += red[threadIdx.x][w];
+    partial[static_cast<uint64_t>(blockIdx.x) * 2 * nd + threadIdx.x] = sum;
+  }
+}
+
 template <class T>
 __global__ __launch_bounds__(kKB) void k_scale_copy(uint64_t n, const T* __restrict__ x, double s, T* __restrict__ y) {
   for (uint64_t t = blockIdx.x * static_cast<uint64_t>(kKB) + threadIdx.x; t < n;
@@ -212,6 +284,25 @@ class Lanczos {
     PBS_HIP(hipMemcpyAsync(host, dots_, 2 * nv * sizeof(double), hipMemcpyDeviceToHost, s_));
     PBS_HIP(hipStreamSynchronize(s_));
   }
+  // y <- y + sum_i c_i x_i, then (host) sum_i conj(x_i) y, or |y|^2 with norm
+  void axpy_dots(const T* xbase, int nv, const double* cre, const double* cim, T* y, bool norm, double* host) {
+    Coeffs c{};
+    for (int i = 0; i < nv; ++i) {
+      c.re[i] = cre[i];
+      c.im[i] = cim[i];
+    }
+    if (norm)
+      hipLaunchKernelGGL((k_multiaxpy_dot<T, true>), dim3(grid_), dim3(kKB), 0, s_, n_, nv, xbase, stride_elems(), c,
+                         y, partial_);
+    else
+      hipLaunchKernelGGL((k_multiaxpy_dot<T, false>), dim3(grid_), dim3(kKB), 0, s_, n_, nv, xbase, stride_elems(),
+                         c, y, partial_);
+    const int nd = norm ? 1 : nv;
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kKB), 0, s_, partial_, static_cast<int>(grid_), 2 * nd, dots_);
+    PBS_HIP(hipGetLastError());
+    PBS_HIP(hipMemcpyAsync(host, dots_, 2 * nd * sizeof(double), hipMemcpyDeviceToHost, s_));
+    PBS_HIP(hipStreamSynchronize(s_));
+  }
   void axpy(const T* xbase, int nv, const double* cre, const double* cim, double y_scale, T* y) {
     Coeffs c{};
     for (int i = 0; i < nv; ++i) {
@@ -248,15 +339,15 @@ class Lanczos {
         nre[i] = -d[2 * i];
         nim[i] = -d[2 * i + 1];
       }
-      axpy(vec(0), static_cast<int>(j + 1), nre, nim, 1.0, W_);
-      // second pass (re-orthogonalisation)
-      dots(vec(0), static_cast<int>(j + 1), W_, d);
+      // subtract them, and in the same sweep the second pass's projections
+      // (re-orthogonalisation)
+      axpy_dots(vec(0), static_cast<int>(j + 1), nre, nim, W_, false, d);
       for (uint32_t i = 0; i <= j; ++i) {
         nre[i] = -d[2 * i];
         nim[i] = -d[2 * i + 1];
       }
-      axpy(vec(0), static_cast<int>(j + 1), nre, nim, 1.0, W_);
-      dots(W_, 1, W_, d);
+      // subtract those, and in the same sweep |w|^2
+      axpy_dots(vec(0), static_cast<int>(j + 1), nre, nim, W_, true, d);
       const double b = std::sqrt(std::max(d[0], 0.0));
       last_b = b;
       scale = std::max(scale, std::max(std::fabs(alpha.back()), b));
