@@ -22,7 +22,7 @@ namespace {
 
 constexpr int kKB = 256;
 constexpr int kMaxK = 16;
-constexpr unsigned kKGrid = 1024;
+constexpr unsigned kKGrid = 4096;  // up to 16 waves per SIMD for the streaming kernels
 
 template <class T>
 struct KAmp;
@@ -52,47 +52,53 @@ struct Coeffs {
   double im[kMaxK];
 };
 
-// partial[b * 2 * nv + 2i + {0,1}] = sum over block b's elements of conj(x_i) * y
-template <class T>
-__global__ __launch_bounds__(kKB) void k_multidot(uint64_t n, int nv, const T* __restrict__ xbase, uint64_t stride,
-                                                  const T* __restrict__ y, double* __restrict__ partial) {
-  double ar[kMaxK], ai[kMaxK];
+// Block partials of ND complex sums held by every thread (ar, ai):
+// partial[b * 2 * ND + 2i + {0,1}], wave shuffles then a fixed-order sum over
+// the block's waves.
+template <int ND>
+__device__ inline void block_partials(const double (&ar)[ND], const double (&ai)[ND], double* __restrict__ partial) {
+  __shared__ double red[2 * ND][kKB / 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-  for (int i = 0; i < kMaxK; ++i) ar[i] = ai[i] = 0.0;
+  for (int i = 0; i < ND; ++i) {
+    double a = ar[i], b = ai[i];
+    for (int d = 32; d > 0; d >>= 1) {
+      a += __shfl_xor(a, d, 64);
+      b += __shfl_xor(b, d, 64);
+    }
+    if (lane == 0) {
+      red[2 * i][wave] = a;
+      red[2 * i + 1][wave] = b;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < 2 * ND) {
+    double s = 0.0;
+    for (int w = 0; w < kKB / 64; ++w) s += red[threadIdx.x][w];
+    partial[static_cast<uint64_t>(blockIdx.x) * 2 * ND + threadIdx.x] = s;
+  }
+}
+
+// partial[b * 2 * NV + 2i + {0,1}] = sum over block b's elements of conj(x_i) * y.
+// The vector count is a template argument so that the kernel holds exactly
+// NV accumulator pairs (registers, hence resident waves, follow NV).
+template <class T, int NV>
+__global__ __launch_bounds__(kKB) void k_multidot(uint64_t n, const T* __restrict__ xbase, uint64_t stride,
+                                                  const T* __restrict__ y, double* __restrict__ partial) {
+  double ar[NV], ai[NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) ar[i] = ai[i] = 0.0;
   for (uint64_t t = blockIdx.x * static_cast<uint64_t>(kKB) + threadIdx.x; t < n;
        t += static_cast<uint64_t>(gridDim.x) * kKB) {
     const double2 w = KAmp<T>::ld(y, t);
 #pragma unroll
-    for (int i = 0; i < kMaxK; ++i) {
-      if (i < nv) {
-        const double2 v = KAmp<T>::ld(xbase + i * stride, t);
-        ar[i] = fma(v.x, w.x, fma(v.y, w.y, ar[i]));
-        ai[i] = fma(v.x, w.y, fma(-v.y, w.x, ai[i]));
-      }
+    for (int i = 0; i < NV; ++i) {
+      const double2 v = KAmp<T>::ld(xbase + i * stride, t);
+      ar[i] = fma(v.x, w.x, fma(v.y, w.y, ar[i]));
+      ai[i] = fma(v.x, w.y, fma(-v.y, w.x, ai[i]));
     }
   }
-  __shared__ double red[2 * kMaxK][kKB / 64];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-  for (int i = 0; i < kMaxK; ++i) {
-    if (i < nv) {
-      double a = ar[i], b = ai[i];
-      for (int d = 32; d > 0; d >>= 1) {
-        a += __shfl_xor(a, d, 64);
-        b += __shfl_xor(b, d, 64);
-      }
-      if (lane == 0) {
-        red[2 * i][wave] = a;
-        red[2 * i + 1][wave] = b;
-      }
-    }
-  }
-  __syncthreads();
-  if (threadIdx.x < 2 * nv) {
-    double s = 0.0;
-    for (int w = 0; w < kKB / 64; ++w) s += red[threadIdx.x][w];
-    partial[static_cast<uint64_t>(blockIdx.x) * 2 * nv + threadIdx.x] = s;
-  }
+  block_partials<NV>(ar, ai, partial);
 }
 
 // out[j] = sum over blocks of partial[b * nvals + j], fixed order.
@@ -141,12 +147,13 @@ __global__ __launch_bounds__(kKB) void k_multiaxpy(uint64_t n, int nv, const T* 
 // updated y as stored: with NORM = false the inner products conj(x_i) y of
 // the same x_i (the next pass's projections), with NORM = true |y|^2 (as
 // k_multidot(y, y)).  Each thread visits the same elements in the same order
-// as in k_multidot, so the partials, hence the reduced values, are those of
-// the unfused sequence bit for bit; the x_i are read once instead of twice.
-template <class T, bool NORM>
-__global__ __launch_bounds__(kKB) void k_multiaxpy_dot(uint64_t n, int nv, const T* __restrict__ xbase, uint64_t stride,
+// as in k_multidot, so the reduced values are those of the unfused sequence
+// bit for bit; y is read and written once instead of read three times and
+// written once.
+template <class T, bool NORM, int NV>
+__global__ __launch_bounds__(kKB) void k_multiaxpy_dot(uint64_t n, const T* __restrict__ xbase, uint64_t stride,
                                                        Coeffs c, T* __restrict__ y, double* __restrict__ partial) {
-  constexpr int kD = NORM ? 1 : kMaxK;
+  constexpr int kD = NORM ? 1 : NV;
   double ar[kD], ai[kD];
 #pragma unroll
   for (int i = 0; i < kD; ++i) ar[i] = ai[i] = 0.0;
@@ -154,14 +161,12 @@ __global__ __launch_bounds__(kKB) void k_multiaxpy_dot(uint64_t n, int nv, const
        t += static_cast<uint64_t>(gridDim.x) * kKB) {
     const double2 w0 = KAmp<T>::ld(y, t);
     double r = w0.x, m = w0.y;
-    double2 v[kMaxK];
+    double2 v[NV];
 #pragma unroll
-    for (int i = 0; i < kMaxK; ++i) {
-      if (i < nv) {
-        v[i] = KAmp<T>::ld(xbase + i * stride, t);
-        r = fma(c.re[i], v[i].x, fma(-c.im[i], v[i].y, r));
-        m = fma(c.re[i], v[i].y, fma(c.im[i], v[i].x, m));
-      }
+    for (int i = 0; i < NV; ++i) {
+      v[i] = KAmp<T>::ld(xbase + i * stride, t);
+      r = fma(c.re[i], v[i].x, fma(-c.im[i], v[i].y, r));
+      m = fma(c.re[i], v[i].y, fma(c.im[i], v[i].x, m));
     }
     KAmp<T>::st(y, t, r, m);
     const double2 w = KAmp<T>::stored(r, m);
@@ -171,37 +176,39 @@ __global__ __launch_bounds__(kKB) void k_multiaxpy_dot(uint64_t n, int nv, const
     } else {
 #pragma unroll
       for (int i = 0; i < kD; ++i) {
-        if (i < nv) {
-          ar[i] = fma(v[i].x, w.x, fma(v[i].y, w.y, ar[i]));
-          ai[i] = fma(v[i].x, w.y, fma(-v[i].y, w.x, ai[i]));
-        }
+        ar[i] = fma(v[i].x, w.x, fma(v[i].y, w.y, ar[i]));
+        ai[i] = fma(v[i].x, w.y, fma(-v[i].y, w.x, ai[i]));
       }
     }
   }
-  const int nd = NORM ? 1 : nv;
-  __shared__ double red[2 * kMaxK][kKB / 64];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-  for (int i = 0; i < kD; ++i) {
-    if (i < nd) {
-      double a = ar[i], b = ai[i];
-      for (int d = 32; d > 0; d >>= 1) {
-        a += __shfl_xor(a, d, 64);
-        b += __shfl_xor(b, d, 64);
-      }
-      if (lane == 0) {
-        red[2 * i][wave] = a;
-        red[2 * i + 1][wave] = b;
-      }
+  block_partials<kD>(ar, ai, partial);
+}
+
+// Launches K<NV> for the runtime count nv in 1..kMaxK.
+template <template <int> class K, int NV = 1, class... A>
+void launch_nv(int nv, dim3 grid, hipStream_t s, A... args) {
+  if constexpr (NV <= kMaxK) {
+    if (nv == NV) {
+      hipLaunchKernelGGL(K<NV>::fn(), grid, dim3(kKB), 0, s, args...);
+      return;
     }
-  }
-  __syncthreads();
-  if (threadIdx.x < 2 * nd) {
-    double sum = 0.0;
-    for (int w = 0; w < kKB / 64; ++w) sum += red[threadIdx.x][w];
-    partial[static_cast<uint64_t>(blockIdx.x) * 2 * nd + threadIdx.x] = sum;
+    launch_nv<K, NV + 1>(nv, grid, s, args...);
   }
 }
+template <class T>
+struct DotK {
+  template <int NV>
+  struct K {
+    static auto fn() { return k_multidot<T, NV>; }
+  };
+};
+template <class T, bool NORM>
+struct AxpyDotK {
+  template <int NV>
+  struct K {
+    static auto fn() { return k_multiaxpy_dot<T, NORM, NV>; }
+  };
+};
 
 template <class T>
 __global__ __launch_bounds__(kKB) void k_scale_copy(uint64_t n, const T* __restrict__ x, double s, T* __restrict__ y) {
@@ -278,7 +285,7 @@ class Lanczos {
 
   // returns sum_i conj(x_i) y for x_0..x_{nv-1} starting at xbase
   void dots(const T* xbase, int nv, const T* y, double* host) {
-    hipLaunchKernelGGL((k_multidot<T>), dim3(grid_), dim3(kKB), 0, s_, n_, nv, xbase, stride_elems(), y, partial_);
+    launch_nv<DotK<T>::template K>(nv, dim3(grid_), s_, n_, xbase, stride_elems(), y, partial_);
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kKB), 0, s_, partial_, static_cast<int>(grid_), 2 * nv, dots_);
     PBS_HIP(hipGetLastError());
     PBS_HIP(hipMemcpyAsync(host, dots_, 2 * nv * sizeof(double), hipMemcpyDeviceToHost, s_));
@@ -292,11 +299,9 @@ class Lanczos {
       c.im[i] = cim[i];
     }
     if (norm)
-      hipLaunchKernelGGL((k_multiaxpy_dot<T, true>), dim3(grid_), dim3(kKB), 0, s_, n_, nv, xbase, stride_elems(), c,
-                         y, partial_);
+      launch_nv<AxpyDotK<T, true>::template K>(nv, dim3(grid_), s_, n_, xbase, stride_elems(), c, y, partial_);
     else
-      hipLaunchKernelGGL((k_multiaxpy_dot<T, false>), dim3(grid_), dim3(kKB), 0, s_, n_, nv, xbase, stride_elems(),
-                         c, y, partial_);
+      launch_nv<AxpyDotK<T, false>::template K>(nv, dim3(grid_), s_, n_, xbase, stride_elems(), c, y, partial_);
     const int nd = norm ? 1 : nv;
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kKB), 0, s_, partial_, static_cast<int>(grid_), 2 * nd, dots_);
     PBS_HIP(hipGetLastError());
