@@ -248,6 +248,14 @@ void upload(DevBuf<T>& d, const std::vector<T>& h) {
   if (!h.empty()) PBS_HIP(hipMemcpy(d.get(), h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
 }
 
+// a temporary of the build, from the call's scratch arena (released without
+// hipFree, which would wait for the whole device)
+template <class T>
+void upload_temp(DevBuf<T>& d, const std::vector<T>& h, hipStream_t s) {
+  d = DevBuf<T>(h.size(), s);
+  if (!h.empty()) PBS_HIP(hipMemcpy(d.get(), h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+}
+
 template <class T>
 std::vector<T> download(const DevBuf<T>& d, size_t n) {
   std::vector<T> h(n);
@@ -406,9 +414,9 @@ void build_plan(pbs_grouped& h, const pbs_space& sp, hipStream_t s) {
   upload(F.cls_f, cls_f);
   DevBuf<uint32_t> d_qlo, d_qzb;
   DevBuf<double> d_qc;
-  upload(d_qlo, q_lo);
-  upload(d_qzb, q_zb);
-  upload(d_qc, q_c);
+  upload_temp(d_qlo, q_lo, s);
+  upload_temp(d_qzb, q_zb, s);
+  upload_temp(d_qc, q_c, s);
 
   if (n_zrows) {
     F.fz.alloc(static_cast<uint64_t>(n_zrows) * db);
@@ -419,8 +427,8 @@ void build_plan(pbs_grouped& h, const pbs_space& sp, hipStream_t s) {
   }
   if (F.c0 != 0xffffffffu) {
     DevBuf<int32_t> d_pk, d_qk;
-    upload(d_pk, pk);
-    upload(d_qk, qk);
+    upload_temp(d_pk, pk, s);
+    upload_temp(d_qk, qk, s);
     F.em.alloc(static_cast<uint64_t>(n_moves) * db);
     F.fp.alloc(static_cast<uint64_t>(n_moves) * F.r2 * db);
     F.eq.alloc(n_qmoves * db);
@@ -448,7 +456,7 @@ void build_plan(pbs_grouped& h, const pbs_space& sp, hipStream_t s) {
     const uint64_t da = sp.dim_alpha;
     if (plain && !simple.empty() && sp.n_orb <= 32) {
       DevBuf<uint32_t> d_simple, cnt(da, s);
-      upload(d_simple, simple);
+      upload_temp(d_simple, simple, s);
       const unsigned grid = static_cast<unsigned>(std::min<uint64_t>(da, 65536));
       hipLaunchKernelGGL(k_alpha_list, dim3(grid), dim3(256), 0, s, 0u, da, sp.n_alpha, sp.str_alpha.get(),
                          d_simple.get(), static_cast<uint32_t>(simple.size()), h.cls_meta.get(), h.u_t0.get(),
@@ -488,7 +496,7 @@ void build_plan(pbs_grouped& h, const pbs_space& sp, hipStream_t s) {
     const uint64_t da = sp.dim_alpha;
     if (!icls.empty()) {
       DevBuf<uint32_t> d_cls, cnt(da, s);
-      upload(d_cls, icls);
+      upload_temp(d_cls, icls, s);
       const unsigned grid = static_cast<unsigned>(std::min<uint64_t>(da, 65536));
       hipLaunchKernelGGL(k_pair_list, dim3(grid), dim3(256), 0, s, 0u, da, sp.n_alpha, sp.str_alpha.get(), d_cls.get(),
                          static_cast<uint32_t>(icls.size()), h.cls_meta.get(), nullptr, cnt.get(), nullptr, nullptr,
@@ -553,6 +561,7 @@ pbs_status pbs_grouped_factor(pbs_grouped* h, const pbs_space* sp, void* stream)
     PBS_REQUIRE(h->has_sector && h->half == sp->n_orb, PBS_ERR_ARG, "operator lacks sector tables for this split");
     PBS_REQUIRE(h->real_coef, PBS_ERR_UNSUPPORTED, "factored evaluation needs real sector-form coefficients");
     h->fplan.reset();
+    Scratch scratch(as_stream(stream));  // temporaries of this call
     build_plan(*h, *sp, as_stream(stream));
   });
 }
