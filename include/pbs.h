@@ -254,7 +254,9 @@ pbs_status pbs_expval_noalloc(const pbs_grouped* h, const pbs_space* sp, pbs_dty
  * are at most 2).  On the alpha side (Eq. precomp_alpha) it lists, for every
  * alpha string of sp's N_alpha, the simple classes (one X_beta = 0 group
  * with beta Z-masks 0) whose source lies in the sector, with their folded
- * coefficients.  The tables are attached to h (replacing earlier ones);
+ * coefficients, and the images of the classes whose pair groups have one
+ * unique each (the folded coefficient per orbital pair and the class's
+ * X_beta = 0 factors).  The tables are attached to h (replacing earlier ones);
  * afterwards pbs_apply_pauli_sum, pbs_expval and batch jobs on sectors with
  * the same (n_orb, N_beta), respectively (n_orb, N_alpha) for the alpha
  * lists, use them (results equal the unfactored evaluation up to rounding).
