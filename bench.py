@@ -553,8 +553,12 @@ def main():
         return (t1 - t0) * 1e3 / args.steps, float(np.mean([a.elapsed_time(b) for a, b in evs]))
 
     ms_step_serial, apply_ms_serial = timed(False)
+    energy_serial = res.cpu().numpy()
     ms_step, apply_ms = timed(True)
     energy = res.cpu().numpy()
+    # every step builds and applies the same operator to the same state, and
+    # the kernels are deterministic: both loops must end on the same bits
+    pipelined_equals_serial = bool(np.array_equal(energy, energy_serial))
 
     # FP64 plain (complex128 storage) vs complex64 storage, apply kernel only
     _, G, sp = build()
@@ -630,6 +634,7 @@ def main():
         "warmup": args.warmup,
         "ms_per_step": ms_step,
         "ms_per_step_serial": ms_step_serial,
+        "pipelined_equals_serial": pipelined_equals_serial,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
