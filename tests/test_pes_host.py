@@ -1,4 +1,4 @@
-"""Host logic of the scan driver (no GPU): the rotation generators' X/Z
+"""Host logic of the scan module (no GPU): the rotation generators' X/Z
 masks against the oracle's independent conversion of their letter form, and
 the scan summary."""
 
