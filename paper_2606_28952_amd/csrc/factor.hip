@@ -208,35 +208,40 @@ __global__ __launch_bounds__(256) void k_pair_list(uint32_t pass, uint64_t da, u
   }
 }
 
-// Images: one thread per (entry, slot j < n_img): the folded coefficient of
-// the class's pair group on orbital pair j, 0 for slot n_pairs, then the
-// X_beta = 0 group's folded factors.
-__global__ void k_pair_images(uint64_t n_ent, uint32_t n_img, uint32_t n_pairs, const uint32_t* str_a,
-                              const uint32_t* ent_cls, const uint32_t* ent_row, const ClassMeta* meta,
-                              const int32_t* pmap, const uint32_t* pg_u0, const uint32_t* u_t0, const uint32_t* pt_za,
-                              const double* pt_c, const uint4* cls_f, const uint32_t* fu_t0, const uint32_t* ft_za,
-                              const double* ft_c, double* img) {
-  const uint64_t n = n_ent * n_img;
-  for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < n;
-       i += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
-    const uint64_t e = i / n_img;
-    const uint32_t j = static_cast<uint32_t>(i % n_img);
-    const uint32_t c = ent_cls[e], ta = str_a[ent_row[e]];
+// Images: one workgroup per entry (an alpha row and one of its image
+// classes), one thread per slot j < n_img: the folded coefficient of the
+// class's pair group on orbital pair j, 0 for slot n_pairs, then the
+// X_beta = 0 group's folded factors.  The entry's class, row and class
+// record are uniform across the workgroup; the pair-map row is read
+// coalesced.
+constexpr uint32_t kImgBlock = 128;
+__global__ __launch_bounds__(kImgBlock) void k_pair_images(uint32_t n_img, uint32_t n_pairs, const uint32_t* str_a,
+                                                           const uint32_t* ent_cls, const uint32_t* ent_row,
+                                                           const ClassMeta* meta, const int32_t* pmap,
+                                                           const uint32_t* pg_u0, const uint32_t* u_t0,
+                                                           const uint32_t* pt_za, const double* pt_c,
+                                                           const uint4* cls_f, const uint32_t* fu_t0,
+                                                           const uint32_t* ft_za, const double* ft_c, double* img) {
+  const uint64_t e = blockIdx.x;
+  const uint32_t c = ent_cls[e], ta = str_a[ent_row[e]];
+  const int32_t* prow = pmap + static_cast<uint64_t>(meta[c].pm) * n_pairs;
+  const uint4 cf = cls_f[c];
+  for (uint32_t j = threadIdx.x; j < n_img; j += kImgBlock) {
     double f = 0.0;
     if (j < n_pairs) {
-      const int32_t g = pmap[static_cast<uint64_t>(meta[c].pm) * n_pairs + j];
+      const int32_t g = prow[j];
       if (g >= 0) {
         const uint32_t u = pg_u0[g];
         for (uint32_t t = u_t0[u]; t < u_t0[u + 1]; ++t) f += (__popc(pt_za[t] & ta) & 1u) ? -pt_c[2 * t] : pt_c[2 * t];
       }
     } else if (j > n_pairs) {
       const uint32_t r = j - n_pairs - 1;
-      if (r < cls_f[c].y) {
-        const uint32_t u = cls_f[c].x + r;
+      if (r < cf.y) {
+        const uint32_t u = cf.x + r;
         for (uint32_t t = fu_t0[u]; t < fu_t0[u + 1]; ++t) f += (__popc(ft_za[t] & ta) & 1u) ? -ft_c[t] : ft_c[t];
       }
     }
-    img[i] = f;
+    img[e * n_img + j] = f;
   }
 }
 
@@ -516,8 +521,8 @@ void build_plan(pbs_grouped& h, const pbs_space& sp, hipStream_t s) {
         hipLaunchKernelGGL(k_pair_list, dim3(grid), dim3(256), 0, s, 1u, da, sp.n_alpha, sp.str_alpha.get(),
                            d_cls.get(), static_cast<uint32_t>(icls.size()), h.cls_meta.get(), F.plist_off.get(),
                            nullptr, F.plist_src.get(), F.plist_cls.get(), ent_row.get());
-        const uint64_t ni = n_ent * F.n_img;
-        hipLaunchKernelGGL(k_pair_images, dim3(grid_for(ni, 256, 65536)), dim3(256), 0, s, n_ent, F.n_img,
+        PBS_REQUIRE(n_ent < (1ull << 31), PBS_ERR_RANGE, "more than 2^31 alpha-image entries");
+        hipLaunchKernelGGL(k_pair_images, dim3(static_cast<unsigned>(n_ent)), dim3(kImgBlock), 0, s, F.n_img,
                            h.n_pairs, sp.str_alpha.get(), F.plist_cls.get(), ent_row.get(), h.cls_meta.get(),
                            h.pmap.get(), h.pg_u0.get(), h.u_t0.get(), h.pt_za.get(), h.pt_c.get(), F.cls_f.get(),
                            F.fu_t0.get(), F.ft_za.get(), F.ft_c.get(), F.pimg.get());

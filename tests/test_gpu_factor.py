@@ -138,3 +138,18 @@ def test_rows_kernel_hubbard_long_rows(dev):
     assert abs(e[0] - e_ref.real) < 1e-12 * max(1.0, abs(e_ref))
     assert abs(e[2] - 1.0) < 1e-13
     assert torch.equal(torch.view_as_real(api.apply_pauli_sum(G, sp, psi)), torch.view_as_real(out))
+    # the energy alone (no stored product) and the fixed-workspace entry point
+    # give the same bits
+    assert np.array_equal(api.expval(G, sp, psi).cpu().numpy(), e)
+    res = torch.empty(3, dtype=torch.float64, device=dev)
+    assert np.array_equal(api.expval_noalloc(G, sp, psi, res).cpu().numpy(), e)
+    # complex64 storage: against the oracle on the same FP32-rounded input
+    psi32_np = psi_np.astype(np.complex64)
+    ref32 = oapply.apply_scatter(ojw.jw_sum(h1, h2), ospace.SectorSpace(n_o, na, nb), psi32_np.astype(np.complex128))
+    psi32 = torch.from_numpy(psi32_np).to(dev)
+    out32 = torch.empty_like(psi32)
+    e32 = api.expval(G, sp, psi32, out=out32).cpu().numpy()
+    assert rel_err(out32.cpu().numpy().astype(np.complex128), ref32) < 1e-6
+    e32_ref = np.vdot(psi32_np.astype(np.complex128), ref32)
+    assert abs(e32[0] - e32_ref.real) < 1e-12 * max(1.0, abs(e32_ref))
+    assert torch.equal(torch.view_as_real(api.apply_pauli_sum(G, sp, psi32)), torch.view_as_real(out32))
