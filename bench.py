@@ -137,7 +137,9 @@ def cpu_baseline(h1, h2, n_orb, n_alpha, n_beta, psi, target_s=3.0):
     applied to all configurations of K whole source rows (alpha strings),
     scattered into the full output.  One warm-up, then the median of three
     runs, on all the threads OpenMP is given and on one thread; K is sized
-    so that each run takes about target_s seconds."""
+    from the marginal cost of a row (two probes, so that the fixed cost of a
+    call -- per-thread output partials and their sum -- does not count as
+    row work) so that each run takes about target_s seconds."""
     from oracle import jw as ojw
     from oracle import native
     from oracle import space as ospace
@@ -161,8 +163,12 @@ def cpu_baseline(h1, h2, n_orb, n_alpha, n_beta, psi, target_s=3.0):
 
     res = {}
     for name, threads in (("all", 0), ("one", 1)):
-        dt, used = timed(1, threads)                     # warm-up and size probe
-        k = int(max(1, min(osp.dim_alpha, round(target_s / max(dt, 1e-3)))))
+        timed(1, threads)                                # warm-up
+        k1, k2 = (4, 16) if threads != 1 else (1, 2)
+        d1, used = timed(k1, threads)
+        d2, _ = timed(k2, threads)
+        per_row = max((d2 - d1) / (k2 - k1), 1e-4)
+        k = int(max(1, min(osp.dim_alpha, round(k1 + (target_s - d1) / per_row))))
         runs = sorted(timed(k, threads)[0] for _ in range(3))
         rate = k * osp.dim_beta * op.n_terms / runs[1]
         res[name] = (rate, used, k, runs[1])
