@@ -1160,10 +1160,10 @@ __device__ inline void row_chunk_of(uint32_t b, uint32_t rows, uint32_t chunks, 
 // LDS: [0, 256) scratch, then rank tables, the list (source ranks, then
 // coefficients), valid classes (source row rank, first and end group
 // record), group records (X_beta, first unique | count << 16), folded
-// uniques and their beta Z-masks; offsets in RowsLayout.
+// uniques and their beta Z-masks, and for the fused energy pass three
+// float64 sums per thread; offsets in RowsLayout.
 struct RowsLayout {
   uint32_t off_rank, off_lsrc, off_lc, off_cls, off_grp, off_f, off_fz, off_e;
-  uint32_t max_list, max_cls, max_grp, max_u;
 };
 
 template <class T, bool EXPVAL>
