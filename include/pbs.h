@@ -119,6 +119,16 @@ pbs_status pbs_sum_info(const pbs_sum* s, uint32_t* n_qubits, uint64_t* n_terms,
  * Any destination may be NULL to skip it.  Synchronizes. */
 pbs_status pbs_sum_read(const pbs_sum* s, uint64_t* x, uint64_t* z, double* coeff, void* stream);
 
+/* Borrowed view of the sum's device arrays (Section 2.3's X, Z, C): *x and
+ * *z point at n_terms*W words each (term-major, word w of term i at
+ * [i*W + w], W = ceil(n_qubits / 64)), *coeff at 2*n_terms doubles (re, im,
+ * letter form).  The pointers stay valid until s is destroyed or modified
+ * (pbs_pauli_canonicalize); the caller must not write through them.  Any
+ * output may be NULL.  An empty sum gives null array pointers.  No copy,
+ * no synchronization. */
+pbs_status pbs_sum_view(const pbs_sum* s, uint32_t* n_qubits, uint64_t* n_terms, const uint64_t** x,
+                        const uint64_t** z, const double** coeff);
+
 void pbs_sum_destroy(pbs_sum* s);
 
 /* Canonical reduction in place (Section 2.3): radix sort on the (X, Z) key,

@@ -25,6 +25,8 @@ SIGNATURES = {
     "pbs_sum_create": (c_int32, [c_uint32, c_uint64, _vp, _vp, _vp, _vp, POINTER(_vp)]),
     "pbs_sum_info": (c_int32, [_vp, POINTER(c_uint32), POINTER(c_uint64), POINTER(c_int32)]),
     "pbs_sum_read": (c_int32, [_vp, _vp, _vp, _vp, _vp]),
+    "pbs_sum_view": (c_int32, [_vp, POINTER(c_uint32), POINTER(c_uint64), POINTER(_vp), POINTER(_vp),
+                               POINTER(_vp)]),
     "pbs_sum_destroy": (None, [_vp]),
     "pbs_pauli_canonicalize": (c_int32, [_vp, c_double, _vp]),
     "pbs_pauli_sum_mul": (c_int32, [_vp, _vp, c_double, _vp, POINTER(_vp)]),

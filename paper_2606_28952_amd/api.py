@@ -106,6 +106,15 @@ class PauliSum:
         call("pbs_sum_read", self._h, _ptr(x), _ptr(z), _ptr(c.view(np.float64)), _stream())
         return x, z, c
 
+    def view(self):
+        """Borrowed device pointers (x, z, coeff) as integers, valid until the
+        sum is destroyed or canonicalized: x and z hold n_terms * W uint64
+        words, coeff 2 * n_terms float64 (re, im); 0 for an empty sum."""
+        nq, m = c_uint32(), c_uint64()
+        x, z, c = c_void_p(), c_void_p(), c_void_p()
+        call("pbs_sum_view", self._h, byref(nq), byref(m), byref(x), byref(z), byref(c))
+        return x.value or 0, z.value or 0, c.value or 0
+
     def canonicalize(self, eps_drop=0.0):
         call("pbs_pauli_canonicalize", self._h, float(eps_drop), _stream())
         return self

@@ -577,6 +577,19 @@ pbs_status pbs_sum_read(const pbs_sum* s, uint64_t* x, uint64_t* z, double* coef
   });
 }
 
+pbs_status pbs_sum_view(const pbs_sum* s, uint32_t* n_qubits, uint64_t* n_terms, const uint64_t** x,
+                        const uint64_t** z, const double** coeff) {
+  return guarded([&] {
+    check_sum(s);
+    if (n_qubits) *n_qubits = s->n_qubits;
+    if (n_terms) *n_terms = s->n_terms;
+    const bool any = s->n_terms > 0;
+    if (x) *x = any ? s->x.get() : nullptr;
+    if (z) *z = any ? s->z.get() : nullptr;
+    if (coeff) *coeff = any ? s->coeff.get() : nullptr;
+  });
+}
+
 void pbs_sum_destroy(pbs_sum* s) { delete s; }
 
 pbs_status pbs_pauli_canonicalize(pbs_sum* sum, double eps_drop, void* stream) {

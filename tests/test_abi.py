@@ -63,6 +63,7 @@ def test_host_side_errors(lib):
     assert lib.pbs_space_sector(40, 1, 1, None, byref(out)) == 2
     assert lib.pbs_space_sector(5, 6, 1, None, byref(out)) == 1   # more electrons than orbitals
     assert lib.pbs_sum_info(None, None, None, None) == 1
+    assert lib.pbs_sum_view(None, None, None, None, None, None) == 1
     assert lib.pbs_apply_pauli_sum(None, None, 0, None, None, None) == 1
     assert lib.pbs_jw_transform(0, None, None, 0.0, 0.0, 0.0, None, byref(out)) == 2
     assert lib.pbs_jw_transform(4, None, None, 0.0, 0.0, 0.0, None, byref(out)) == 1

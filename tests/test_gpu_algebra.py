@@ -216,3 +216,29 @@ def test_jw_multiword(dev):
         p, q, r, s = rng.integers(0, n, 4)
         h2[p, q, r, s] += rng.standard_normal()
     _assert_same(_jw_gpu(dev, h1, h2), ojw.jw_hamiltonian(h1, h2))
+
+
+@pytest.mark.parametrize("n", [12, 130])
+def test_sum_view_borrows_the_device_arrays(dev, n):
+    """pbs_sum_view's pointers are the sum's own device arrays: a sum built
+    from them through the C ABI reads back bit for bit, and an empty sum
+    gives null pointers."""
+    from ctypes import byref, c_void_p
+
+    from paper_2606_28952_amd._abi import call
+
+    api = _api()
+    m = 517
+    x, z, _ = synth.random_symplectic(m, n, seed=60 + n)
+    rng = np.random.default_rng(61 + n)
+    c = rng.standard_normal(m) + 1j * rng.standard_normal(m)
+    s = api.PauliSum.create(n, x.reshape(-1), z.reshape(-1), c)
+    xp, zp, cp = s.view()
+    assert xp and zp and cp
+    out = c_void_p()
+    call("pbs_sum_create", n, m, c_void_p(xp), c_void_p(zp), c_void_p(cp), None, byref(out))
+    copy = api.PauliSum(out)
+    for a, b in zip(s.read(), copy.read()):
+        assert a.tobytes() == b.tobytes()
+    empty = api.PauliSum.create(n, np.zeros(0, np.uint64), np.zeros(0, np.uint64), np.zeros(0, np.complex128))
+    assert empty.view() == (0, 0, 0)
