@@ -606,6 +606,19 @@ def main():
     # kernel source (null when the kernel has changed since).  The method's
     # algorithmic gather bytes per launch, D * 8 B * (1 + G_conn), are
     # reported beside it: most of them are served from LDS and caches.
+    # HBM bandwidth a plain device-to-device copy reaches on this device
+    # (1 GiB read + 1 GiB written), reported beside the published peak
+    cp_src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+    cp_dst = torch.empty_like(cp_src)
+    cp_dst.copy_(cp_src)
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0.record()
+    for _ in range(5):
+        cp_dst.copy_(cp_src)
+    c1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 2 * cp_src.numel() * 4 * 5 / (c0.elapsed_time(c1) * 1e-3) / 1e9
+    del cp_src, cp_dst
     bytes_per_launch = D * 8 * (1.0 + g_conn)
     gather_gbs = bytes_per_launch / (apply_ms * 1e-3) / 1e9
     kernel_tag = f"apply_{prm.get('kernel', 'sector') if not args.no_factor else 'sector'}_c64_{args.workload}"
@@ -617,7 +630,7 @@ def main():
         # bandwidth-bound (few groups per target, rows too long for LDS): the
         # algorithmic gather bytes against the HBM peak
         roofline = {"bound": "hbm", "achieved": gather_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": gather_gbs / HBM_PEAK_GBS, "traffic": traffic,
+                    "frac": gather_gbs / HBM_PEAK_GBS, "measured_copy_GBs": copy_gbs, "traffic": traffic,
                     "hbm_GBs": traffic / (apply_ms * 1e-3) / 1e9 if traffic else None,
                     "valu_frac": valu / (apply_ms * 1e-3) / 1e9 / valu_peak if valu else None,
                     "apply_ms": apply_ms, "apply_ms_serial_steps": apply_ms_serial}
@@ -629,6 +642,7 @@ def main():
                     "traffic": traffic,
                     "hbm_GBs": traffic / (apply_ms * 1e-3) / 1e9 if traffic else None,
                     "hbm_frac": traffic / (apply_ms * 1e-3) / 1e9 / HBM_PEAK_GBS if traffic else None,
+                    "measured_copy_GBs": copy_gbs,
                     "algorithmic_gather_bytes": bytes_per_launch, "algorithmic_gather_GBs": gather_gbs,
                     "apply_ms": apply_ms, "apply_ms_serial_steps": apply_ms_serial}
     line = {

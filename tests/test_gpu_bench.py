@@ -35,5 +35,6 @@ def test_bench_line_contract():
     assert d["rel_err_c64_vs_c128_same_input"] < 1e-6
     r = d["roofline"]
     assert r["bound"] in ("alu", "hbm") and r["peak"] > 0 and r["apply_ms"] > 0
+    assert 100.0 < r["measured_copy_GBs"] < 16000.0  # a plain copy, against the 8 TB/s HBM peak
     c = d["cpu_baseline"]
     assert c["kind"] == "oracle" and c["value"] > 0 and c["cores"] >= 1 and c["sample"]
