@@ -193,6 +193,8 @@ void launch_nv(int nv, dim3 grid, hipStream_t s, A... args) {
       return;
     }
     launch_nv<K, NV + 1>(nv, grid, s, args...);
+  } else {
+    PBS_REQUIRE(false, PBS_ERR_RANGE, "vector count outside 1..16");
   }
 }
 template <class T>
