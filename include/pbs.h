@@ -231,6 +231,34 @@ pbs_status pbs_expval_workspace_bytes(const pbs_space* sp, uint64_t* bytes);
 pbs_status pbs_expval(const pbs_grouped* h, const pbs_space* sp, pbs_dtype dt, const void* psi, void* out,
                       double* result, void* work, uint64_t work_bytes, void* stream);
 
+/* One share of pbs_apply_pauli_sum in a spin sector: the targets of alpha
+ * rows [row_begin, row_end) only.  Target-driven summation (Eq. reverse_sum,
+ * Eq. sreverse_sum) evaluates each target amplitude on its own, so the rows
+ * of a sector split into independent shares that need the whole psi and no
+ * reduction; a device holding one share runs this with its rows.  The same
+ * kernels as the whole-sector call, so the shares concatenated are
+ * bit-identical to pbs_apply_pauli_sum's output.
+ *  psi  device, the whole state (D values of type dt);
+ *  out  device, (row_end - row_begin) * dim_beta values: out[(a - row_begin)
+ *       * dim_beta + b] is the target of alpha row a, beta column b; it must
+ *       not overlap psi.
+ * PBS_ERR_ARG on a full space, PBS_ERR_RANGE unless row_begin <= row_end <=
+ * dim_alpha; an empty range enqueues nothing.  Asynchronous; allocates
+ * nothing. */
+pbs_status pbs_apply_pauli_sum_rows(const pbs_grouped* h, const pbs_space* sp, pbs_dtype dt, const void* psi,
+                                    void* out, uint64_t row_begin, uint64_t row_end, void* stream);
+
+/* pbs_expval over alpha rows [row_begin, row_end) of a sector: result[0..2] =
+ * (Re, Im of sum over the share's targets t of conj(psi_t) (H psi)_t, and sum
+ * of |psi_t|^2 over them), so that the shares' results add up to
+ * pbs_expval's (up to the order of the float64 sums).  out is NULL or a
+ * share as in pbs_apply_pauli_sum_rows; work as in pbs_expval (the whole
+ * space's pbs_expval_workspace_bytes is always enough).  Same errors as
+ * pbs_apply_pauli_sum_rows.  Asynchronous; allocates nothing. */
+pbs_status pbs_expval_rows(const pbs_grouped* h, const pbs_space* sp, pbs_dtype dt, const void* psi, void* out,
+                           uint64_t row_begin, uint64_t row_end, double* result, void* work, uint64_t work_bytes,
+                           void* stream);
+
 /* Size of the fixed device workspace behind pbs_expval_noalloc. */
 #define PBS_EXPVAL_NOALLOC_MAX_BYTES (8u * 1024u * 1024u)
 

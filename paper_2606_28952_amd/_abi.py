@@ -47,6 +47,8 @@ SIGNATURES = {
     "pbs_expval_workspace_bytes": (c_int32, [_vp, POINTER(c_uint64)]),
     "pbs_expval": (c_int32, [_vp, _vp, c_int32, _vp, _vp, _vp, _vp, c_uint64, _vp]),
     "pbs_expval_noalloc": (c_int32, [_vp, _vp, c_int32, _vp, _vp, _vp, _vp]),
+    "pbs_apply_pauli_sum_rows": (c_int32, [_vp, _vp, c_int32, _vp, _vp, c_uint64, c_uint64, _vp]),
+    "pbs_expval_rows": (c_int32, [_vp, _vp, c_int32, _vp, _vp, c_uint64, c_uint64, _vp, _vp, c_uint64, _vp]),
     "pbs_grouped_factor": (c_int32, [_vp, _vp, _vp]),
     "pbs_grouped_set_factored": (c_int32, [_vp, c_int32]),
     "pbs_grouped_factor_info": (c_int32, [_vp, _vp]),

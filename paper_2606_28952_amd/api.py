@@ -304,6 +304,43 @@ def expval_noalloc(grouped, space, psi, result, out=None):
     return result
 
 
+def _check_rows(space, psi, out, row_begin, row_end):
+    """Host-side shape checks of a row-range call (the library checks the
+    range itself against the sector)."""
+    code = _dtype_code(psi)
+    if psi.device.type != "cuda" or psi.numel() != space.dim:
+        raise ValueError(f"state must be a device vector of length {space.dim}")
+    dim_beta = space.shape()[4]
+    rows = max(0, int(row_end) - int(row_begin))
+    if out is not None and (out.dtype != psi.dtype or out.numel() != rows * dim_beta or out.device != psi.device):
+        raise ValueError(f"out must hold {rows} x {dim_beta} values of psi's dtype on psi's device")
+    return code, rows * dim_beta
+
+
+def apply_pauli_sum_rows(grouped, space, psi, row_begin, row_end, out=None):
+    """Alpha rows [row_begin, row_end) of P H P psi in a sector (one share of
+    the target-row split), as a vector of (row_end - row_begin) * dim_beta."""
+    code, n = _check_rows(space, psi, out, row_begin, row_end)
+    if out is None:
+        out = torch.empty(n, dtype=psi.dtype, device=psi.device)
+    call("pbs_apply_pauli_sum_rows", grouped._h, space._h, code, _ptr(psi), _ptr(out), int(row_begin), int(row_end),
+         _stream())
+    return out
+
+
+def expval_rows(grouped, space, psi, row_begin, row_end, work=None, result=None, out=None):
+    """The share of alpha rows [row_begin, row_end) in expval's three sums;
+    with ``out`` the same pass stores those rows of H psi."""
+    code, _ = _check_rows(space, psi, out, row_begin, row_end)
+    if work is None:
+        work = torch.empty(max(1, space.workspace_bytes() // 8), dtype=torch.float64, device=psi.device)
+    if result is None:
+        result = torch.empty(3, dtype=torch.float64, device=psi.device)
+    call("pbs_expval_rows", grouped._h, space._h, code, _ptr(psi), _ptr(out), int(row_begin), int(row_end),
+         _ptr(result), _ptr(work), work.numel() * 8, _stream())
+    return result
+
+
 class KrylovPropagator:
     """psi <- exp(-i H dt) psi by short-iterative Lanczos with m vectors; owns
     its device workspace (allocated once, reused by every step)."""

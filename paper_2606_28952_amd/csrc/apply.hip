@@ -314,9 +314,13 @@ bool plan_rows(const pbs_grouped& h, const SectorArgs& a, bool r16, bool expval,
   return true;
 }
 
+// Launches the apply (EXPVAL: with the energy partials) for target alpha
+// rows [row_begin, row_end) of a sector space (the whole space by default);
+// out holds those rows only, from row_begin's first column.  Returns the
+// number of energy partials written.
 template <class T, bool EXPVAL>
 uint64_t launch(const pbs_grouped& h, const pbs_space& sp, const void* psi, void* out, double* partial,
-                hipStream_t s) {
+                hipStream_t s, uint64_t row_begin = 0, uint64_t row_end = ~0ull) {
   const T* p = static_cast<const T*>(psi);
   T* o = static_cast<T*>(out);
   if (!sp.sector) {
@@ -329,22 +333,30 @@ uint64_t launch(const pbs_grouped& h, const pbs_space& sp, const void* psi, void
     bool r16 = false;
     const Launch L = plan_sector(h, sp, sizeof(T), true, h.real_coef, &a, &r16);
     const pbs_dtype dt = sizeof(T) == 16 ? PBS_C128 : PBS_C64;
+    row_end = std::min<uint64_t>(row_end, sp.dim_alpha);
+    const uint64_t rows = row_end - row_begin;
+    if (rows == 0) return 0;
+    a.row_begin = static_cast<uint32_t>(row_begin);
+    // the kernels store target t = row * dim_beta + column at out[t]: shift
+    // the base so that row_begin's first column lands at out[0]
+    if (o) o = reinterpret_cast<T*>(reinterpret_cast<uintptr_t>(o) - row_begin * sp.dim_beta * sizeof(T));
     RowsLayout Lr;
     size_t lds_rows = 0;
     if (h.real_coef && plan_rows(h, a, r16, EXPVAL, &Lr, &lds_rows)) {
       // one workgroup per alpha row, sweeping all of its columns
-      hipLaunchKernelGGL((k_apply_rows<T, EXPVAL>), dim3(static_cast<unsigned>(sp.dim_alpha)), dim3(kSB), lds_rows, s,
-                         a, Lr, p, o, partial);
+      hipLaunchKernelGGL((k_apply_rows<T, EXPVAL>), dim3(static_cast<unsigned>(rows)), dim3(kSB), lds_rows, s, a, Lr,
+                         p, o, partial);
       PBS_HIP(hipGetLastError());
-      return sp.dim_alpha;
+      return rows;
     }
     void* kern = sector_kernel(dt, EXPVAL, false, r16, a.row_lds != 0, h.real_coef);
     if (L.lds > 64 * 1024)
       PBS_HIP(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(L.lds)));
     void* args[] = {&a, &p, &o, &partial};
-    PBS_HIP(hipLaunchKernel(kern, L.grid, L.block, args, L.lds, s));
+    const uint64_t parts = rows * L.chunks;
+    PBS_HIP(hipLaunchKernel(kern, dim3(static_cast<unsigned>(parts)), L.block, args, L.lds, s));
     PBS_HIP(hipGetLastError());
-    return L.parts;
+    return parts;
   }
   PBS_HIP(hipGetLastError());
   return partial_count(sp);
@@ -407,6 +419,62 @@ pbs_status pbs_expval(const pbs_grouped* h, const pbs_space* sp, pbs_dtype dt, c
     double* partial = static_cast<double*>(work);
     const uint64_t parts = dt == PBS_C128 ? launch<double2, true>(*h, *sp, psi, out, partial, s)
                                           : launch<float2, true>(*h, *sp, psi, out, partial, s);
+    hipLaunchKernelGGL(k_expval_finish, dim3(1), dim3(kBlock), 0, s, partial, parts, result);
+    PBS_HIP(hipGetLastError());
+  });
+}
+
+}  // extern "C"
+
+namespace {
+// Checks of a target-row range call: a sector space, rows within it, and an
+// output shard of (row_end - row_begin) rows that does not overlap psi.
+void check_rows(const pbs_space* sp, pbs_dtype dt, const void* psi, const void* out, uint64_t row_begin,
+                uint64_t row_end) {
+  PBS_REQUIRE(sp->sector, PBS_ERR_ARG, "a row range needs a spin-sector space");
+  PBS_REQUIRE(row_begin <= row_end && row_end <= sp->dim_alpha, PBS_ERR_RANGE,
+              "rows [" + std::to_string(row_begin) + ", " + std::to_string(row_end) + ") outside the sector's " +
+                  std::to_string(sp->dim_alpha) + " alpha rows");
+  PBS_REQUIRE(psi != nullptr, PBS_ERR_ARG, "null state pointer");
+  if (out) {
+    const uint64_t elem = dt == PBS_C128 ? 16ull : 8ull;
+    const auto a = reinterpret_cast<uintptr_t>(psi), b = reinterpret_cast<uintptr_t>(out);
+    const uint64_t in_bytes = sp->dim * elem, out_bytes = (row_end - row_begin) * sp->dim_beta * elem;
+    PBS_REQUIRE(a + in_bytes <= b || b + out_bytes <= a, PBS_ERR_ARG, "out overlaps psi");
+  }
+}
+}  // namespace
+
+extern "C" {
+
+pbs_status pbs_apply_pauli_sum_rows(const pbs_grouped* h, const pbs_space* sp, pbs_dtype dt, const void* psi,
+                                    void* out, uint64_t row_begin, uint64_t row_end, void* stream) {
+  return guarded([&] {
+    validate(h, sp, dt);
+    check_rows(sp, dt, psi, out, row_begin, row_end);
+    PBS_REQUIRE(out != nullptr || row_begin == row_end, PBS_ERR_ARG, "null output pointer");
+    hipStream_t s = as_stream(stream);
+    if (dt == PBS_C128)
+      launch<double2, false>(*h, *sp, psi, out, nullptr, s, row_begin, row_end);
+    else
+      launch<float2, false>(*h, *sp, psi, out, nullptr, s, row_begin, row_end);
+  });
+}
+
+pbs_status pbs_expval_rows(const pbs_grouped* h, const pbs_space* sp, pbs_dtype dt, const void* psi, void* out,
+                           uint64_t row_begin, uint64_t row_end, double* result, void* work, uint64_t work_bytes,
+                           void* stream) {
+  return guarded([&] {
+    validate(h, sp, dt);
+    PBS_REQUIRE(result != nullptr && work != nullptr, PBS_ERR_ARG, "null pointer");
+    check_rows(sp, dt, psi, out, row_begin, row_end);
+    const uint64_t need = partial_count(*sp) * 3 * sizeof(double);
+    PBS_REQUIRE(work_bytes >= need, PBS_ERR_ARG,
+                "workspace of " + std::to_string(work_bytes) + " bytes, need " + std::to_string(need));
+    hipStream_t s = as_stream(stream);
+    double* partial = static_cast<double*>(work);
+    const uint64_t parts = dt == PBS_C128 ? launch<double2, true>(*h, *sp, psi, out, partial, s, row_begin, row_end)
+                                          : launch<float2, true>(*h, *sp, psi, out, partial, s, row_begin, row_end);
     hipLaunchKernelGGL(k_expval_finish, dim3(1), dim3(kBlock), 0, s, partial, parts, result);
     PBS_HIP(hipGetLastError());
   });

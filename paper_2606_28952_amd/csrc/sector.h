@@ -206,6 +206,7 @@ constexpr uint32_t kFactAlpha = 4u;  // simple classes through the alpha lists
 struct SectorArgs {
   uint32_t n_orb, n_alpha, n_beta, n_chunks;
   uint32_t dim_beta;
+  uint32_t row_begin;  // first target alpha row of the launch (0: the whole sector)
   uint32_t n_class, n_pairs, n_moves;
   uint32_t row_lds, enum_ok;
   uint32_t list_cap;  // entries of the simple-class row list (in the row space)
@@ -1170,7 +1171,7 @@ template <class T, bool EXPVAL>
 __global__ __launch_bounds__(kSB) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 8 : 1, 8))) void k_apply_rows(SectorArgs P, RowsLayout Lr, const T* __restrict__ psi,
                                                     T* __restrict__ out, double* __restrict__ partial) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const uint32_t ia = blockIdx.x;
+  const uint32_t ia = blockIdx.x + P.row_begin;
   const uint64_t db = P.dim_beta;
   uint16_t* s_rank = reinterpret_cast<uint16_t*>(smem + Lr.off_rank);
   uint32_t* s_lsrc = reinterpret_cast<uint32_t*>(smem + Lr.off_lsrc);
@@ -1308,14 +1309,15 @@ __global__ __launch_bounds__(kSB) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
                              partial + 3ull * blockIdx.x, reinterpret_cast<double(*)[kSB / 64]>(smem + 64));
 }
 
-// One-dimensional grid of dim_alpha * chunks workgroups.
+// One-dimensional grid of rows * chunks workgroups for target rows
+// [row_begin, row_begin + rows) (all rows unless a row range is asked for).
 template <class T, bool EXPVAL, bool R16, bool ROWLDS, bool REALC>
 __global__ __launch_bounds__(kSB) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_apply_sector(
     SectorArgs P, const T* __restrict__ psi, T* __restrict__ out, double* __restrict__ partial) {
   const uint32_t chunks = (P.dim_beta + kSB - 1) / kSB;
   uint32_t row, chunk;
   row_chunk_of(blockIdx.x, gridDim.x / chunks, chunks, P.row_lds != 0, row, chunk);
-  sector_body<T, EXPVAL, R16, ROWLDS, REALC>(P, psi, out, partial + 3ull * blockIdx.x, row, chunk);
+  sector_body<T, EXPVAL, R16, ROWLDS, REALC>(P, psi, out, partial + 3ull * blockIdx.x, row + P.row_begin, chunk);
 }
 
 // A job of a batched launch: one operator on one sector state.

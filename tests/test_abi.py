@@ -65,6 +65,8 @@ def test_host_side_errors(lib):
     assert lib.pbs_sum_info(None, None, None, None) == 1
     assert lib.pbs_sum_view(None, None, None, None, None, None) == 1
     assert lib.pbs_apply_pauli_sum(None, None, 0, None, None, None) == 1
+    assert lib.pbs_apply_pauli_sum_rows(None, None, 0, None, None, 0, 1, None) == 1
+    assert lib.pbs_expval_rows(None, None, 0, None, None, 0, 1, None, None, 0, None) == 1
     assert lib.pbs_jw_transform(0, None, None, 0.0, 0.0, 0.0, None, byref(out)) == 2
     assert lib.pbs_jw_transform(4, None, None, 0.0, 0.0, 0.0, None, byref(out)) == 1
     assert lib.pbs_pauli_mul(300, 1, *([None] * 9), None) == 2

@@ -12,6 +12,9 @@ configuration the benchmark times.
 * 32-qubit 4x4 Hubbard sector ((8, 8), D = 165,636,900): 16 whole rows of
   12,870 columns for a dense state, and the whole vector for a state
   supported on 4 rows.
+* One device's share of an eight-way split of the target alpha rows at both
+  sizes (the row-range entry points), bit-identical to those rows of the
+  whole-sector apply.
 
 Bars: complex128 storage within 1e-12 of the oracle in the relative 2-norm;
 complex64 storage within 1e-6 of the oracle run on the same FP32-rounded
@@ -143,6 +146,34 @@ def test_28q_hermiticity_dense_states(dev, mol28):
     assert abs(lhs - rhs) < 1e-11 * max(1.0, abs(lhs))
 
 
+def _eighth(dim_alpha, r):
+    return r * dim_alpha // 8, (r + 1) * dim_alpha // 8
+
+
+def test_28q_one_eighth_row_share(dev, mol28):
+    """One device's share of an eight-way split of the target alpha rows, in
+    complex64 as the benchmark runs: bit-identical to the same rows of the
+    whole-sector apply, four of its rows against the oracle, and the eight
+    shares' energy sums adding up to the whole-sector energy."""
+    api = _api()
+    G, sp, osp, op, prep = mol28
+    psi32 = synth.random_state(sp.dim, seed=2103).astype(np.complex64)
+    t32 = torch.from_numpy(psi32).to(dev)
+    whole = api.apply_pauli_sum(G, sp, t32)
+    a0, a1 = _eighth(osp.dim_alpha, 3)
+    print(f"[28q share] rows [{a0}, {a1}) of {osp.dim_alpha}, complex64", flush=True)
+    share = api.apply_pauli_sum_rows(G, sp, t32, a0, a1)
+    db = osp.dim_beta
+    assert torch.equal(torch.view_as_real(share), torch.view_as_real(whole[a0 * db:a1 * db]))
+    rows = np.array([a0, a0 + 17, a1 - 40, a1 - 1])
+    ref, _ = native.apply_targets(op, osp, psi32, _row_targets(rows, db), prepared=prep)
+    sel = torch.from_numpy(_row_targets(rows - a0, db)).to(dev)
+    assert rel_err(share[sel].cpu().numpy().astype(np.complex128), ref) < 1e-6
+    e_whole = api.expval(G, sp, t32).cpu().numpy()
+    e_sum = sum(api.expval_rows(G, sp, t32, *_eighth(osp.dim_alpha, r)).cpu().numpy() for r in range(8))
+    assert np.all(np.abs(e_sum - e_whole) < 1e-12 * max(1.0, abs(e_whole[0]))), (e_sum, e_whole)
+
+
 @pytest.fixture(scope="module", params=[False, True], ids=["plain", "factored"])
 def hub32(dev, request):
     api = _api()
@@ -195,3 +226,17 @@ def test_32q_hubbard_sparse_support_whole_vector(dev, hub32):
     assert rel_err(got.astype(np.complex128), ref) < 1e-6
     e_ref = np.vdot(psi32.astype(np.complex128), ref)
     assert abs(e[0] - e_ref.real) < 1e-8
+
+
+def test_32q_hubbard_one_eighth_row_share(dev, hub32):
+    """One device's share of an eight-way row split of the 4x4 Hubbard
+    sector (complex64): bit-identical to those rows of the whole apply."""
+    api = _api()
+    G, sp, osp, _, _ = hub32
+    t32 = torch.from_numpy(synth.random_state(sp.dim, seed=4103).astype(np.complex64)).to(dev)
+    a0, a1 = _eighth(osp.dim_alpha, 5)
+    print(f"[32q share] rows [{a0}, {a1}) of {osp.dim_alpha}, complex64", flush=True)
+    share = api.apply_pauli_sum_rows(G, sp, t32, a0, a1)
+    whole = api.apply_pauli_sum(G, sp, t32)
+    db = osp.dim_beta
+    assert torch.equal(torch.view_as_real(share), torch.view_as_real(whole[a0 * db:a1 * db]))
