@@ -584,6 +584,24 @@ def main():
 
     c64_ms = time_apply(psi32, out32)
     c128_ms = time_apply(psi64, out64)
+
+    # one device's share of an eight-way split of the target alpha rows
+    # (the row-range entry point; each share needs the whole state): the
+    # kernel time of each share at its real shape, complex64
+    def time_share(a0, a1, reps=10):
+        o = out32[a0 * sp.shape()[4]:a1 * sp.shape()[4]]
+        api.apply_pauli_sum_rows(G, sp, psi32, a0, a1, out=o)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record()
+        for _ in range(reps):
+            api.apply_pauli_sum_rows(G, sp, psi32, a0, a1, out=o)
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    dim_alpha = sp.shape()[3]
+    share_ms = [time_share(r * dim_alpha // 8, (r + 1) * dim_alpha // 8) for r in range(8)]
     # the unfactored evaluation of the same kernel, for comparison
     G.set_factored(0)
     c64_plain_ms = time_apply(psi32, torch.empty_like(psi32))
@@ -673,6 +691,7 @@ def main():
         "apply_rate_c128": D * M / (c128_ms * 1e-3),
         "speedup_c64_vs_c128": c128_ms / c64_ms,
         "factored": not args.no_factor,
+        "apply_ms_c64_row_shares_of_8": [round(t, 4) for t in share_ms],
         "apply_ms_c64_unfactored": c64_plain_ms,
         "apply_ms_c128_unfactored": c128_plain_ms,
         "rel_err_c64_vs_c128_same_input": err_kernel,

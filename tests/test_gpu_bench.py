@@ -33,6 +33,8 @@ def test_bench_line_contract():
     assert d["config"]["workload"] == "molecular-12q-sector" and d["config"]["dim"] == 400
     assert d["pipelined_equals_serial"] is True
     assert d["rel_err_c64_vs_c128_same_input"] < 1e-6
+    shares = d["apply_ms_c64_row_shares_of_8"]
+    assert len(shares) == 8 and min(shares) > 0
     r = d["roofline"]
     assert r["bound"] in ("alu", "hbm") and r["peak"] > 0 and r["apply_ms"] > 0
     assert 100.0 < r["measured_copy_GBs"] < 16000.0  # a plain copy, against the 8 TB/s HBM peak
