@@ -86,6 +86,37 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_apply(const uint32_t* in, u
   }
 }
 
+// Single block: the whole scan for short inputs (at most kScanSingleTiles
+// tiles), tile after tile with a running carry; in == out is allowed (each
+// thread reads its items before the block scan and writes them after it).
+constexpr uint64_t kScanSingleTiles = 16;
+__global__ __launch_bounds__(kScanBlock) void k_scan_single(const uint32_t* in, uint32_t* out, uint64_t n,
+                                                            uint32_t* total_out) {
+  __shared__ uint32_t lds[kScanBlock / 64];
+  uint32_t carry = 0;
+  for (uint64_t c = 0; c < n; c += kScanTile) {
+    const uint64_t base = c + threadIdx.x * kScanItems;
+    uint32_t v[kScanItems];
+    uint32_t s = 0;
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+      const uint64_t i = base + j;
+      v[j] = i < n ? in[i] : 0u;
+      s += v[j];
+    }
+    uint32_t tot;
+    uint32_t run = carry + block_exclusive_scan(s, lds, tot);
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+      const uint64_t i = base + j;
+      if (i < n) out[i] = run;
+      run += v[j];
+    }
+    carry += tot;
+  }
+  if (threadIdx.x == 0 && total_out) *total_out = carry;
+}
+
 // ---------------------------------------------------------------- radix sort
 constexpr int kSortBlock = 256;
 constexpr uint32_t kSortTile = 4096;
@@ -209,12 +240,20 @@ void exclusive_scan_u32(const uint32_t* in, uint32_t* out, uint64_t n, uint32_t*
     return;
   }
   const uint64_t nb = (n + kScanTile - 1) / kScanTile;
+  if (nb <= kScanSingleTiles) {  // one launch, no temporary
+    hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(kScanBlock), 0, s, in, out, n, total);
+    PBS_HIP(hipGetLastError());
+    return;
+  }
   DevBuf<uint32_t> partial(nb, s);
   hipLaunchKernelGGL(k_scan_partials, dim3(static_cast<unsigned>(nb)), dim3(kScanBlock), 0, s, in, n, partial.get());
   hipLaunchKernelGGL(k_scan_partials_scan, dim3(1), dim3(kScanBlock), 0, s, partial.get(), nb, total);
   hipLaunchKernelGGL(k_scan_apply, dim3(static_cast<unsigned>(nb)), dim3(kScanBlock), 0, s, in, out, n, partial.get());
   PBS_HIP(hipGetLastError());
-  PBS_HIP(hipStreamSynchronize(s));  // `partial` is released on return
+  // `partial` is released on return: a temporary of the call's scratch scope
+  // stays reserved until the scope ends (which waits for the stream); one
+  // from hipMalloc must not be freed under queued work
+  if (!partial.borrowed) PBS_HIP(hipStreamSynchronize(s));
 }
 
 void mark_heads(const uint64_t* keys, uint64_t m, int nw, uint32_t* heads, hipStream_t s) {
@@ -259,7 +298,9 @@ void radix_sort_keys(uint64_t* keys, uint32_t* vals, uint64_t m, int nw, hipStre
     PBS_HIP(hipMemcpyAsync(keys, kcur, m * nw * sizeof(uint64_t), hipMemcpyDeviceToDevice, s));
     PBS_HIP(hipMemcpyAsync(vals, vcur, m * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
   }
-  PBS_HIP(hipStreamSynchronize(s));
+  // temporaries of the call's scratch scope stay reserved until it ends;
+  // hipMalloc'd ones are freed on return, after the queued work
+  if (!(vary.borrowed && ktmp.borrowed && vtmp.borrowed && counts.borrowed)) PBS_HIP(hipStreamSynchronize(s));
 }
 
 }  // namespace pbs
