@@ -18,6 +18,8 @@
 // exact ranks on these matrices with the same rounding-level residual.
 #include <algorithm>
 #include <cmath>
+#include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "handles.h"
@@ -247,26 +249,115 @@ __global__ __launch_bounds__(kImgBlock) void k_pair_images(uint32_t n_img, uint3
 
 // ---------------------------------------------------------------- host side
 
-template <class T>
-void upload(DevBuf<T>& d, const std::vector<T>& h) {
-  d.alloc(h.size());
-  if (!h.empty()) PBS_HIP(hipMemcpy(d.get(), h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
-}
+// Pinned host staging for the build's small host<->device copies, one buffer
+// per device for the process's lifetime, used by one build at a time.  Copies
+// through it are stream-ordered and asynchronous: an upload returns at once,
+// and several downloads complete with one wait.  A copy that does not fit
+// goes through pageable memory (synchronously, as before) and the buffer
+// grows for the next build.
+class Staging {
+ public:
+  explicit Staging(hipStream_t s) : s_(s) {
+    int dev = 0;
+    PBS_HIP(hipGetDevice(&dev));
+    PBS_REQUIRE(dev >= 0 && dev < kMaxDevices, PBS_ERR_RANGE, "device index beyond the staging table");
+    pool_ = &pools()[dev];
+    pool_->mu.lock();
+    if (!pool_->base && hipHostMalloc(&pool_->base, kInitial, hipHostMallocDefault) == hipSuccess)
+      pool_->cap = kInitial;
+    (void)hipGetLastError();
+  }
+  ~Staging() {
+    // queued copies read or fill the buffer until the stream reaches them
+    (void)hipStreamSynchronize(s_);
+    if (wanted_ > pool_->cap) {
+      if (pool_->base) (void)hipHostFree(pool_->base);
+      pool_->base = nullptr;
+      pool_->cap = 0;
+      const size_t grown = wanted_ + wanted_ / 4;
+      if (hipHostMalloc(&pool_->base, grown, hipHostMallocDefault) == hipSuccess) pool_->cap = grown;
+    }
+    (void)hipGetLastError();
+    pool_->mu.unlock();
+  }
+  Staging(const Staging&) = delete;
+  Staging& operator=(const Staging&) = delete;
 
-// a temporary of the build, from the call's scratch arena (released without
-// hipFree, which would wait for the whole device)
-template <class T>
-void upload_temp(DevBuf<T>& d, const std::vector<T>& h, hipStream_t s) {
-  d = DevBuf<T>(h.size(), s);
-  if (!h.empty()) PBS_HIP(hipMemcpy(d.get(), h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
-}
+  // handle-owned buffer (hipMalloc), filled from h
+  template <class T>
+  void upload(DevBuf<T>& d, const std::vector<T>& h) {
+    d.alloc(h.size());
+    put(d.get(), h);
+  }
+  // temporary of the build, from the call's scratch arena
+  template <class T>
+  void upload_temp(DevBuf<T>& d, const std::vector<T>& h) {
+    d = DevBuf<T>(h.size(), s_);
+    put(d.get(), h);
+  }
+  // n values of d into out, complete after wait()
+  template <class T>
+  void fetch(std::vector<T>& out, const DevBuf<T>& d, size_t n) {
+    out.resize(n);
+    if (!n) return;
+    const size_t bytes = n * sizeof(T);
+    if (void* p = take(bytes)) {
+      PBS_HIP(hipMemcpyAsync(p, d.get(), bytes, hipMemcpyDeviceToHost, s_));
+      pending_.push_back({out.data(), p, bytes});
+    } else {
+      PBS_HIP(hipMemcpyAsync(out.data(), d.get(), bytes, hipMemcpyDeviceToHost, s_));
+    }
+  }
+  // waits for the stream and moves the fetched values into place
+  void wait() {
+    PBS_HIP(hipStreamSynchronize(s_));
+    for (const Pending& q : pending_) std::memcpy(q.dst, q.src, q.bytes);
+    pending_.clear();
+  }
 
-template <class T>
-std::vector<T> download(const DevBuf<T>& d, size_t n) {
-  std::vector<T> h(n);
-  if (n) PBS_HIP(hipMemcpy(h.data(), d.get(), n * sizeof(T), hipMemcpyDeviceToHost));
-  return h;
-}
+ private:
+  static constexpr int kMaxDevices = 64;
+  static constexpr size_t kInitial = size_t(8) << 20;
+  struct Pool {
+    void* base = nullptr;
+    size_t cap = 0;
+    std::mutex mu;
+  };
+  struct Pending {
+    void* dst;
+    const void* src;
+    size_t bytes;
+  };
+  static Pool* pools() {
+    static Pool table[kMaxDevices];  // lives until the process ends
+    return table;
+  }
+  void* take(size_t bytes) {
+    const size_t need = (bytes + 255) & ~static_cast<size_t>(255);
+    const size_t at = top_;
+    top_ += need;
+    wanted_ = std::max(wanted_, top_);
+    if (!pool_->base || top_ > pool_->cap) return nullptr;
+    return static_cast<char*>(pool_->base) + at;
+  }
+  template <class T>
+  void put(T* dst, const std::vector<T>& h) {
+    if (h.empty()) return;
+    const size_t bytes = h.size() * sizeof(T);
+    if (void* p = take(bytes)) {
+      std::memcpy(p, h.data(), bytes);
+      PBS_HIP(hipMemcpyAsync(dst, p, bytes, hipMemcpyHostToDevice, s_));
+    } else {
+      PBS_HIP(hipMemcpyAsync(dst, h.data(), bytes, hipMemcpyHostToDevice, s_));
+      PBS_HIP(hipStreamSynchronize(s_));  // h may change once we return
+    }
+  }
+
+  hipStream_t s_;
+  Pool* pool_ = nullptr;
+  size_t top_ = 0, wanted_ = 0;
+  std::vector<Pending> pending_;
+};
 
 void build_plan(pbs_grouped& h, const pbs_space& sp, hipStream_t s) {
   auto plan = std::make_unique<FactorPlan>();
@@ -275,20 +366,22 @@ void build_plan(pbs_grouped& h, const pbs_space& sp, hipStream_t s) {
   F.n_beta = sp.n_beta;
   F.dim_beta = sp.dim_beta;
   const uint64_t db = sp.dim_beta;
-  PBS_HIP(hipStreamSynchronize(s));
+  Staging st(s);
   HostTables T;
-  T.pg_u0 = download(h.pg_u0, h.n_pgroup + 1);
-  T.u_zb = download(h.u_zb, h.n_unique);
-  T.u_t0 = download(h.u_t0, h.n_unique + 1);
-  T.pt_za = download(h.pt_za, h.n_pterm);
-  T.pg_xb = download(h.pg_xb, h.n_pgroup);
-  {
-    const std::vector<double> c = download(h.pt_c, 2ull * h.n_pterm);
-    T.pt_c.resize(h.n_pterm);
-    for (uint32_t t = 0; t < h.n_pterm; ++t) T.pt_c[t] = c[2ull * t];
-  }
-  const std::vector<ClassMeta> meta = download(h.cls_meta, h.n_class);
-  const std::vector<uint32_t> ns = download(h.ns_list, h.n_ns);
+  std::vector<double> pt_c2;
+  std::vector<ClassMeta> meta;
+  std::vector<uint32_t> ns;
+  st.fetch(T.pg_u0, h.pg_u0, h.n_pgroup + 1);
+  st.fetch(T.u_zb, h.u_zb, h.n_unique);
+  st.fetch(T.u_t0, h.u_t0, h.n_unique + 1);
+  st.fetch(T.pt_za, h.pt_za, h.n_pterm);
+  st.fetch(T.pg_xb, h.pg_xb, h.n_pgroup);
+  st.fetch(pt_c2, h.pt_c, 2ull * h.n_pterm);
+  st.fetch(meta, h.cls_meta, h.n_class);
+  st.fetch(ns, h.ns_list, h.n_ns);
+  st.wait();
+  T.pt_c.resize(h.n_pterm);
+  for (uint32_t t = 0; t < h.n_pterm; ++t) T.pt_c[t] = pt_c2[2ull * t];
 
   // factor uniques (alpha side) and the beta lists of the table rows
   std::vector<uint32_t> fu_t0{0}, ft_za;
@@ -413,15 +506,15 @@ void build_plan(pbs_grouped& h, const pbs_space& sp, hipStream_t s) {
   F.t_quad = most_terms(F.c0_fq, F.c0_fu1);
   F.t_zero = most_terms(F.c0_fu1, F.n_fu);
   F.n_ft = static_cast<uint32_t>(ft_za.size());
-  upload(F.fu_t0, fu_t0);
-  upload(F.ft_za, ft_za);
-  upload(F.ft_c, ft_c);
-  upload(F.cls_f, cls_f);
+  st.upload(F.fu_t0, fu_t0);
+  st.upload(F.ft_za, ft_za);
+  st.upload(F.ft_c, ft_c);
+  st.upload(F.cls_f, cls_f);
   DevBuf<uint32_t> d_qlo, d_qzb;
   DevBuf<double> d_qc;
-  upload_temp(d_qlo, q_lo, s);
-  upload_temp(d_qzb, q_zb, s);
-  upload_temp(d_qc, q_c, s);
+  st.upload_temp(d_qlo, q_lo);
+  st.upload_temp(d_qzb, q_zb);
+  st.upload_temp(d_qc, q_c);
 
   if (n_zrows) {
     F.fz.alloc(static_cast<uint64_t>(n_zrows) * db);
@@ -432,8 +525,8 @@ void build_plan(pbs_grouped& h, const pbs_space& sp, hipStream_t s) {
   }
   if (F.c0 != 0xffffffffu) {
     DevBuf<int32_t> d_pk, d_qk;
-    upload_temp(d_pk, pk, s);
-    upload_temp(d_qk, qk, s);
+    st.upload_temp(d_pk, pk);
+    st.upload_temp(d_qk, qk);
     F.em.alloc(static_cast<uint64_t>(n_moves) * db);
     F.fp.alloc(static_cast<uint64_t>(n_moves) * F.r2 * db);
     F.eq.alloc(n_qmoves * db);
@@ -461,19 +554,20 @@ void build_plan(pbs_grouped& h, const pbs_space& sp, hipStream_t s) {
     const uint64_t da = sp.dim_alpha;
     if (plain && !simple.empty() && sp.n_orb <= 32) {
       DevBuf<uint32_t> d_simple, cnt(da, s);
-      upload_temp(d_simple, simple, s);
+      st.upload_temp(d_simple, simple);
       const unsigned grid = static_cast<unsigned>(std::min<uint64_t>(da, 65536));
       hipLaunchKernelGGL(k_alpha_list, dim3(grid), dim3(256), 0, s, 0u, da, sp.n_alpha, sp.str_alpha.get(),
                          d_simple.get(), static_cast<uint32_t>(simple.size()), h.cls_meta.get(), h.u_t0.get(),
                          h.pt_za.get(), h.pt_c.get(), nullptr, cnt.get(), nullptr, nullptr);
       PBS_HIP(hipGetLastError());
-      PBS_HIP(hipStreamSynchronize(s));
-      std::vector<uint32_t> c = download(cnt, da), off(da + 1, 0u);
+      std::vector<uint32_t> c, off(da + 1, 0u);
+      st.fetch(c, cnt, da);
+      st.wait();
       for (uint64_t i = 0; i < da; ++i) {
         off[i + 1] = off[i] + c[i];
         F.alist_max = std::max(F.alist_max, c[i]);
       }
-      upload(F.alist_off, off);
+      st.upload(F.alist_off, off);
       F.alist_src.alloc(off[da]);
       F.alist_c.alloc(off[da]);
       if (off[da]) {
@@ -488,9 +582,10 @@ void build_plan(pbs_grouped& h, const pbs_space& sp, hipStream_t s) {
     }
   }
   // image classes and their per-row images
+  std::vector<uint32_t> flag(h.n_class, 0u);
   if (F.alist && h.pair_sign && F.n_alpha == sp.n_alpha) {
-    std::vector<uint32_t> icls, flag(h.n_class, 0u);
-    const std::vector<uint4> cf = download(F.cls_f, h.n_class);
+    std::vector<uint32_t> icls;
+    const std::vector<uint4>& cf = cls_f;  // as uploaded to F.cls_f
     for (uint32_t c : ns) {
       const ClassMeta& m = meta[c];
       if (c == F.c0 || m.pm < 0 || !(m.flags & kClassPairsSingle) || m.p1 != m.g1) continue;
@@ -501,17 +596,18 @@ void build_plan(pbs_grouped& h, const pbs_space& sp, hipStream_t s) {
     const uint64_t da = sp.dim_alpha;
     if (!icls.empty()) {
       DevBuf<uint32_t> d_cls, cnt(da, s);
-      upload_temp(d_cls, icls, s);
+      st.upload_temp(d_cls, icls);
       const unsigned grid = static_cast<unsigned>(std::min<uint64_t>(da, 65536));
       hipLaunchKernelGGL(k_pair_list, dim3(grid), dim3(256), 0, s, 0u, da, sp.n_alpha, sp.str_alpha.get(), d_cls.get(),
                          static_cast<uint32_t>(icls.size()), h.cls_meta.get(), nullptr, cnt.get(), nullptr, nullptr,
                          nullptr);
       PBS_HIP(hipGetLastError());
-      PBS_HIP(hipStreamSynchronize(s));
-      std::vector<uint32_t> c = download(cnt, da), off(da + 1, 0u);
+      std::vector<uint32_t> c, off(da + 1, 0u);
+      st.fetch(c, cnt, da);
+      st.wait();
       for (uint64_t i = 0; i < da; ++i) off[i + 1] = off[i] + c[i];
       const uint64_t n_ent = off[da];
-      upload(F.plist_off, off);
+      st.upload(F.plist_off, off);
       F.plist_src.alloc(n_ent);
       F.plist_cls.alloc(n_ent);
       DevBuf<uint32_t> ent_row(n_ent, s);
@@ -528,13 +624,13 @@ void build_plan(pbs_grouped& h, const pbs_space& sp, hipStream_t s) {
                            F.fu_t0.get(), F.ft_za.get(), F.ft_c.get(), F.pimg.get());
         PBS_HIP(hipGetLastError());
       }
-      upload(F.pimg_flag, flag);
-      PBS_HIP(hipStreamSynchronize(s));
+      st.upload(F.pimg_flag, flag);
       F.plist = true;
     }
   }
   {
-    std::vector<uint32_t> flag = F.plist ? download(F.pimg_flag, h.n_class) : std::vector<uint32_t>(h.n_class, 0u);
+    // the image flags as uploaded to F.pimg_flag, none without images
+    if (!F.plist) flag.assign(h.n_class, 0u);
     for (uint32_t c : ns) {
       F.ns_uniques += meta[c].u_end - meta[c].ua;
       F.ns_groups += meta[c].g1 - meta[c].g0;
@@ -545,7 +641,7 @@ void build_plan(pbs_grouped& h, const pbs_space& sp, hipStream_t s) {
       for (uint32_t c : ns)
         if (!((k != 1 && c == F.c0) || (k != 0 && flag[c]))) l.push_back(c);
       F.ns_sizes[k] = static_cast<uint32_t>(l.size());
-      upload(F.ns_rest[k], l);
+      st.upload(F.ns_rest[k], l);
     }
   }
   PBS_HIP(hipStreamSynchronize(s));

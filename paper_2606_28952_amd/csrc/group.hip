@@ -370,9 +370,11 @@ static void build_sector_tables(pbs_grouped& g, const uint64_t* x, hipStream_t s
 
   // class schedule (host side, once per operator)
   std::vector<ClassMeta> meta(g.n_class);
-  std::vector<uint32_t> u0(g.n_pgroup + 1);
+  std::vector<uint32_t> u0(g.n_pgroup + 1), xb(g.n_pgroup), zb(g.n_unique);
   PBS_HIP(hipMemcpyAsync(meta.data(), g.cls_meta.get(), meta.size() * sizeof(ClassMeta), hipMemcpyDeviceToHost, s));
   PBS_HIP(hipMemcpyAsync(u0.data(), g.pg_u0.get(), u0.size() * 4, hipMemcpyDeviceToHost, s));
+  if (!xb.empty()) PBS_HIP(hipMemcpyAsync(xb.data(), g.pg_xb.get(), xb.size() * 4, hipMemcpyDeviceToHost, s));
+  if (!zb.empty()) PBS_HIP(hipMemcpyAsync(zb.data(), g.u_zb.get(), zb.size() * 4, hipMemcpyDeviceToHost, s));
   PBS_HIP(hipStreamSynchronize(s));
   std::vector<uint32_t> runs, ns;
   int64_t qcnt = -1;
@@ -396,11 +398,8 @@ static void build_sector_tables(pbs_grouped& g, const uint64_t* x, hipStream_t s
     }
   }
   // beta Z-masks of the single-unique pair groups, per orbital pair
+  std::vector<uint32_t> zp(g.n_pairs + 1, 0u);
   {
-    std::vector<uint32_t> xb(g.n_pgroup), zb(g.n_unique);
-    PBS_HIP(hipMemcpy(xb.data(), g.pg_xb.get(), xb.size() * 4, hipMemcpyDeviceToHost));
-    PBS_HIP(hipMemcpy(zb.data(), g.u_zb.get(), zb.size() * 4, hipMemcpyDeviceToHost));
-    std::vector<uint32_t> zp(g.n_pairs + 1, 0u);
     std::vector<char> seen(g.n_pairs + 1, 0);
     bool uniform = true;
     for (uint32_t c = 0; c < g.n_class && uniform; ++c) {
@@ -422,16 +421,17 @@ static void build_sector_tables(pbs_grouped& g, const uint64_t* x, hipStream_t s
       }
     }
     g.pair_sign = uniform && g.n_pairs > 0;
-    g.zpair.alloc(zp.size());
-    PBS_HIP(hipMemcpy(g.zpair.get(), zp.data(), zp.size() * 4, hipMemcpyHostToDevice));
   }
   g.n_runs = static_cast<uint32_t>(runs.size() / 2);
   g.n_ns = static_cast<uint32_t>(ns.size());
   g.quad_cnt = qcnt > 0 ? static_cast<uint32_t>(qcnt) : 0u;
+  g.zpair.alloc(zp.size());
   g.runs.alloc(runs.size());
   g.ns_list.alloc(ns.size());
-  if (!runs.empty()) PBS_HIP(hipMemcpy(g.runs.get(), runs.data(), runs.size() * 4, hipMemcpyHostToDevice));
-  if (!ns.empty()) PBS_HIP(hipMemcpy(g.ns_list.get(), ns.data(), ns.size() * 4, hipMemcpyHostToDevice));
+  PBS_HIP(hipMemcpyAsync(g.zpair.get(), zp.data(), zp.size() * 4, hipMemcpyHostToDevice, s));
+  if (!runs.empty()) PBS_HIP(hipMemcpyAsync(g.runs.get(), runs.data(), runs.size() * 4, hipMemcpyHostToDevice, s));
+  if (!ns.empty()) PBS_HIP(hipMemcpyAsync(g.ns_list.get(), ns.data(), ns.size() * 4, hipMemcpyHostToDevice, s));
+  PBS_HIP(hipStreamSynchronize(s));  // the host vectors end here
 }
 
 }  // namespace pbs
