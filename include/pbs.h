@@ -252,9 +252,11 @@ pbs_status pbs_apply_pauli_sum_rows(const pbs_grouped* h, const pbs_space* sp, p
  * (Re, Im of sum over the share's targets t of conj(psi_t) (H psi)_t, and sum
  * of |psi_t|^2 over them), so that the shares' results add up to
  * pbs_expval's (up to the order of the float64 sums).  out is NULL or a
- * share as in pbs_apply_pauli_sum_rows; work as in pbs_expval (the whole
- * space's pbs_expval_workspace_bytes is always enough).  Same errors as
- * pbs_apply_pauli_sum_rows.  Asynchronous; allocates nothing. */
+ * share as in pbs_apply_pauli_sum_rows; work: device workspace of at least
+ * (row_end - row_begin) * ceil(dim_beta / 512) * 24 bytes (the whole space's
+ * pbs_expval_workspace_bytes is always enough; PBS_ERR_ARG when smaller).
+ * Same errors as pbs_apply_pauli_sum_rows.  Asynchronous; allocates
+ * nothing. */
 pbs_status pbs_expval_rows(const pbs_grouped* h, const pbs_space* sp, pbs_dtype dt, const void* psi, void* out,
                            uint64_t row_begin, uint64_t row_end, double* result, void* work, uint64_t work_bytes,
                            void* stream);

@@ -331,9 +331,11 @@ def apply_pauli_sum_rows(grouped, space, psi, row_begin, row_end, out=None):
 def expval_rows(grouped, space, psi, row_begin, row_end, work=None, result=None, out=None):
     """The share of alpha rows [row_begin, row_end) in expval's three sums;
     with ``out`` the same pass stores those rows of H psi."""
-    code, _ = _check_rows(space, psi, out, row_begin, row_end)
-    if work is None:
-        work = torch.empty(max(1, space.workspace_bytes() // 8), dtype=torch.float64, device=psi.device)
+    code, n = _check_rows(space, psi, out, row_begin, row_end)
+    if work is None:  # the share's partials: one per (row, 512-column chunk)
+        dim_beta = space.shape()[4]
+        rows = n // dim_beta if dim_beta else 0
+        work = torch.empty(max(1, rows * ((dim_beta + 511) // 512) * 3), dtype=torch.float64, device=psi.device)
     if result is None:
         result = torch.empty(3, dtype=torch.float64, device=psi.device)
     call("pbs_expval_rows", grouped._h, space._h, code, _ptr(psi), _ptr(out), int(row_begin), int(row_end),

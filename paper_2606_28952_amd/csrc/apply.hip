@@ -468,7 +468,8 @@ pbs_status pbs_expval_rows(const pbs_grouped* h, const pbs_space* sp, pbs_dtype 
     validate(h, sp, dt);
     PBS_REQUIRE(result != nullptr && work != nullptr, PBS_ERR_ARG, "null pointer");
     check_rows(sp, dt, psi, out, row_begin, row_end);
-    const uint64_t need = partial_count(*sp) * 3 * sizeof(double);
+    // at most one partial per (row, column chunk) of the share
+    const uint64_t need = (row_end - row_begin) * ((sp->dim_beta + kSB - 1) / kSB) * 3 * sizeof(double);
     PBS_REQUIRE(work_bytes >= need, PBS_ERR_ARG,
                 "workspace of " + std::to_string(work_bytes) + " bytes, need " + std::to_string(need));
     hipStream_t s = as_stream(stream);

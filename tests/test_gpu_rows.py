@@ -49,8 +49,12 @@ def _check_shares(api, G, sp, psi, whole, e_whole):
         out = torch.empty_like(part)
         e = api.expval_rows(G, sp, psi, a0, a1, out=out).cpu().numpy()
         assert torch.equal(torch.view_as_real(out), torch.view_as_real(part))
-        # the energy alone (no stored product) gives the same bits
+        # the energy alone (no stored product) gives the same bits, also with
+        # a workspace sized for the share only
         assert np.array_equal(api.expval_rows(G, sp, psi, a0, a1).cpu().numpy(), e)
+        chunks = (dim_beta + 511) // 512
+        small = torch.empty(max(1, (a1 - a0) * chunks * 3), dtype=torch.float64, device=psi.device)
+        assert np.array_equal(api.expval_rows(G, sp, psi, a0, a1, work=small).cpu().numpy(), e)
         e_sum += e
     got = torch.cat(parts)
     assert torch.equal(torch.view_as_real(got), torch.view_as_real(whole))
@@ -111,6 +115,8 @@ def test_row_range_refusals(dev):
         api.apply_pauli_sum_rows(G, sp, psi, 4, 3)
     with pytest.raises(PbsError, match="overlaps"):
         api.apply_pauli_sum_rows(G, sp, psi, 0, 2, out=psi[6:18])
+    with pytest.raises(PbsError, match="workspace"):  # 3 rows x 1 chunk x 3 doubles needed
+        api.expval_rows(G, sp, psi, 1, 4, work=torch.empty(8, dtype=torch.float64, device=dev))
     full = api.Space.full(8)
     psi_f = torch.from_numpy(synth.random_state(full.dim, 9)).to(dev)
     with pytest.raises(PbsError, match="sector"):
