@@ -388,8 +388,9 @@ pbs_status pbs_krylov_workspace_bytes(const pbs_space* sp, pbs_dtype dt, uint32_
 
 /* One real-time step psi <- exp(-i H dt_step) psi (Section 2.1,
  * Eq. real_time_evolution) by short-iterative Lanczos: up to m Krylov vectors
- * built with pbs_apply_pauli_sum's kernels, two classical Gram-Schmidt passes
- * per vector with float64 inner products, exp(-i T dt) e_1 of the tridiagonal
+ * built with pbs_apply_pauli_sum's kernels, the three-term recurrence and
+ * one full classical Gram-Schmidt re-orthogonalisation per vector with
+ * float64 inner products, exp(-i T dt) e_1 of the tridiagonal
  * T from its eigen-decomposition, psi rebuilt as |psi| V exp(-i T dt) e_1.
  * The basis stops early when the new vector's norm falls below 1e-14 times
  * the largest entry of T (the Krylov space is then invariant and the step is

@@ -4,9 +4,11 @@
 // this is the textbook method of Park and Light, 1986).
 //
 // Device work per Lanczos vector: one operator-state product (the sector or
-// full-space apply), two passes of classical Gram-Schmidt against all
-// previous vectors (a multi-dot, then two multi-axpy sweeps that also return
-// the next pass's projections and the norm), and a scale.  Inner products accumulate in float64 with a fixed-order two-stage
+// full-space apply), the three-term recurrence (alpha_j from one dot with the
+// newest vector) followed by one full pass of classical Gram-Schmidt against
+// all basis vectors (two multi-axpy sweeps: the first subtracts the
+// recurrence terms and returns the projections, the second subtracts those
+// and returns the norm), and a scale.  Inner products accumulate in float64 with a fixed-order two-stage
 // reduction (deterministic).  The k x k tridiagonal matrix (k <= 16) is
 // diagonalised on the host by cyclic Jacobi rotations and exp(-i T dt) e_1
 // combines the basis vectors on the device.
@@ -338,16 +340,16 @@ class Lanczos {
     uint32_t k = 0;
     for (uint32_t j = 0; j < m_; ++j) {
       apply_launch(h_, sp_, dt_, vec(j), W_, s_);
-      // first Gram-Schmidt pass: its projection on v_j is alpha_j
-      dots(vec(0), static_cast<int>(j + 1), W_, d);
-      alpha.push_back(d[2 * j]);
-      double nre[kMaxK], nim[kMaxK];
-      for (uint32_t i = 0; i <= j; ++i) {
-        nre[i] = -d[2 * i];
-        nim[i] = -d[2 * i + 1];
-      }
-      // subtract them, and in the same sweep the second pass's projections
-      // (re-orthogonalisation)
+      // the three-term recurrence: alpha_j = <v_j, w> on the fresh product
+      // (H is Hermitian, so w has no other component in exact arithmetic)
+      dots(vec(j), 1, W_, d);
+      alpha.push_back(d[0]);
+      double nre[kMaxK] = {}, nim[kMaxK] = {};
+      nre[j] = -d[0];
+      nim[j] = -d[1];
+      if (j > 0) nre[j - 1] = -beta[j - 1];
+      // subtract alpha_j v_j + beta_{j-1} v_{j-1}, and in the same sweep the
+      // projections on every basis vector (full re-orthogonalisation)
       axpy_dots(vec(0), static_cast<int>(j + 1), nre, nim, W_, false, d);
       for (uint32_t i = 0; i <= j; ++i) {
         nre[i] = -d[2 * i];
