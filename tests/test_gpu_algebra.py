@@ -90,6 +90,27 @@ def test_canonicalize_bit_exact(dev, n, m, pool, spread, eps):
     assert s.info()[2]
 
 
+@pytest.mark.parametrize("m", [2047, 2048, 2049, 32768, 32769, 524288, 524289])
+def test_canonicalize_at_scan_tile_boundaries(dev, m):
+    """Contribution counts at the prefix sums' tile boundaries (2,048 items
+    per tile; one single-block launch up to 16 tiles, three launches above):
+    the head and survivor scans of the canonical reduction switch between
+    the two forms at 32,768 items, and the radix sort's digit-count scan
+    (256 counts per 4,096-key tile) at 524,288 keys; the result must stay
+    bit-exact on both sides."""
+    api = _api()
+    x, z, _ = synth.random_symplectic(m, 40, seed=m, pool=max(1, m // 2))
+    rng = np.random.default_rng(m + 1)
+    c = (rng.standard_normal(m) + 1j * rng.standard_normal(m)).astype(np.complex128)
+    s = api.PauliSum.create(40, x.reshape(-1), z.reshape(-1), c)
+    s.canonicalize(0.0)
+    gx, gz, gc = s.read()
+    rx, rz, rc = opauli.canonicalize_xz(x, z, c.real, c.imag, 0.0)
+    np.testing.assert_array_equal(gx, rx)
+    np.testing.assert_array_equal(gz, rz)
+    assert gc.tobytes() == rc.tobytes()
+
+
 def _adversarial_segments():
     """Coefficient lists whose correctly rounded sums are decided by ties,
     tiny tails, cancellation or subnormals (one list per distinct string)."""
